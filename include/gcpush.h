@@ -1,0 +1,253 @@
+/*
+ * gcpush.h -- C ABI of the MI355X (gfx950) guiding-centre electron pusher.
+ *
+ * The library advances relativistic guiding-centre (GC) electrons through a
+ * steady gridded spherical field, following Houeibib, Pantellini & Griton,
+ * "Dynamics of energetic electrons scattered in the solar wind" (A&A 2025,
+ * arXiv 2403.06706):
+ *   - GC equations of motion, Eqs. (1)-(3) of Sect. 2.2, with X = (R, gamma v_par);
+ *   - field at the particle by trilinear interpolation of the grid (Sect. 2.2);
+ *   - third-order predictor-corrector, Eqs. (5)-(6), started by a backward
+ *     Euler step at injection and after each collision (Sect. 2.2);
+ *   - hard-sphere scattering along the field line, Eqs. (9)-(10) (and (12))
+ *     of Sect. 2.3, in the inertial frame (Sect. 3).
+ *
+ * Conventions (all entry points):
+ *   - Every call returns a gc_status and never throws.  Argument errors are
+ *     detected on the host before any device work and described by
+ *     gc_last_error().  A failed HIP call or launch returns GC_EDEVICE.
+ *   - Device work is queued on the context's HIP stream and returns without
+ *     waiting, unless stated otherwise.
+ *   - Units are SI.  Field vectors are in the local orthonormal spherical
+ *     basis (r^, th^, ph^), right-handed.
+ *   - The library owns the particle state and the packed field (device memory
+ *     it allocates with hipMalloc).  Buffers passed in are owned by the caller.
+ *   - Per-particle faults (leaving the shell, non-finite values) are particle
+ *     status values, not errors.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef GCPUSH_H
+#define GCPUSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gc_ctx gc_ctx;
+
+typedef enum {
+    GC_OK = 0,
+    GC_EINVAL = -1,   /* invalid argument (nothing was queued) */
+    GC_ENOMEM = -2,   /* device allocation failed */
+    GC_EDEVICE = -3,  /* HIP runtime or kernel launch error */
+    GC_ESTATE = -4    /* call out of order (e.g. gc_advance before gc_load_field) */
+} gc_status;
+
+typedef enum { GC_F64 = 0, GC_F32 = 1, GC_F16 = 2 } gc_dtype;
+
+/* Arithmetic of the push (the paper fixes none):
+ *   GC_PREC_F64        everything in FP64;
+ *   GC_PREC_F32_ACC64  field interpolation and right-hand side in FP32, position,
+ *                      u and time accumulated in FP64;
+ *   GC_PREC_F32_KAHAN  everything in FP32, position, u and time accumulated with
+ *                      Kahan compensation (compensation terms kept in the state). */
+typedef enum { GC_PREC_F64 = 0, GC_PREC_F32_ACC64 = 1, GC_PREC_F32_KAHAN = 2 } gc_precision;
+
+/* particle status */
+enum { GC_ACTIVE = 0, GC_EXITED = 1, GC_FINISHED = 2, GC_NONFINITE = 3 };
+/* particle flags */
+enum { GC_FLAG_BOOTSTRAP = 1u, GC_FLAG_PENDING = 2u };
+
+/* Particle reordering before each chunk of steps. */
+enum {
+    GC_ORDER_NONE = 0,     /* never reorder; every slot is visited by every launch */
+    GC_ORDER_COMPACT = 1,  /* stable partition: active particles first (wavefront ballots) */
+    GC_ORDER_BIN = 2       /* radix sort by field cell, inactive particles last */
+};
+
+typedef struct {
+    void *hip_stream;       /* hipStream_t for all device work; NULL: the null stream */
+    int32_t device;         /* HIP device ordinal */
+    int32_t precision;      /* gc_precision */
+    int32_t order;          /* GC_ORDER_* */
+    int32_t chunk_steps;    /* steps per push launch (and per reorder); > 0 */
+    int32_t bin_coarsen;    /* cells per bin along each axis = 2^bin_coarsen (GC_ORDER_BIN) */
+    int32_t block_size;     /* push workgroup size: 64, 128, 256, 512 or 1024 */
+    int32_t persistent;     /* 1: persistent push with a tile work queue */
+    int32_t tile;           /* particles per work-queue tile (persistent mode, multiple of block_size) */
+    int32_t log_depth;      /* per particle, record the step of the first log_depth collisions (0: off) */
+    int32_t timing;         /* 1: record HIP events around each push launch (see gc_timing) */
+} gc_options;
+
+/* Fill *opt with the defaults (FP64, binning every 64 steps, 256 threads). */
+void gc_default_options(gc_options *opt);
+
+/* Create a context on opt->device.  out receives the handle. */
+gc_status gc_create(gc_ctx **out, const gc_options *opt);
+void gc_destroy(gc_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *gc_last_error(const gc_ctx *ctx);
+/* Change options between calls (precision, order, chunk, block, persistence, tile, timing).
+ * log_depth and device cannot change after creation. */
+gc_status gc_set_options(gc_ctx *ctx, const gc_options *opt);
+gc_status gc_get_options(const gc_ctx *ctx, gc_options *opt);
+
+/* ---------------------------------------------------------------- field */
+/* Grid geometry (a uniform stand-in for the paper's MHD grid, Sect. 2.1):
+ *   r_i  = r_min + i (r_max - r_min)/(nr - 1)   i = 0..nr-1
+ *   th_j = (j + 1/2) pi / nth                   j = 0..nth-1
+ *   ph_k = 2 pi k / nph  (periodic)             k = 0..nph-1
+ * data: HOST pointer to [nr][nth][nph][12] values of type src_dtype, components
+ *   B_r B_th B_ph | E_r E_th E_ph | (grad|B|)_r,th,ph | ((b.grad)b)_r,th,ph.
+ * The library copies and repacks the data in store_dtype (GC_F16 stores each
+ * component divided by a per-component power-of-two scale); the caller's buffer
+ * may be freed when the call returns.  The call waits for the upload.
+ * Errors: GC_EINVAL if nr < 2, nth < 2, nph < 2, r_min <= 0, r_max <= r_min,
+ * data == NULL or a dtype is unknown.  Loading a new field keeps the particles. */
+typedef struct {
+    int32_t nr, nth, nph;
+    int32_t src_dtype;      /* GC_F64 or GC_F32 */
+    double r_min, r_max;    /* m */
+    const void *data;       /* host */
+    int32_t store_dtype;    /* GC_F64, GC_F32 or GC_F16 */
+    int32_t pad;
+} gc_field_desc;
+
+gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *desc);
+
+/* ------------------------------------------------------------ injection */
+/* Append desc->n particles of one ensemble (Sect. 3: mono-energetic electrons
+ * released at one site).  Particle j of the call gets id first_id + j within
+ * the ensemble and the next global index.  Its draws come from Philox4x64-10
+ * with key (seed, ensemble) and counter (id, 0, 1, 0):
+ *   ph  = lon0 + dlon (2 a0 - 1),  pitch cosine mu = mu_lo + (mu_hi - mu_lo) a1,
+ *   r   = r0 + dr0 (2 a2 - 1),     th = pi/2 - (lat0 + dlat (2 a3 - 1)),
+ * and its first free path from counter (id, 0, 0, 0): ell_0 = -lambda ln(1 - a0).
+ * u = gamma v mu from ekin; mu_B/m = (p/m)^2 (1 - mu^2) / (2 |B(R0)|).
+ * A particle placed outside [r_in, r_out] x [th_0, th_{nth-1}] is EXITED.
+ * Ensemble parameters (q, m, lambda_par, r_in, r_out, max_steps, drift_free,
+ * scatter_law, seed) are stored per ensemble index; injecting again into an
+ * existing ensemble index replaces them.  lambda_par <= 0 disables scattering;
+ * max_steps > 0 makes a particle FINISHED after that many steps; drift_free = 1
+ * keeps only v_par b in dR/dt (Sect. 3.2); scatter_law 0: mu' = 1 - 2a (Eq. 10),
+ * 1: mu' = +-sqrt(a) (Eq. 12).
+ * Errors: GC_ESTATE before gc_load_field; GC_EINVAL for ensemble >= 4096,
+ * m <= 0, q == 0, ekin <= 0, r_in >= r_out, mu_lo/mu_hi outside [-1, 1].
+ * n == 0 is a no-op. */
+typedef struct {
+    uint32_t ensemble;
+    uint32_t first_id;
+    uint64_t n;
+    uint64_t seed;
+    double q, m;            /* C, kg */
+    double ekin;            /* J */
+    double r0, lat0, lon0;  /* m, rad, rad */
+    double dlon, dr0, dlat; /* half-widths */
+    double mu_lo, mu_hi;
+    double lambda_par;      /* m */
+    double r_in, r_out;     /* m */
+    int64_t max_steps;
+    int32_t drift_free;
+    int32_t scatter_law;
+} gc_inject_desc;
+
+gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *desc);
+
+/* ------------------------------------------------------------- advance */
+/* Advance every active particle by n_steps steps of size dt (s), or until it
+ * exits, finishes or meets a non-finite value.  Per step (Eqs. 5-6 and 9-10):
+ * gather at X^n; apply a pending collision; F^n; bootstrap F^{n-1} if flagged;
+ * predictor X*; gather and F*; corrector X^{n+1}; path += (|v_par^n| + |v_par*|) dt / 2,
+ * collision pending once the path reaches the free path; exit/finish tests.
+ * tau = dt / (previous dt) on the first step after a change of dt.
+ * The work is split in launches of chunk_steps steps, each preceded by the
+ * configured reordering.  Errors: GC_ESTATE without field; GC_EINVAL if dt is
+ * not finite and > 0 or n_steps < 0. */
+gc_status gc_advance(gc_ctx *ctx, double dt, int64_t n_steps);
+
+/* Same work as gc_advance, captured once per (dt, n_steps, options) into a
+ * hipGraph and replayed on later calls with identical arguments. */
+gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps);
+
+/* -------------------------------------------------------------- moments */
+/* Snapshot statistics (Sect. 3: <sin^2 alpha>(r), energy versus age near
+ * 1 AU, pitch-cosine distributions).  out: caller-owned DEVICE buffer of
+ * gc_moments_size(spec) int64 values, overwritten:
+ *   [0..3] particles per status, [4] sum of collision counts, [5] sum of steps,
+ *   [6] sum over active particles of floor(r/len_unit * 2^32),
+ *   [7] active particles with at least one collision,
+ *   then n_rbins x {count, sum floor(sin^2 alpha * 2^32), sum floor(E/e_unit * 2^16)}
+ *     for active particles with r in [r_lo, r_hi),
+ *   then n_mubins counts of mu = cos(alpha) on [-1, 1] for active particles with
+ *     r in [sel_r_lo, sel_r_hi), age in [age_lo, age_hi), k >= min_collisions,
+ *   then n_agebins x n_ebins counts of (age on [0, age_max), E on [e_lo, e_hi))
+ *     for active particles with r in [sel_r_lo, sel_r_hi).
+ * alpha is the pitch angle, E = (gamma - 1) m c^2 with |B| interpolated at the
+ * particle, age = time since injection.  Integer sums: the result does not
+ * depend on the particle order.  Errors: GC_EINVAL for out == NULL, negative
+ * bin counts, empty ranges, or more than 8192 outputs. */
+typedef struct {
+    int32_t n_rbins;   double r_lo, r_hi;
+    int32_t n_mubins;
+    double sel_r_lo, sel_r_hi;
+    double age_lo, age_hi;
+    int32_t min_collisions;
+    int32_t n_agebins; double age_max;
+    int32_t n_ebins;   double e_lo, e_hi;
+    double e_unit;     /* J per energy unit */
+    double len_unit;   /* m per length unit */
+} gc_moment_spec;
+
+int64_t gc_moments_size(const gc_moment_spec *spec);
+gc_status gc_moments(gc_ctx *ctx, const gc_moment_spec *spec, int64_t *out);
+
+/* --------------------------------------------------- state checkpointing */
+/* Per-particle state in global injection order (index g = order of injection).
+ * Every pointer is a caller-owned DEVICE array of n entries; NULL members are
+ * skipped.  mu is mu_B / m (m^2 s^-2 T^-1).  (cr, cth, cph, cu, ct) are the
+ * Kahan compensation terms of the FP32 form (zero otherwise). */
+typedef struct {
+    double *r, *th, *ph, *u, *mu;
+    double *fr, *fth, *fph, *fu;       /* F^{n-1} */
+    double *dtp, *s, *ell, *t;
+    double *cr, *cth, *cph, *cu, *ct;
+    uint32_t *k, *flags, *status, *step, *id, *ens;
+} gc_state_view;
+
+/* Number of particles injected so far. */
+gc_status gc_count(const gc_ctx *ctx, uint64_t *n);
+/* Copy the state out (async). */
+gc_status gc_get_state(gc_ctx *ctx, const gc_state_view *dst);
+/* Replace the whole state by n particles read from src (async); every member
+ * must be non-NULL.  ens values must name ensembles already injected. */
+gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n);
+/* Copy the collision log out (async): dst is a DEVICE array of n x log_depth
+ * uint32, entry [g][k] = step count at which collision k+1 of particle g was
+ * applied, 0xFFFFFFFF if none.  GC_ESTATE if log_depth is 0. */
+gc_status gc_get_log(gc_ctx *ctx, uint32_t *dst);
+
+/* ----------------------------------------------------------- counters */
+/* Waits for the stream.  push_ms: summed duration of push launches recorded
+ * with timing = 1; n_push: their number; particle_steps: steps taken by active
+ * particles since the context was created or counters were reset. */
+typedef struct {
+    double push_ms;
+    int64_t n_push;
+    double reorder_ms;
+    int64_t n_reorder;
+    uint64_t particle_steps;
+} gc_counters;
+gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out);
+gc_status gc_reset_counters(gc_ctx *ctx);
+
+/* Copy n_bytes from src to dst (both device) with a plain streaming kernel;
+ * used to calibrate hardware traffic counters against a known byte count. */
+gc_status gc_copy_probe(gc_ctx *ctx, void *dst, const void *src, uint64_t n_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCPUSH_H */

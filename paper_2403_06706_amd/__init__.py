@@ -1,0 +1,202 @@
+"""MI355X guiding-centre electron pusher: Python binding of libgcpush.so.
+
+Argument marshalling only.  Every step of the method runs in the HIP kernels
+behind the C ABI (include/gcpush.h); torch supplies device buffers for
+outputs and the HIP stream.  Importing this package needs the built library
+(it raises ImportError otherwise); using a context needs a GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import (GC_F64, GC_F32, GC_F16, GC_PREC_F64, GC_PREC_F32_ACC64, GC_PREC_F32_KAHAN,  # noqa: F401
+                   GC_ACTIVE, GC_EXITED, GC_FINISHED, GC_NONFINITE, GC_FLAG_BOOTSTRAP, GC_FLAG_PENDING,
+                   GC_ORDER_NONE, GC_ORDER_COMPACT, GC_ORDER_BIN, STATE_DOUBLES, STATE_U32)
+
+lib = _abi.load()
+
+_DTYPES = {"f64": GC_F64, "f32": GC_F32, "f16": GC_F16}
+_PRECS = {"f64": GC_PREC_F64, "f32_acc64": GC_PREC_F32_ACC64, "f32_kahan": GC_PREC_F32_KAHAN}
+_ORDERS = {"none": GC_ORDER_NONE, "compact": GC_ORDER_COMPACT, "bin": GC_ORDER_BIN}
+
+
+class GCError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"gc status {status}: {message}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """One gc_ctx on one device, using torch's current stream unless one is given."""
+
+    def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
+                 bin_coarsen: int = 0, block_size: int = 256, persistent: bool = False, tile: int = 1024,
+                 log_depth: int = 0, timing: bool = False, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the guiding-centre pusher runs only on the device")
+        self.device = device
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        o = _abi.gc_options()
+        lib.gc_default_options(C.byref(o))
+        o.hip_stream = self._stream.cuda_stream
+        o.device = device
+        o.precision = _PRECS[precision]
+        o.order = _ORDERS[order]
+        o.chunk_steps = chunk_steps
+        o.bin_coarsen = bin_coarsen
+        o.block_size = block_size
+        o.persistent = int(persistent)
+        o.tile = tile
+        o.log_depth = log_depth
+        o.timing = int(timing)
+        self._opt = o
+        h = C.c_void_p()
+        st = lib.gc_create(C.byref(h), C.byref(o))
+        self._h = h
+        if st != 0:
+            msg = lib.gc_last_error(h).decode() if h else ""
+            if h:
+                lib.gc_destroy(h)
+            self._h = None
+            raise GCError(st, msg)
+        self.log_depth = log_depth
+
+    # -------------------------------------------------------------- basics
+    def _check(self, st: int):
+        if st != 0:
+            raise GCError(st, lib.gc_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def set_options(self, **kw):
+        o = _abi.gc_options()
+        self._check(lib.gc_get_options(self._h, C.byref(o)))
+        for k, v in kw.items():
+            if k == "precision":
+                v = _PRECS[v]
+            elif k == "order":
+                v = _ORDERS[v]
+            elif k == "stream":
+                self._stream = v
+                k, v = "hip_stream", v.cuda_stream
+            setattr(o, k, int(v) if not isinstance(v, int) and k != "hip_stream" else v)
+        self._check(lib.gc_set_options(self._h, C.byref(o)))
+
+    def count(self) -> int:
+        n = C.c_uint64()
+        self._check(lib.gc_count(self._h, C.byref(n)))
+        return n.value
+
+    # --------------------------------------------------------------- field
+    def load_field(self, grid, data: np.ndarray, store_dtype: str = "f64"):
+        arr = np.ascontiguousarray(data)
+        if arr.dtype not in (np.float64, np.float32):
+            raise TypeError("field data must be float64 or float32")
+        d = _abi.gc_field_desc(grid.nr, grid.nth, grid.nph, GC_F64 if arr.dtype == np.float64 else GC_F32,
+                               grid.r_min, grid.r_max, arr.ctypes.data, _DTYPES[store_dtype], 0)
+        self._check(lib.gc_load_field(self._h, C.byref(d)))
+
+    # ----------------------------------------------------------- injection
+    def inject(self, ens, first_id: int = 0, n: Optional[int] = None):
+        """ens: object with the attributes of synthetic.workloads.Ensemble."""
+        d = _abi.gc_inject_desc(ens.ensemble, first_id, ens.n if n is None else n, ens.seed, ens.q, ens.m, ens.ekin,
+                                ens.r0, ens.lat0, ens.lon0, ens.dlon, ens.dr0, ens.dlat, ens.mu_lo, ens.mu_hi,
+                                ens.lambda_par, ens.r_in, ens.r_out, int(ens.max_steps), int(ens.drift_free),
+                                int(ens.scatter_law))
+        self._check(lib.gc_inject(self._h, C.byref(d)))
+
+    # ------------------------------------------------------------- advance
+    def advance(self, dt: float, n_steps: int):
+        self._check(lib.gc_advance(self._h, float(dt), int(n_steps)))
+
+    def advance_graph(self, dt: float, n_steps: int):
+        self._check(lib.gc_advance_graph(self._h, float(dt), int(n_steps)))
+
+    # ------------------------------------------------------------- moments
+    @staticmethod
+    def _spec(spec) -> _abi.gc_moment_spec:
+        return _abi.gc_moment_spec(spec.n_rbins, spec.r_lo, spec.r_hi, spec.n_mubins, spec.sel_r_lo, spec.sel_r_hi,
+                                   spec.age_lo, spec.age_hi, spec.min_collisions, spec.n_agebins, spec.age_max,
+                                   spec.n_ebins, spec.e_lo, spec.e_hi, spec.e_unit, spec.len_unit)
+
+    def moments(self, spec):
+        torch = _torch()
+        s = self._spec(spec)
+        m = lib.gc_moments_size(C.byref(s))
+        out = torch.empty(max(int(m), 1), dtype=torch.int64, device=f"cuda:{self.device}")
+        self._check(lib.gc_moments(self._h, C.byref(s), C.c_void_p(out.data_ptr())))
+        return out[:m]
+
+    # --------------------------------------------------------------- state
+    def get_state(self) -> Dict[str, "object"]:
+        torch = _torch()
+        n = self.count()
+        dev = f"cuda:{self.device}"
+        out = {k: torch.empty(max(n, 1), dtype=torch.float64, device=dev) for k in STATE_DOUBLES}
+        out.update({k: torch.empty(max(n, 1), dtype=torch.int32, device=dev) for k in STATE_U32})
+        v = _abi.gc_state_view(**{k: t.data_ptr() for k, t in out.items()})
+        self._check(lib.gc_get_state(self._h, C.byref(v)))
+        return {k: t[:n] for k, t in out.items()}
+
+    def set_state(self, state: Dict[str, "object"]):
+        torch = _torch()
+        n = int(state["r"].shape[0])
+        keep = {}
+        for k in STATE_DOUBLES:
+            keep[k] = state[k].to(device=f"cuda:{self.device}", dtype=torch.float64).contiguous()
+        for k in STATE_U32:
+            keep[k] = state[k].to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
+        v = _abi.gc_state_view(**{k: t.data_ptr() for k, t in keep.items()})
+        self._check(lib.gc_set_state(self._h, C.byref(v), n))
+        self._stream.synchronize()   # the buffers above may be freed on return
+
+    def get_log(self):
+        torch = _torch()
+        n = self.count()
+        out = torch.empty((max(n, 1), max(self.log_depth, 1)), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib.gc_get_log(self._h, C.c_void_p(out.data_ptr())))
+        return out[:n]
+
+    # ------------------------------------------------------------ counters
+    def counters(self) -> dict:
+        c = _abi.gc_counters()
+        self._check(lib.gc_get_counters(self._h, C.byref(c)))
+        return {"push_ms": c.push_ms, "n_push": c.n_push, "reorder_ms": c.reorder_ms, "n_reorder": c.n_reorder,
+                "particle_steps": c.particle_steps}
+
+    def reset_counters(self):
+        self._check(lib.gc_reset_counters(self._h))
+
+    def copy_probe(self, dst, src, n_bytes: int):
+        self._check(lib.gc_copy_probe(self._h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(n_bytes)))
+
+
+def state_to_numpy(state: Dict[str, "object"]) -> Dict[str, np.ndarray]:
+    out = {}
+    for k, t in state.items():
+        a = t.cpu().numpy()
+        out[k] = a.view(np.uint32) if a.dtype == np.int32 else a
+    return out

@@ -1,0 +1,668 @@
+// gc_api.cpp -- host implementation of the C ABI declared in gcpush.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gc_internal.h"
+#include "gc_launch.h"
+#include "gcpush.h"
+
+using namespace gc;
+
+struct GraphKey {
+    double dt = 0;
+    int64_t n_steps = -1;
+    uint64_t n = 0;
+    gc_options opt{};
+};
+
+struct gc_ctx {
+    gc_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    int n_cus = 256;
+    // field
+    bool have_field = false;
+    void *field_buf = nullptr;
+    FieldDev f{};
+    // ensembles
+    std::vector<EnsDev> ens_host;
+    std::vector<char> ens_set;
+    EnsDev *ens_dev = nullptr;
+    // particles (A is current, B is the permutation target)
+    uint64_t n = 0, cap = 0;
+    void *soa_mem[2] = {nullptr, nullptr};
+    SoA A{}, B{};
+    OrderScratch sc{};
+    void *scratch_mem = nullptr;
+    uint32_t *n_active = nullptr;
+    uint32_t *queue = nullptr;
+    unsigned long long *steps = nullptr;
+    uint32_t *log = nullptr;
+    // timing
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_push, ev_reorder;
+    std::vector<hipEvent_t> ev_pool;   // recorded and read events, ready for reuse
+    // graph
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey{};
+};
+
+namespace {
+
+gc_status fail(gc_ctx *c, gc_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) return fail(ctx, GC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }
+
+gc_status check_options(gc_ctx *ctx, const gc_options *o) {
+    if (o->precision < GC_PREC_F64 || o->precision > GC_PREC_F32_KAHAN)
+        return fail(ctx, GC_EINVAL, "unknown precision %d", o->precision);
+    if (o->order < GC_ORDER_NONE || o->order > GC_ORDER_BIN) return fail(ctx, GC_EINVAL, "unknown order %d", o->order);
+    if (o->chunk_steps <= 0) return fail(ctx, GC_EINVAL, "chunk_steps must be > 0");
+    if (o->bin_coarsen < 0 || o->bin_coarsen > 6) return fail(ctx, GC_EINVAL, "bin_coarsen must be in [0, 6]");
+    if (!valid_block(o->block_size)) return fail(ctx, GC_EINVAL, "block_size must be 64, 128 or 256");
+    if (o->persistent && (o->tile <= 0 || o->tile % o->block_size != 0))
+        return fail(ctx, GC_EINVAL, "tile must be a positive multiple of block_size");
+    if (o->log_depth < 0 || o->log_depth > 4096) return fail(ctx, GC_EINVAL, "log_depth must be in [0, 4096]");
+    return GC_OK;
+}
+
+// carve one allocation into the SoA arrays
+void carve(void *mem, uint64_t cap, SoA &s) {
+    double *d = static_cast<double *>(mem);
+    double **dp[kNumDoubleArrays] = {&s.r, &s.th, &s.ph, &s.u, &s.mu, &s.fr, &s.fth, &s.fph, &s.fu,
+                                     &s.dtp, &s.s, &s.ell, &s.t, &s.cr, &s.cth, &s.cph, &s.cu, &s.ct};
+    for (int i = 0; i < kNumDoubleArrays; ++i) *dp[i] = d + (size_t)i * cap;
+    uint32_t *u = reinterpret_cast<uint32_t *>(d + (size_t)kNumDoubleArrays * cap);
+    uint32_t **up[kNumU32Arrays] = {&s.k, &s.flags, &s.status, &s.step, &s.id, &s.ens, &s.gid};
+    for (int i = 0; i < kNumU32Arrays; ++i) *up[i] = u + (size_t)i * cap;
+}
+
+size_t soa_bytes(uint64_t cap) { return (size_t)cap * (kNumDoubleArrays * 8 + kNumU32Arrays * 4); }
+
+gc_status reserve(gc_ctx *ctx, uint64_t need) {
+    if (need <= ctx->cap) return GC_OK;
+    if (need > 0xFFFFFFF0ull) return fail(ctx, GC_EINVAL, "too many particles (%llu)", (unsigned long long)need);
+    uint64_t cap = std::max<uint64_t>({need, ctx->cap * 2, 1024});
+    cap = (cap + 2047) & ~uint64_t(2047);
+    void *m[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i)
+        if (hipMalloc(&m[i], soa_bytes(cap)) != hipSuccess) {
+            if (m[0]) (void)hipFree(m[0]);
+            return fail(ctx, GC_ENOMEM, "cannot allocate particle state for %llu particles", (unsigned long long)cap);
+        }
+    SoA na{}, nb{};
+    carve(m[0], cap, na);
+    carve(m[1], cap, nb);
+    const uint32_t max_blocks = (uint32_t)((cap + kSortTile - 1) / kSortTile);
+    const size_t scratch = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + 64;
+    void *sm = nullptr;
+    if (hipMalloc(&sm, scratch) != hipSuccess) {
+        (void)hipFree(m[0]);
+        (void)hipFree(m[1]);
+        return fail(ctx, GC_ENOMEM, "cannot allocate sort scratch");
+    }
+    uint32_t *log = nullptr;
+    if (ctx->opt.log_depth > 0 &&
+        hipMalloc(&log, (size_t)cap * ctx->opt.log_depth * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(m[0]);
+        (void)hipFree(m[1]);
+        (void)hipFree(sm);
+        return fail(ctx, GC_ENOMEM, "cannot allocate collision log");
+    }
+    hipStream_t s = ctx->stream;
+    if (log) HIPCHK(launch_fill_u32(log, 0xFFFFFFFFu, (size_t)cap * ctx->opt.log_depth, s));
+    if (ctx->n > 0) {
+        // keep the current state (and log) of the first n slots
+        double **src_d[kNumDoubleArrays] = {&ctx->A.r, &ctx->A.th, &ctx->A.ph, &ctx->A.u, &ctx->A.mu, &ctx->A.fr,
+                                            &ctx->A.fth, &ctx->A.fph, &ctx->A.fu, &ctx->A.dtp, &ctx->A.s, &ctx->A.ell,
+                                            &ctx->A.t, &ctx->A.cr, &ctx->A.cth, &ctx->A.cph, &ctx->A.cu, &ctx->A.ct};
+        double **dst_d[kNumDoubleArrays] = {&na.r, &na.th, &na.ph, &na.u, &na.mu, &na.fr, &na.fth, &na.fph, &na.fu,
+                                            &na.dtp, &na.s, &na.ell, &na.t, &na.cr, &na.cth, &na.cph, &na.cu, &na.ct};
+        for (int i = 0; i < kNumDoubleArrays; ++i)
+            HIPCHK(hipMemcpyAsync(*dst_d[i], *src_d[i], ctx->n * 8, hipMemcpyDeviceToDevice, s));
+        uint32_t **src_u[kNumU32Arrays] = {&ctx->A.k, &ctx->A.flags, &ctx->A.status, &ctx->A.step,
+                                           &ctx->A.id, &ctx->A.ens, &ctx->A.gid};
+        uint32_t **dst_u[kNumU32Arrays] = {&na.k, &na.flags, &na.status, &na.step, &na.id, &na.ens, &na.gid};
+        for (int i = 0; i < kNumU32Arrays; ++i)
+            HIPCHK(hipMemcpyAsync(*dst_u[i], *src_u[i], ctx->n * 4, hipMemcpyDeviceToDevice, s));
+        if (log && ctx->log)
+            HIPCHK(hipMemcpyAsync(log, ctx->log, ctx->n * ctx->opt.log_depth * 4, hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < 2; ++i)
+        if (ctx->soa_mem[i]) (void)hipFree(ctx->soa_mem[i]);
+    if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);
+    if (ctx->log) (void)hipFree(ctx->log);
+    ctx->soa_mem[0] = m[0];
+    ctx->soa_mem[1] = m[1];
+    ctx->A = na;
+    ctx->B = nb;
+    ctx->scratch_mem = sm;
+    uint32_t *p = static_cast<uint32_t *>(sm);
+    ctx->sc.keys[0] = p;
+    ctx->sc.keys[1] = p + cap;
+    ctx->sc.vals[0] = p + 2 * cap;
+    ctx->sc.vals[1] = p + 3 * cap;
+    ctx->sc.counts = p + 4 * cap;
+    ctx->sc.totals = ctx->sc.counts + (size_t)256 * max_blocks;
+    ctx->sc.max_blocks = max_blocks;
+    ctx->log = log;
+    ctx->cap = cap;
+    if (ctx->gexec) {
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    return GC_OK;
+}
+
+hipEvent_t take_event(gc_ctx *ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+uint32_t bits_for(uint32_t max_key) {
+    uint32_t b = 1;
+    while (b < 32 && (max_key >> b) != 0) ++b;
+    return b;
+}
+
+gc_status reorder(gc_ctx *ctx, bool timed) {
+    hipStream_t s = ctx->stream;
+    const uint32_t n = (uint32_t)ctx->n;
+    if (ctx->opt.order == GC_ORDER_NONE) {
+        HIPCHK(launch_set_count(ctx->n_active, n, s));
+        return GC_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = take_event(ctx);
+        e1 = take_event(ctx);
+        HIPCHK(hipEventRecord(e0, s));
+    }
+    uint32_t *perm = nullptr;
+    if (ctx->opt.order == GC_ORDER_COMPACT) {
+        HIPCHK(launch_compact(ctx->A, n, ctx->sc, ctx->n_active, &perm, s));
+    } else {
+        const int c = ctx->opt.bin_coarsen;
+        const uint32_t nrc = ((uint32_t)ctx->f.nr + (1u << c) - 1) >> c;
+        const uint32_t nthc = ((uint32_t)ctx->f.nth + (1u << c) - 1) >> c;
+        const uint32_t nphc = ((uint32_t)ctx->f.nph + (1u << c) - 1) >> c;
+        const uint32_t dead = nrc * nthc * nphc;
+        HIPCHK(launch_cell_keys(ctx->A, ctx->f, n, c, dead, ctx->sc.keys[0], ctx->n_active, s));
+        HIPCHK(launch_radix_sort(ctx->sc, n, (int)bits_for(dead), &perm, s));
+    }
+    HIPCHK(launch_permute(ctx->A, ctx->B, perm, n, s));
+    std::swap(ctx->A, ctx->B);
+    std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
+    if (timed) {
+        HIPCHK(hipEventRecord(e1, s));
+        ctx->ev_reorder.emplace_back(e0, e1);
+    }
+    return GC_OK;
+}
+
+gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
+    hipStream_t s = ctx->stream;
+    PushArgs a{};
+    a.st = ctx->A;
+    a.f = ctx->f;
+    a.ens = ctx->ens_dev;
+    a.n_active = ctx->n_active;
+    a.n_slots = (uint32_t)ctx->n;
+    a.n_steps = steps;
+    a.dt = dt;
+    a.steps_done = ctx->steps;
+    a.log = ctx->log;
+    a.log_depth = ctx->opt.log_depth;
+    a.tile = ctx->opt.tile;
+    a.queue = ctx->queue;
+    const bool pers = ctx->opt.persistent != 0;
+    const int grid_blocks = ctx->n_cus * (1024 / ctx->opt.block_size);
+    if (pers) HIPCHK(launch_fill_u32(ctx->queue, 0u, 1, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = take_event(ctx);
+        e1 = take_event(ctx);
+        HIPCHK(hipEventRecord(e0, s));
+    }
+    HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, grid_blocks, s));
+    if (timed) {
+        HIPCHK(hipEventRecord(e1, s));
+        ctx->ev_push.emplace_back(e0, e1);
+    }
+    return GC_OK;
+}
+
+gc_status enqueue_advance(gc_ctx *ctx, double dt, int64_t n_steps, bool timed) {
+    int64_t left = n_steps;
+    while (left > 0) {
+        const int32_t c = (int32_t)std::min<int64_t>(left, ctx->opt.chunk_steps);
+        gc_status st = reorder(ctx, timed);
+        if (st != GC_OK) return st;
+        st = push(ctx, dt, c, timed);
+        if (st != GC_OK) return st;
+        left -= c;
+    }
+    return GC_OK;
+}
+
+gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
+    if (!ctx) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_advance before gc_load_field");
+    if (!(std::isfinite(dt) && dt > 0.0)) return fail(ctx, GC_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+    if (n_steps < 0) return fail(ctx, GC_EINVAL, "n_steps must be >= 0");
+    return GC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gc_default_options(gc_options *o) {
+    std::memset(o, 0, sizeof *o);
+    o->precision = GC_PREC_F64;
+    o->order = GC_ORDER_BIN;
+    o->chunk_steps = 64;
+    o->bin_coarsen = 0;
+    o->block_size = 256;
+    o->persistent = 0;
+    o->tile = 1024;
+    o->log_depth = 0;
+    o->timing = 0;
+}
+
+gc_status gc_create(gc_ctx **out, const gc_options *opt) {
+    if (!out) return GC_EINVAL;
+    *out = nullptr;
+    gc_options o;
+    if (opt) o = *opt;
+    else gc_default_options(&o);
+    gc_ctx *ctx = new gc_ctx();
+    ctx->opt = o;
+    gc_status st = check_options(ctx, &o);
+    if (st != GC_OK) {
+        *out = ctx;   // the caller can read the message, then destroy
+        return st;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
+        *out = ctx;
+        return fail(ctx, GC_EDEVICE, "no HIP device %d (count %d)", o.device, ndev);
+    }
+    *out = ctx;
+    HIPCHK(hipSetDevice(o.device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, o.device));
+    ctx->n_cus = prop.multiProcessorCount;
+    ctx->stream = static_cast<hipStream_t>(o.hip_stream);
+    ctx->ens_host.assign(kMaxEnsembles, EnsDev{});
+    ctx->ens_set.assign(kMaxEnsembles, 0);
+    HIPCHK(hipMalloc(&ctx->ens_dev, sizeof(EnsDev) * kMaxEnsembles));
+    void *small = nullptr;
+    HIPCHK(hipMalloc(&small, 256));
+    ctx->n_active = static_cast<uint32_t *>(small);
+    ctx->queue = ctx->n_active + 1;
+    ctx->steps = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 64);
+    HIPCHK(launch_fill_u32(ctx->n_active, 0u, 2, ctx->stream));
+    HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return GC_OK;
+}
+
+void gc_destroy(gc_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (auto *v : {&ctx->ev_push, &ctx->ev_reorder})
+        for (auto &p : *v) {
+            (void)hipEventDestroy(p.first);
+            (void)hipEventDestroy(p.second);
+        }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (int i = 0; i < 2; ++i)
+        if (ctx->soa_mem[i]) (void)hipFree(ctx->soa_mem[i]);
+    if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);
+    if (ctx->log) (void)hipFree(ctx->log);
+    if (ctx->field_buf) (void)hipFree(ctx->field_buf);
+    if (ctx->ens_dev) (void)hipFree(ctx->ens_dev);
+    if (ctx->n_active) (void)hipFree(ctx->n_active);
+    delete ctx;
+}
+
+const char *gc_last_error(const gc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gc_status gc_set_options(gc_ctx *ctx, const gc_options *opt) {
+    if (!ctx || !opt) return GC_EINVAL;
+    gc_options o = *opt;
+    if (o.log_depth != ctx->opt.log_depth) return fail(ctx, GC_EINVAL, "log_depth cannot change after creation");
+    if (o.device != ctx->opt.device) return fail(ctx, GC_EINVAL, "device cannot change after creation");
+    gc_status st = check_options(ctx, &o);
+    if (st != GC_OK) return st;
+    ctx->opt = o;
+    ctx->stream = static_cast<hipStream_t>(o.hip_stream);
+    return GC_OK;
+}
+
+gc_status gc_get_options(const gc_ctx *ctx, gc_options *opt) {
+    if (!ctx || !opt) return GC_EINVAL;
+    *opt = ctx->opt;
+    return GC_OK;
+}
+
+gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
+    if (!ctx || !d) return GC_EINVAL;
+    if (d->nr < 2 || d->nth < 2 || d->nph < 2)
+        return fail(ctx, GC_EINVAL, "grid needs at least 2 nodes per axis (%d, %d, %d)", d->nr, d->nth, d->nph);
+    if (!(d->r_min > 0.0) || !(d->r_max > d->r_min)) return fail(ctx, GC_EINVAL, "need 0 < r_min < r_max");
+    if (!d->data) return fail(ctx, GC_EINVAL, "data is NULL");
+    if (d->src_dtype != GC_F64 && d->src_dtype != GC_F32) return fail(ctx, GC_EINVAL, "src_dtype must be F64 or F32");
+    if (d->store_dtype < GC_F64 || d->store_dtype > GC_F16) return fail(ctx, GC_EINVAL, "unknown store_dtype");
+    const size_t nodes = (size_t)d->nr * d->nth * d->nph;
+    const size_t packed = (size_t)d->nr * d->nth * (d->nph + 1) * 12;
+    if (packed >= 0xFFFFFFF0ull) return fail(ctx, GC_EINVAL, "grid too large for 32-bit offsets");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    // stage as float64 on the device, then pack
+    std::vector<double> conv;
+    const double *src = static_cast<const double *>(d->data);
+    if (d->src_dtype == GC_F32) {
+        conv.resize(nodes * 12);
+        const float *fp = static_cast<const float *>(d->data);
+        for (size_t i = 0; i < nodes * 12; ++i) conv[i] = fp[i];
+        src = conv.data();
+    }
+    float scale[12], inv_scale[12];
+    for (int c = 0; c < 12; ++c) scale[c] = inv_scale[c] = 1.0f;
+    if (d->store_dtype == GC_F16) {
+        double mx[12] = {0};
+        for (size_t i = 0; i < nodes; ++i)
+            for (int c = 0; c < 12; ++c) mx[c] = std::max(mx[c], std::fabs(src[i * 12 + c]));
+        for (int c = 0; c < 12; ++c) {
+            if (!(mx[c] > 0.0) || !std::isfinite(mx[c])) continue;
+            const int e = (int)std::ceil(std::log2(mx[c])) - 14;   // max maps into (8192, 16384]
+            scale[c] = std::ldexp(1.0f, e);
+            inv_scale[c] = std::ldexp(1.0f, -e);
+        }
+    }
+    const size_t esz = d->store_dtype == GC_F64 ? 8 : (d->store_dtype == GC_F32 ? 4 : 2);
+    void *stage = nullptr, *buf = nullptr;
+    if (hipMalloc(&stage, nodes * 12 * 8 + 64) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot stage field");
+    if (hipMalloc(&buf, packed * esz) != hipSuccess) {
+        (void)hipFree(stage);
+        return fail(ctx, GC_ENOMEM, "cannot allocate field");
+    }
+    float *dscale = reinterpret_cast<float *>(static_cast<char *>(stage) + nodes * 12 * 8);
+    HIPCHK(hipMemcpyAsync(stage, src, nodes * 12 * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s));
+    HIPCHK(hipStreamSynchronize(s));
+    (void)hipFree(stage);
+    if (ctx->field_buf) (void)hipFree(ctx->field_buf);
+    ctx->field_buf = buf;
+    FieldDev &f = ctx->f;
+    f.data = buf;
+    f.nr = d->nr;
+    f.nth = d->nth;
+    f.nph = d->nph;
+    f.dtype = d->store_dtype;
+    f.r_min = d->r_min;
+    const double pi = 3.14159265358979323846;
+    f.inv_dr = (double)(d->nr - 1) / (d->r_max - d->r_min);
+    f.inv_dth = (double)d->nth / pi;
+    f.inv_dph = (double)d->nph / (2.0 * pi);
+    f.inv_nph = 1.0 / (double)d->nph;
+    f.th_lo = 0.5 * pi / d->nth;
+    f.th_hi = pi - 0.5 * pi / d->nth;
+    for (int c = 0; c < 12; ++c) f.scale[c] = scale[c];
+    ctx->have_field = true;
+    if (ctx->gexec) {
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    return GC_OK;
+}
+
+gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
+    if (!ctx || !d) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_inject before gc_load_field");
+    if (d->ensemble >= (uint32_t)kMaxEnsembles) return fail(ctx, GC_EINVAL, "ensemble index >= %d", kMaxEnsembles);
+    if (!(d->m > 0.0) || d->q == 0.0 || !std::isfinite(d->q)) return fail(ctx, GC_EINVAL, "need m > 0 and q != 0");
+    if (!(d->ekin > 0.0) || !std::isfinite(d->ekin)) return fail(ctx, GC_EINVAL, "need ekin > 0");
+    if (!(d->r_in < d->r_out)) return fail(ctx, GC_EINVAL, "need r_in < r_out");
+    if (!(d->mu_lo >= -1.0 && d->mu_lo <= 1.0 && d->mu_hi >= -1.0 && d->mu_hi <= 1.0))
+        return fail(ctx, GC_EINVAL, "mu_lo and mu_hi must be in [-1, 1]");
+    if (d->scatter_law != 0 && d->scatter_law != 1) return fail(ctx, GC_EINVAL, "scatter_law must be 0 or 1");
+    if (d->n == 0) return GC_OK;
+    if ((uint64_t)d->first_id + d->n > 0x100000000ull) return fail(ctx, GC_EINVAL, "ids exceed 32 bits");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    gc_status st = reserve(ctx, ctx->n + d->n);
+    if (st != GC_OK) return st;
+    EnsDev e{};
+    e.qm = d->q / d->m;
+    e.iqm = d->m / d->q;
+    e.m = d->m;
+    e.lambda = d->lambda_par;
+    e.r_in = d->r_in;
+    e.r_out = d->r_out;
+    e.seed = d->seed;
+    e.max_steps = d->max_steps;
+    e.ensemble = d->ensemble;
+    e.drift_free = d->drift_free ? 1 : 0;
+    e.scatter_law = d->scatter_law;
+    ctx->ens_host[d->ensemble] = e;
+    ctx->ens_set[d->ensemble] = 1;
+    HIPCHK(hipMemcpyAsync(ctx->ens_dev + d->ensemble, &ctx->ens_host[d->ensemble], sizeof(EnsDev),
+                          hipMemcpyHostToDevice, ctx->stream));
+    InjectParams ip{d->ekin, d->r0, d->lat0, d->lon0, d->dlon, d->dr0, d->dlat, d->mu_lo, d->mu_hi};
+    HIPCHK(launch_inject(ctx->A, ctx->f, e, ip, (uint32_t)ctx->n, (uint32_t)d->n, d->first_id, d->ensemble,
+                         ctx->stream));
+    ctx->n += d->n;
+    return GC_OK;
+}
+
+gc_status gc_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
+    gc_status st = check_advance(ctx, dt, n_steps);
+    if (st != GC_OK) return st;
+    if (ctx->n == 0 || n_steps == 0) return GC_OK;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    return enqueue_advance(ctx, dt, n_steps, ctx->opt.timing != 0);
+}
+
+gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
+    gc_status st = check_advance(ctx, dt, n_steps);
+    if (st != GC_OK) return st;
+    if (ctx->n == 0 || n_steps == 0) return GC_OK;
+    if (!ctx->stream) return fail(ctx, GC_EINVAL, "graph capture needs a non-null stream");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const bool same = ctx->gexec && ctx->gkey.dt == dt && ctx->gkey.n_steps == n_steps && ctx->gkey.n == ctx->n &&
+                      std::memcmp(&ctx->gkey.opt, &ctx->opt, sizeof(gc_options)) == 0;
+    if (!same) {
+        if (ctx->gexec) {
+            (void)hipGraphExecDestroy(ctx->gexec);
+            ctx->gexec = nullptr;
+        }
+        // the number of reorders must be even so that the state ends in the buffer it started in
+        const int64_t chunks = (n_steps + ctx->opt.chunk_steps - 1) / ctx->opt.chunk_steps;
+        if (ctx->opt.order != GC_ORDER_NONE && (chunks & 1))
+            return fail(ctx, GC_EINVAL, "graph mode needs an even number of chunks (n_steps / chunk_steps)");
+        HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        st = enqueue_advance(ctx, dt, n_steps, false);
+        hipGraph_t g = nullptr;
+        hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
+        if (st != GC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        HIPCHK(ce);
+        hipGraphExec_t ex = nullptr;
+        hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(ie);
+        ctx->gexec = ex;
+        ctx->gkey.dt = dt;
+        ctx->gkey.n_steps = n_steps;
+        ctx->gkey.n = ctx->n;
+        ctx->gkey.opt = ctx->opt;
+    }
+    HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+    return GC_OK;
+}
+
+int64_t gc_moments_size(const gc_moment_spec *s) {
+    if (!s) return -1;
+    return 8 + 3 * (int64_t)s->n_rbins + s->n_mubins + (int64_t)s->n_agebins * s->n_ebins;
+}
+
+gc_status gc_moments(gc_ctx *ctx, const gc_moment_spec *s, int64_t *out) {
+    if (!ctx || !s) return GC_EINVAL;
+    if (!out) return fail(ctx, GC_EINVAL, "out is NULL");
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_moments before gc_load_field");
+    if (s->n_rbins < 0 || s->n_mubins < 0 || s->n_agebins < 0 || s->n_ebins < 0)
+        return fail(ctx, GC_EINVAL, "negative bin count");
+    if (s->n_rbins > 0 && !(s->r_hi > s->r_lo)) return fail(ctx, GC_EINVAL, "empty radial range");
+    if (s->n_agebins > 0 && !(s->age_max > 0.0)) return fail(ctx, GC_EINVAL, "age_max must be > 0");
+    if (s->n_ebins > 0 && !(s->e_hi > s->e_lo)) return fail(ctx, GC_EINVAL, "empty energy range");
+    if (!(s->e_unit > 0.0) || !(s->len_unit > 0.0)) return fail(ctx, GC_EINVAL, "e_unit and len_unit must be > 0");
+    const int64_t total = gc_moments_size(s);
+    if (total > kMaxMoments) return fail(ctx, GC_EINVAL, "too many moment outputs (%lld > %d)", (long long)total, kMaxMoments);
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    MomDev m{};
+    m.n_rbins = s->n_rbins;
+    m.n_mubins = s->n_mubins;
+    m.n_agebins = s->n_agebins;
+    m.n_ebins = s->n_ebins;
+    m.min_collisions = s->min_collisions;
+    m.total = (int32_t)total;
+    m.r_lo = s->r_lo;
+    m.r_hi = s->r_hi;
+    m.sel_r_lo = s->sel_r_lo;
+    m.sel_r_hi = s->sel_r_hi;
+    m.age_lo = s->age_lo;
+    m.age_hi = s->age_hi;
+    m.age_max = s->age_max;
+    m.e_lo = s->e_lo;
+    m.e_hi = s->e_hi;
+    m.e_unit = s->e_unit;
+    m.len_unit = s->len_unit;
+    HIPCHK(launch_moments(ctx->A, ctx->f, ctx->ens_dev, (uint32_t)ctx->n, m,
+                          reinterpret_cast<unsigned long long *>(out), ctx->stream));
+    return GC_OK;
+}
+
+gc_status gc_count(const gc_ctx *ctx, uint64_t *n) {
+    if (!ctx || !n) return GC_EINVAL;
+    *n = ctx->n;
+    return GC_OK;
+}
+
+gc_status gc_get_state(gc_ctx *ctx, const gc_state_view *dst) {
+    if (!ctx || !dst) return GC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(launch_state_out(ctx->A, *dst, (uint32_t)ctx->n, ctx->stream));
+    return GC_OK;
+}
+
+gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
+    if (!ctx || !src) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_set_state before gc_load_field");
+    const void *ptrs[] = {src->r, src->th, src->ph, src->u, src->mu, src->fr, src->fth, src->fph, src->fu,
+                          src->dtp, src->s, src->ell, src->t, src->cr, src->cth, src->cph, src->cu, src->ct,
+                          src->k, src->flags, src->status, src->step, src->id, src->ens};
+    for (const void *p : ptrs)
+        if (!p) return fail(ctx, GC_EINVAL, "every member of the state view must be set");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    gc_status st = reserve(ctx, n);
+    if (st != GC_OK) return st;
+    HIPCHK(launch_state_in(ctx->A, *src, (uint32_t)n, ctx->stream));
+    ctx->n = n;
+    if (ctx->gexec) {
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    return GC_OK;
+}
+
+gc_status gc_get_log(gc_ctx *ctx, uint32_t *dst) {
+    if (!ctx || !dst) return GC_EINVAL;
+    if (ctx->opt.log_depth <= 0) return fail(ctx, GC_ESTATE, "collision log is off (log_depth = 0)");
+    if (ctx->n == 0) return GC_OK;
+    HIPCHK(hipMemcpyAsync(dst, ctx->log, ctx->n * ctx->opt.log_depth * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    return GC_OK;
+}
+
+gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out) {
+    if (!ctx || !out) return GC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::memset(out, 0, sizeof *out);
+    for (auto &p : ctx->ev_push) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        out->push_ms += ms;
+        out->n_push += 1;
+    }
+    for (auto &p : ctx->ev_reorder) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        out->reorder_ms += ms;
+        out->n_reorder += 1;
+    }
+    unsigned long long steps = 0;
+    HIPCHK(hipMemcpy(&steps, ctx->steps, sizeof steps, hipMemcpyDeviceToHost));
+    out->particle_steps = steps;
+    return GC_OK;
+}
+
+gc_status gc_reset_counters(gc_ctx *ctx) {
+    if (!ctx) return GC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (auto *v : {&ctx->ev_push, &ctx->ev_reorder}) {
+        for (auto &p : *v) {
+            ctx->ev_pool.push_back(p.first);
+            ctx->ev_pool.push_back(p.second);
+        }
+        v->clear();
+    }
+    HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return GC_OK;
+}
+
+gc_status gc_copy_probe(gc_ctx *ctx, void *dst, const void *src, uint64_t n_bytes) {
+    if (!ctx || !dst || !src) return GC_EINVAL;
+    if (n_bytes % 16) return fail(ctx, GC_EINVAL, "n_bytes must be a multiple of 16");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(launch_copy_probe(dst, src, n_bytes, ctx->stream));
+    return GC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,193 @@
+// gc_device.h -- device building blocks of the push: counter-based random
+// numbers, trilinear field gather, guiding-centre right-hand side.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "gc_internal.h"
+
+namespace gc {
+
+constexpr double kC = 299792458.0;                    // speed of light (m/s)
+constexpr double kInvC2 = 1.0 / (299792458.0 * 299792458.0);
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of the
+// 64x64->128-bit multiply-xor bijection, key advanced by two Weyl constants.
+// ---------------------------------------------------------------------------
+struct U64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round) { k0 += 0x9E3779B97F4A7C15ULL; k1 += 0xBB67AE8584CAA73BULL; }
+        const uint64_t m0 = 0xD2E7470EE14C6C93ULL, m1 = 0xCA5A826395121157ULL;
+        uint64_t hi0 = __umul64hi(m0, c0), lo0 = m0 * c0;
+        uint64_t hi1 = __umul64hi(m1, c2), lo1 = m1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    }
+    U64x4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// uniform double on [0, 1) from the top 53 bits
+__device__ __forceinline__ double u01(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+// counter word 2: what the block is drawn for
+enum : uint64_t { kPurposePath = 0, kPurposeInject = 1 };
+
+// ---------------------------------------------------------------------------
+// Trilinear interpolation of the packed grid in index space: r nodes from
+// r_min with spacing dr, theta nodes at (j + 1/2) dth, phi periodic.  The
+// stencil is clamped to the grid in floating point before any conversion to
+// an integer, so every load stays inside the buffer for any input.
+// Returns false if the input or any interpolated value is not finite.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R clampr(R x, R lo, R hi) { return fmin(fmax(x, lo), hi); }
+
+template <int FDT> struct Pair;   // 24 values of two phi-adjacent nodes, 12 components each
+
+template <> struct Pair<GC_F32> {
+    float v[24];
+    __device__ __forceinline__ void load(const void *base, uint32_t off) {
+        const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(base) + off);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float4 x = p[q];
+            v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
+    }
+    __device__ __forceinline__ float get(int c, const FieldDev &) const { return v[c]; }
+};
+
+template <> struct Pair<GC_F64> {
+    double v[24];
+    __device__ __forceinline__ void load(const void *base, uint32_t off) {
+        const double2 *p = reinterpret_cast<const double2 *>(static_cast<const double *>(base) + off);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            double2 x = p[q];
+            v[2 * q + 0] = x.x; v[2 * q + 1] = x.y;
+        }
+    }
+    __device__ __forceinline__ double get(int c, const FieldDev &) const { return v[c]; }
+};
+
+template <> struct Pair<GC_F16> {
+    __half v[24];
+    __device__ __forceinline__ void load(const void *base, uint32_t off) {
+        const uint2 *p = reinterpret_cast<const uint2 *>(static_cast<const __half *>(base) + off);
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            uint2 x = p[q];
+            __half h[4];
+            __builtin_memcpy(h, &x, 8);
+            v[4 * q + 0] = h[0]; v[4 * q + 1] = h[1]; v[4 * q + 2] = h[2]; v[4 * q + 3] = h[3];
+        }
+    }
+    __device__ __forceinline__ float get(int c, const FieldDev &f) const {
+        return __half2float(v[c]) * f.scale[c % 12];
+    }
+};
+
+template <int FDT, typename R>
+__device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
+    R x = (r - (R)f.r_min) * (R)f.inv_dr;
+    R y = th * (R)f.inv_dth - (R)0.5;
+    R z = ph * (R)f.inv_dph;
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) return false;
+    const R nph = (R)f.nph;
+    R fi = clampr(floor(x), (R)0, (R)(f.nr - 2));
+    R fj = clampr(floor(y), (R)0, (R)(f.nth - 2));
+    R wr = clampr(x - fi, (R)0, (R)1);
+    R wt = clampr(y - fj, (R)0, (R)1);
+    R zf = floor(z);
+    R wp = z - zf;
+    R km = zf - nph * floor(zf * (R)f.inv_nph);
+    km = km < (R)0 ? km + nph : km;
+    km = km >= nph ? km - nph : km;
+    km = clampr(km, (R)0, nph - (R)1);
+    const uint32_t i = (uint32_t)fi, j = (uint32_t)fj, k = (uint32_t)km;
+    const uint32_t row = (uint32_t)(f.nph + 1) * 12u;
+    const uint32_t o00 = (i * (uint32_t)f.nth + j) * row + k * 12u;
+    const uint32_t dI = (uint32_t)f.nth * row;
+    // sum over the four (r, theta) corners of w_ab * (phi-lerp of the node pair)
+    const R w[4] = {((R)1 - wr) * ((R)1 - wt), ((R)1 - wr) * wt, wr * ((R)1 - wt), wr * wt};
+    const uint32_t off[4] = {o00, o00 + row, o00 + dI, o00 + dI + row};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = (R)0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Pair<FDT> p;
+        p.load(f.data, off[q]);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const R a = (R)p.get(c, f), b = (R)p.get(c + 12, f);
+            out[c] = fma(w[q], fma(wp, b - a, a), out[c]);
+        }
+        if (q & 1) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
+    }
+    R sum = (R)0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sum += out[c];
+    return isfinite(sum);
+}
+
+// ---------------------------------------------------------------------------
+// Guiding-centre right-hand side, Eqs. (1)-(2), reduced to the terms the
+// twelve gridded components determine (b, E, grad|B|, (b.grad)b):
+//   gamma = sqrt(1 + (u^2 + 2 mu B)/c^2)      (mu = mu_B / m, u = gamma v_par)
+//   dR/dt = v_par b + v_E + (gamma/(q/m B)) b x a,
+//   a     = (mu/gamma^2) grad B + ((q/m) v_par E_par/(gamma c^2)) v_E + v_par^2 (b.grad)b
+//   du/dt = (q/m) E_par - (mu/gamma) b.grad B + gamma v_par v_E.(b.grad)b
+// drift-free form (only v_par b kept): dR/dt = v_par b, du/dt without the v_E term.
+// Output: coordinate rates (dr/dt, dth/dt, dph/dt, du/dt) and v_par.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void gc_rhs(R r, R th, R u, R mu, R qm, R iqm, bool drift_free,
+                                       const R g[12], R F[4], R &vpar) {
+    const R Bx = g[0], By = g[1], Bz = g[2];
+    const R Ex = g[3], Ey = g[4], Ez = g[5];
+    const R Gx = g[6], Gy = g[7], Gz = g[8];
+    const R Kx = g[9], Ky = g[10], Kz = g[11];
+    const R B = sqrt(Bx * Bx + By * By + Bz * Bz);
+    const R iB = (R)1 / B;
+    const R bx = Bx * iB, by = By * iB, bz = Bz * iB;
+    const R gamma = sqrt((R)1 + (u * u + (R)2 * mu * B) * (R)kInvC2);
+    const R ig = (R)1 / gamma;
+    vpar = u * ig;
+    const R Epar = Ex * bx + Ey * by + Ez * bz;
+    const R vEx = (Ey * bz - Ez * by) * iB;
+    const R vEy = (Ez * bx - Ex * bz) * iB;
+    const R vEz = (Ex * by - Ey * bx) * iB;
+    const R bG = bx * Gx + by * Gy + bz * Gz;
+    R Vx, Vy, Vz, udot;
+    if (drift_free) {
+        Vx = vpar * bx; Vy = vpar * by; Vz = vpar * bz;
+        udot = qm * Epar - mu * ig * bG;
+    } else {
+        const R cG = mu * ig * ig;
+        const R cE = qm * vpar * Epar * ig * (R)kInvC2;
+        const R cK = vpar * vpar;
+        const R ax = cG * Gx + cE * vEx + cK * Kx;
+        const R ay = cG * Gy + cE * vEy + cK * Ky;
+        const R az = cG * Gz + cE * vEz + cK * Kz;
+        const R pref = gamma * iqm * iB;
+        Vx = vpar * bx + vEx + pref * (by * az - bz * ay);
+        Vy = vpar * by + vEy + pref * (bz * ax - bx * az);
+        Vz = vpar * bz + vEz + pref * (bx * ay - by * ax);
+        udot = qm * Epar - mu * ig * bG + gamma * vpar * (vEx * Kx + vEy * Ky + vEz * Kz);
+    }
+    const R ir = (R)1 / r;
+    F[0] = Vx;
+    F[1] = Vy * ir;
+    F[2] = Vz * ir / sin(th);
+    F[3] = udot;
+}
+
+}  // namespace gc

@@ -1,0 +1,66 @@
+// gc_internal.h -- structures shared by the host library and its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gcpush.h"
+
+namespace gc {
+
+constexpr int kMaxEnsembles = 4096;
+constexpr int kMaxMoments = 8192;
+constexpr int kNumComp = 12;
+
+// Per-ensemble parameters, indexed by the particle's ensemble field.
+struct EnsDev {
+    double qm;          // q / m (C/kg)
+    double iqm;         // m / q
+    double m;           // kg
+    double lambda;      // mean free path (m); <= 0: no scattering
+    double r_in, r_out; // exit shell (m)
+    uint64_t seed;      // generator key word 0
+    int64_t max_steps;  // > 0: FINISHED after this many steps
+    uint32_t ensemble;  // generator key word 1
+    int32_t drift_free;
+    int32_t scatter_law;
+    int32_t pad;
+};
+
+// Packed field on the device: [nr][nth][nph+1][12], the extra phi node repeats
+// node 0 so that every phi pair (k, k+1) is contiguous.
+struct FieldDev {
+    const void *data;
+    int32_t nr, nth, nph, dtype;
+    double r_min;
+    double inv_dr, inv_dth, inv_dph, inv_nph;
+    double th_lo, th_hi;  // first and last theta node (exit bounds)
+    float scale[12];      // GC_F16: stored value * scale = field value
+};
+
+// Structure-of-arrays particle state (one slot per particle).
+struct SoA {
+    double *r, *th, *ph, *u, *mu;
+    double *fr, *fth, *fph, *fu;
+    double *dtp, *s, *ell, *t;
+    double *cr, *cth, *cph, *cu, *ct;
+    uint32_t *k, *flags, *status, *step, *id, *ens, *gid;
+};
+constexpr int kNumDoubleArrays = 18;
+constexpr int kNumU32Arrays = 7;
+
+struct PushArgs {
+    SoA st;
+    FieldDev f;
+    const EnsDev *ens;
+    const uint32_t *n_active;      // device count of slots to visit
+    uint32_t n_slots;              // grid coverage
+    int32_t n_steps;
+    double dt;
+    unsigned long long *steps_done;
+    uint32_t *log;                 // [n_total][log_depth] indexed by gid
+    int32_t log_depth;
+    int32_t tile;                  // persistent mode: particles per work item
+    uint32_t *queue;               // persistent mode: next tile counter
+};
+
+}  // namespace gc

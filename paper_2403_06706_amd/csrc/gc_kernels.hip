@@ -1,0 +1,238 @@
+// gc_kernels.hip -- injection, field packing, moments, state copies, fills.
+#include <hip/hip_runtime.h>
+
+#include "gc_device.h"
+#include "gc_launch.h"
+
+namespace gc {
+
+// ---------------------------------------------------------------------------
+// Field packing: [nr][nth][nph][12] float64 (staged on the device) ->
+// [nr][nth][nph+1][12] in the storage type, the extra phi node repeating node 0.
+// ---------------------------------------------------------------------------
+__global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
+                             const float *inv_scale_in) {
+    const size_t total = (size_t)nr * nth * (nph + 1) * 12;
+    for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total; o += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(o % 12);
+        size_t node = o / 12;
+        const int k = (int)(node % (nph + 1));
+        const size_t ij = node / (nph + 1);
+        const size_t si = (ij * nph + (k == nph ? 0 : k)) * 12 + c;
+        const double v = src[si];
+        if (dtype == GC_F64) static_cast<double *>(dst)[o] = v;
+        else if (dtype == GC_F32) static_cast<float *>(dst)[o] = (float)v;
+        else static_cast<__half *>(dst)[o] = __float2half((float)(v * (double)inv_scale_in[c]));
+    }
+}
+
+hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
+                             const float *inv_scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_field, dim3(2048), dim3(256), 0, s, src, dst, nr, nth, nph, dtype, inv_scale);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Injection (Sect. 3): one particle per lane, FP64.
+// ---------------------------------------------------------------------------
+template <int FDT>
+__global__ void k_inject(SoA st, FieldDev f, EnsDev e, InjectParams ip, uint32_t n0, uint32_t n,
+                         uint32_t first_id, uint32_t eidx) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t slot = n0 + i, pid = first_id + i;
+    const U64x4 a = philox4x64_10(pid, 0, kPurposeInject, 0, e.seed, e.ensemble);
+    const double ph = ip.lon0 + ip.dlon * (2.0 * u01(a.v[0]) - 1.0);
+    const double mup = ip.mu_lo + (ip.mu_hi - ip.mu_lo) * u01(a.v[1]);
+    const double r = ip.r0 + ip.dr0 * (2.0 * u01(a.v[2]) - 1.0);
+    const double lat = ip.lat0 + ip.dlat * (2.0 * u01(a.v[3]) - 1.0);
+    const double th = 0.5 * kPi - lat;
+    const double gamma = 1.0 + ip.ekin / (e.m * kC * kC);
+    const double pm = kC * sqrt(gamma * gamma - 1.0);        // |p| / m
+    const U64x4 b = philox4x64_10(pid, 0, kPurposePath, 0, e.seed, e.ensemble);
+    const double ell = e.lambda > 0.0 ? -e.lambda * log(1.0 - u01(b.v[0])) : __builtin_inf();
+    uint32_t status = GC_ACTIVE;
+    double mu = 0.0;
+    if (r < e.r_in || r > e.r_out || th < f.th_lo || th > f.th_hi) {
+        status = GC_EXITED;
+    } else {
+        double g[12];
+        if (!gather<FDT, double>(f, r, th, ph, g)) status = GC_NONFINITE;
+        else mu = pm * pm * (1.0 - mup * mup) / (2.0 * sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]));
+    }
+    st.r[slot] = r; st.th[slot] = th; st.ph[slot] = ph; st.u[slot] = pm * mup; st.mu[slot] = mu;
+    st.fr[slot] = 0.0; st.fth[slot] = 0.0; st.fph[slot] = 0.0; st.fu[slot] = 0.0;
+    st.dtp[slot] = 0.0; st.s[slot] = 0.0; st.ell[slot] = ell; st.t[slot] = 0.0;
+    st.cr[slot] = 0.0; st.cth[slot] = 0.0; st.cph[slot] = 0.0; st.cu[slot] = 0.0; st.ct[slot] = 0.0;
+    st.k[slot] = 0; st.flags[slot] = GC_FLAG_BOOTSTRAP; st.status[slot] = status; st.step[slot] = 0;
+    st.id[slot] = pid; st.ens[slot] = eidx; st.gid[slot] = slot;
+}
+
+hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, const InjectParams &ip,
+                         uint32_t n0, uint32_t n, uint32_t first_id, uint32_t eidx, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const dim3 grid((n + 255) / 256), block(256);
+    switch (f.dtype) {
+        case GC_F64: hipLaunchKernelGGL(k_inject<GC_F64>, grid, block, 0, s, st, f, e, ip, n0, n, first_id, eidx); break;
+        case GC_F32: hipLaunchKernelGGL(k_inject<GC_F32>, grid, block, 0, s, st, f, e, ip, n0, n, first_id, eidx); break;
+        default:     hipLaunchKernelGGL(k_inject<GC_F16>, grid, block, 0, s, st, f, e, ip, n0, n, first_id, eidx); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Moments: per-block 64-bit histograms in LDS, merged with global atomics.
+// Every contribution is an integer, so the result does not depend on order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long fixp(double x, double scale) {
+    return (unsigned long long)(long long)floor(x * scale);
+}
+
+template <int FDT>
+__global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, MomDev m, unsigned long long *out) {
+    extern __shared__ unsigned long long h[];
+    for (int i = threadIdx.x; i < m.total; i += blockDim.x) h[i] = 0ull;
+    __syncthreads();
+    unsigned long long *rb = h + 8;
+    unsigned long long *mh = rb + 3 * m.n_rbins;
+    unsigned long long *eh = mh + m.n_mubins;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t status = st.status[i];
+        if (status <= GC_NONFINITE) atomicAdd(&h[status], 1ull);
+        atomicAdd(&h[4], (unsigned long long)st.k[i]);
+        atomicAdd(&h[5], (unsigned long long)st.step[i]);
+        if (status != GC_ACTIVE) continue;
+        const double r = st.r[i], th = st.th[i], ph = st.ph[i], u = st.u[i], mu = st.mu[i], t = st.t[i];
+        const uint32_t k = st.k[i];
+        atomicAdd(&h[6], fixp(r / m.len_unit, 4294967296.0));
+        if (k >= 1) atomicAdd(&h[7], 1ull);
+        double g[12];
+        if (!gather<FDT, double>(f, r, th, ph, g)) continue;
+        const double B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+        const double p2 = u * u + 2.0 * mu * B;                // (|p|/m)^2
+        const double pm = sqrt(p2);
+        const double cosa = pm > 0.0 ? u / pm : 1.0;
+        const double sin2 = 1.0 - cosa * cosa;
+        const double gamma = sqrt(1.0 + p2 * kInvC2);
+        const double ekin = (gamma - 1.0) * ens[min(st.ens[i], (uint32_t)(kMaxEnsembles - 1))].m * kC * kC / m.e_unit;
+        if (m.n_rbins > 0) {
+            const double x = (r - m.r_lo) / (m.r_hi - m.r_lo) * m.n_rbins;
+            if (x >= 0.0 && x < (double)m.n_rbins) {
+                const int bi = (int)floor(x);
+                atomicAdd(&rb[3 * bi + 0], 1ull);
+                atomicAdd(&rb[3 * bi + 1], fixp(sin2, 4294967296.0));
+                atomicAdd(&rb[3 * bi + 2], fixp(ekin, 65536.0));
+            }
+        }
+        if (r < m.sel_r_lo || r >= m.sel_r_hi) continue;
+        if (m.n_mubins > 0 && t >= m.age_lo && t < m.age_hi && (int64_t)k >= (int64_t)m.min_collisions) {
+            const double x = (cosa + 1.0) * 0.5 * m.n_mubins;
+            int bi = (int)floor(x);
+            bi = bi < 0 ? 0 : (bi >= m.n_mubins ? m.n_mubins - 1 : bi);
+            atomicAdd(&mh[bi], 1ull);
+        }
+        if (m.n_agebins > 0 && m.n_ebins > 0) {
+            const double xa = t / m.age_max * m.n_agebins;
+            const double xe = (ekin - m.e_lo) / (m.e_hi - m.e_lo) * m.n_ebins;
+            if (xa >= 0.0 && xa < (double)m.n_agebins && xe >= 0.0 && xe < (double)m.n_ebins)
+                atomicAdd(&eh[(int)floor(xa) * m.n_ebins + (int)floor(xe)], 1ull);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m.total; i += blockDim.x)
+        if (h[i]) atomicAdd(&out[i], h[i]);
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static unsigned grid_for(size_t n, unsigned block) {
+    size_t g = (n + block - 1) / block;
+    if (g > 4096) g = 4096;
+    return g == 0 ? 1u : (unsigned)g;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
+                          unsigned long long *out, hipStream_t s) {
+    hipError_t e = launch_fill_u64(out, 0ull, (size_t)m.total, s);
+    if (e != hipSuccess || n == 0) return e;
+    const dim3 grid(grid_for(n, 256) > 1024 ? 1024 : grid_for(n, 256)), block(256);
+    const size_t lds = (size_t)m.total * sizeof(unsigned long long);
+    switch (f.dtype) {
+        case GC_F64: hipLaunchKernelGGL(k_moments<GC_F64>, grid, block, lds, s, st, f, ens, n, m, out); break;
+        case GC_F32: hipLaunchKernelGGL(k_moments<GC_F32>, grid, block, lds, s, st, f, ens, n, m, out); break;
+        default:     hipLaunchKernelGGL(k_moments<GC_F16>, grid, block, lds, s, st, f, ens, n, m, out); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// State export / import in global injection order.
+// ---------------------------------------------------------------------------
+#define GC_FOR_DOUBLES(X) X(r) X(th) X(ph) X(u) X(mu) X(fr) X(fth) X(fph) X(fu) X(dtp) X(s) X(ell) X(t) \
+                          X(cr) X(cth) X(cph) X(cu) X(ct)
+#define GC_FOR_U32(X) X(k) X(flags) X(status) X(step) X(id) X(ens)
+
+__global__ void k_state_out(SoA st, gc_state_view dst, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t g = st.gid[i];
+#define OUT_(name) if (dst.name) dst.name[g] = st.name[i];
+    GC_FOR_DOUBLES(OUT_)
+    GC_FOR_U32(OUT_)
+#undef OUT_
+}
+
+__global__ void k_state_in(SoA st, gc_state_view src, uint32_t n) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+#define IN_(name) st.name[g] = src.name[g];
+    GC_FOR_DOUBLES(IN_)
+    GC_FOR_U32(IN_)
+#undef IN_
+    st.gid[g] = g;
+}
+
+hipError_t launch_state_out(const SoA &st, const gc_state_view &dst, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_state_out, dim3((n + 255) / 256), dim3(256), 0, s, st, dst, n);
+    return hipGetLastError();
+}
+hipError_t launch_state_in(const SoA &st, const gc_state_view &src, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_state_in, dim3((n + 255) / 256), dim3(256), 0, s, st, src, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Plain streaming copy (16 B per lane per iteration) for counter calibration.
+// ---------------------------------------------------------------------------
+__global__ void k_copy_probe(uint4 *dst, const uint4 *src, size_t n16) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t s) {
+    const size_t n16 = n_bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_probe, dim3(grid_for(n16, 256)), dim3(256), 0, s, static_cast<uint4 *>(dst),
+                       static_cast<const uint4 *>(src), n16);
+    return hipGetLastError();
+}
+
+}  // namespace gc

@@ -1,0 +1,52 @@
+// gc_launch.h -- host-side launchers of the kernels (defined in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "gc_internal.h"
+
+namespace gc {
+
+struct InjectParams {
+    double ekin, r0, lat0, lon0, dlon, dr0, dlat, mu_lo, mu_hi;
+};
+
+struct MomDev {
+    int32_t n_rbins, n_mubins, n_agebins, n_ebins, min_collisions, total;
+    double r_lo, r_hi, sel_r_lo, sel_r_hi, age_lo, age_hi, age_max, e_lo, e_hi, e_unit, len_unit;
+};
+
+// push (gc_push.hip)
+hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int grid_blocks,
+                       hipStream_t s);
+
+// injection, moments, state copies, fills (gc_kernels.hip)
+hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, const InjectParams &ip,
+                         uint32_t n0, uint32_t n, uint32_t first_id, uint32_t eidx, hipStream_t s);
+hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
+                          unsigned long long *out, hipStream_t s);
+hipError_t launch_state_out(const SoA &st, const gc_state_view &dst, uint32_t n, hipStream_t s);
+hipError_t launch_state_in(const SoA &st, const gc_state_view &src, uint32_t n, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t s);
+hipError_t launch_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t s);
+hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
+                             const float *inv_scale, hipStream_t s);
+
+// reordering (gc_order.hip)
+struct OrderScratch {
+    uint32_t *keys[2];
+    uint32_t *vals[2];
+    uint32_t *counts;      // [256][max_blocks] radix histograms, or per-block alive counts
+    uint32_t *totals;      // [256]
+    uint32_t max_blocks;
+};
+constexpr int kSortTile = 2048;     // items per radix-sort block
+hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, uint32_t n, int coarsen, uint32_t dead_key,
+                            uint32_t *keys, uint32_t *n_active, hipStream_t s);
+hipError_t launch_radix_sort(OrderScratch &sc, uint32_t n, int bits, uint32_t **perm_out, hipStream_t s);
+hipError_t launch_compact(const SoA &st, uint32_t n, OrderScratch &sc, uint32_t *n_active, uint32_t **perm_out,
+                          hipStream_t s);
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, hipStream_t s);
+hipError_t launch_set_count(uint32_t *n_active, uint32_t n, hipStream_t s);
+
+}  // namespace gc

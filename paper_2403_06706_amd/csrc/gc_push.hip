@@ -1,0 +1,262 @@
+// gc_push.hip -- the hot path: advance particles by a chunk of steps.
+//
+// One particle per lane.  Its state is loaded into registers once per launch,
+// advanced for n_steps steps of the third-order predictor-corrector (Eqs. 5-6)
+// with hard-sphere scattering (Eqs. 9-10), and stored once.  Each step makes
+// two trilinear gathers of the 12 field components (at X^n and at X*), a third
+// one on bootstrap steps (injection and after a collision).
+#include <hip/hip_runtime.h>
+
+#include "gc_device.h"
+#include "gc_launch.h"
+
+namespace gc {
+
+template <int PREC> struct PrecT;
+template <> struct PrecT<GC_PREC_F64> { using R = double; using A = double; static constexpr bool kKahan = false; };
+template <> struct PrecT<GC_PREC_F32_ACC64> { using R = float; using A = double; static constexpr bool kKahan = false; };
+template <> struct PrecT<GC_PREC_F32_KAHAN> { using R = float; using A = float; static constexpr bool kKahan = true; };
+
+// x += d with Kahan compensation c (true sum ~ x - c)
+template <typename A>
+__device__ __forceinline__ void kahan_add(A &x, A &c, A d) {
+    A y = d - c;
+    A t = x + y;
+    c = (t - x) - y;
+    x = t;
+}
+
+// Generator block of collision k1 (counter (id, k1, 0, 0), key (seed, ensemble)):
+// new pitch cosine from a1 (Eq. 10, or Eq. 12 with the sign from a2) and the
+// next free path -lambda ln(1 - a0).  Kept out of line: it runs for a few
+// steps in a thousand, and inlined it would raise the push's register count.
+struct CollisionDraw { double mun, ell; };
+
+__device__ __noinline__ CollisionDraw draw_collision(uint32_t pid, uint32_t k1, uint64_t seed, uint32_t ens,
+                                                     int law, double lambda) {
+    const U64x4 rb = philox4x64_10(pid, k1, kPurposePath, 0, seed, ens);
+    const double a0 = u01(rb.v[0]), a1 = u01(rb.v[1]), a2 = u01(rb.v[2]);
+    CollisionDraw d;
+    d.mun = law == 1 ? (a2 < 0.5 ? -1.0 : 1.0) * sqrt(a1) : 1.0 - 2.0 * a1;
+    d.ell = -lambda * log(1.0 - a0);
+    return d;
+}
+
+template <int PREC, int FDT>
+__device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot) {
+    using R = typename PrecT<PREC>::R;
+    using A = typename PrecT<PREC>::A;
+    constexpr bool kKahan = PrecT<PREC>::kKahan;
+    const SoA &st = a.st;
+    uint32_t status = st.status[slot];
+    if (status != GC_ACTIVE) return 0;
+    uint32_t flags = st.flags[slot], k = st.k[slot], step = st.step[slot];
+    const uint32_t step0 = step;
+    const EnsDev e = a.ens[min(st.ens[slot], (uint32_t)(kMaxEnsembles - 1))];
+    const uint32_t pid = st.id[slot];
+    A X0 = (A)st.r[slot], X1 = (A)st.th[slot], X2 = (A)st.ph[slot], X3 = (A)st.u[slot];
+    A T = (A)st.t[slot];
+    A c0 = 0, c1 = 0, c2 = 0, c3 = 0, cT = 0;
+    if (kKahan) {
+        c0 = (A)st.cr[slot]; c1 = (A)st.cth[slot]; c2 = (A)st.cph[slot]; c3 = (A)st.cu[slot]; cT = (A)st.ct[slot];
+    }
+    R fp0 = (R)st.fr[slot], fp1 = (R)st.fth[slot], fp2 = (R)st.fph[slot], fp3 = (R)st.fu[slot];
+    R mu = (R)st.mu[slot], dtp = (R)st.dtp[slot], s = (R)st.s[slot], ell = (R)st.ell[slot];
+    const R qm = (R)e.qm, iqm = (R)e.iqm;
+    const bool drift_free = e.drift_free != 0;
+    const bool scatter = e.lambda > 0.0;
+    const R h = (R)a.dt;
+    const double r_in = e.r_in, r_out = e.r_out, th_lo = a.f.th_lo, th_hi = a.f.th_hi;
+
+    for (int it = 0; it < a.n_steps; ++it) {
+        // Field evaluations of the step, through one gather + right-hand side
+        // site: stage 0 at X^n, stage 1 (bootstrap only) at X^{n-1} = X^n - dt F^n,
+        // stage 2 at the predictor X*.  Lanes of a wavefront in different
+        // stages run the same instructions.
+        R Fn[4], Fs[4], vpn = 0, vps = 0, tau = 1;
+        // A pending collision k+1 draws its generator block before the first
+        // gather of the step (few live registers here); it is applied once the
+        // gather at X^n gives |B| there.
+        R mun = 0, ell_new = 0;
+        if (flags & GC_FLAG_PENDING) {
+            const CollisionDraw d = draw_collision(pid, k + 1, e.seed, e.ensemble, e.scatter_law, e.lambda);
+            mun = (R)d.mun;
+            ell_new = (R)d.ell;
+        }
+        R px = (R)X0, pth = (R)X1, pph = (R)X2, pu = (R)X3;
+        int stage = 0;
+        bool bad = false;
+        for (;;) {
+            R g[12];
+            if (!gather<FDT, R>(a.f, px, pth, pph, g)) { bad = true; break; }
+            if (stage == 0 && (flags & GC_FLAG_PENDING)) {
+                // collision k+1 (Eqs. 9-10): |p| kept, new pitch cosine and free path
+                const R B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                const R p2 = pu * pu + (R)2 * mu * B;            // (p/m)^2
+                X3 = (A)(mun * sqrt(p2));
+                c3 = 0;
+                pu = (R)X3;
+                mu = p2 * ((R)1 - mun * mun) / ((R)2 * B);
+                ell = ell_new;
+                s = 0;
+                k += 1;
+                flags = (flags | GC_FLAG_BOOTSTRAP) & ~GC_FLAG_PENDING;
+                if (a.log_depth > 0 && k <= (uint32_t)a.log_depth)
+                    a.log[(size_t)st.gid[slot] * a.log_depth + (k - 1)] = step;
+            }
+            R F[4], vp;
+            gc_rhs<R>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp);
+            if (stage == 2) {
+                Fs[0] = F[0]; Fs[1] = F[1]; Fs[2] = F[2]; Fs[3] = F[3];
+                vps = vp;
+                break;
+            }
+            if (stage == 0) {
+                Fn[0] = F[0]; Fn[1] = F[1]; Fn[2] = F[2]; Fn[3] = F[3];
+                vpn = vp;
+                if (flags & GC_FLAG_BOOTSTRAP) {
+                    // backward Euler start (Sect. 2.2)
+                    px = (R)X0 - h * F[0]; pth = (R)X1 - h * F[1]; pph = (R)X2 - h * F[2]; pu = (R)X3 - h * F[3];
+                    stage = 1;
+                    continue;
+                }
+                tau = h / dtp;
+            } else {   // stage 1: F^{n-1} of the bootstrap
+                fp0 = F[0]; fp1 = F[1]; fp2 = F[2]; fp3 = F[3];
+                tau = (R)1;
+                flags &= ~GC_FLAG_BOOTSTRAP;
+            }
+            // predictor, Eq. 5
+            const R wn = (R)1 + (R)0.5 * tau, wq = (R)0.5 * tau;
+            const R d0 = h * (wn * Fn[0] - wq * fp0), d1 = h * (wn * Fn[1] - wq * fp1);
+            const R d2 = h * (wn * Fn[2] - wq * fp2), d3 = h * (wn * Fn[3] - wq * fp3);
+            if (kKahan) {
+                px = (R)(X0 + (d0 - c0)); pth = (R)(X1 + (d1 - c1)); pph = (R)(X2 + (d2 - c2)); pu = (R)(X3 + (d3 - c3));
+            } else {
+                px = (R)(X0 + (A)d0); pth = (R)(X1 + (A)d1); pph = (R)(X2 + (A)d2); pu = (R)(X3 + (A)d3);
+            }
+            stage = 2;
+        }
+        if (bad) { status = GC_NONFINITE; break; }
+        // corrector, Eq. 6: dt/(6(1+tau)) [(1+tau)(3+tau) F^n + (3+2 tau) F* - tau^2 F^{n-1}]
+        const R cf = h / ((R)6 * ((R)1 + tau));
+        const R an = ((R)1 + tau) * ((R)3 + tau), as = (R)3 + (R)2 * tau, ap = tau * tau;
+        const R e0 = cf * (an * Fn[0] + as * Fs[0] - ap * fp0);
+        const R e1 = cf * (an * Fn[1] + as * Fs[1] - ap * fp1);
+        const R e2 = cf * (an * Fn[2] + as * Fs[2] - ap * fp2);
+        const R e3 = cf * (an * Fn[3] + as * Fs[3] - ap * fp3);
+        // path along the field line over the step (trapezoid of |v_par|), Eq. 9
+        if (scatter) {
+            s += (R)0.5 * (fabs(vpn) + fabs(vps)) * h;
+            if (s >= ell) flags |= GC_FLAG_PENDING;
+        }
+        A n0, n1, n2, n3;
+        A nc0 = c0, nc1 = c1, nc2 = c2, nc3 = c3;   // new compensation terms (Kahan form)
+        if (kKahan) {
+            n0 = X0; n1 = X1; n2 = X2; n3 = X3;
+            kahan_add(n0, nc0, (A)e0); kahan_add(n1, nc1, (A)e1);
+            kahan_add(n2, nc2, (A)e2); kahan_add(n3, nc3, (A)e3);
+        } else {
+            n0 = X0 + (A)e0; n1 = X1 + (A)e1; n2 = X2 + (A)e2; n3 = X3 + (A)e3;
+        }
+        X0 = n0; X1 = n1; X2 = n2; X3 = n3;
+        c0 = nc0; c1 = nc1; c2 = nc2; c3 = nc3;
+        fp0 = Fn[0]; fp1 = Fn[1]; fp2 = Fn[2]; fp3 = Fn[3];
+        dtp = h;
+        if (kKahan) kahan_add(T, cT, (A)h);
+        else T += (A)a.dt;
+        step += 1;
+        if (!(isfinite(n0) && isfinite(n1) && isfinite(n2) && isfinite(n3))) { status = GC_NONFINITE; break; }
+        const double r = (double)X0, th = (double)X1;
+        if (r < r_in || r > r_out || th < th_lo || th > th_hi) { status = GC_EXITED; break; }
+        if (e.max_steps > 0 && (int64_t)step >= e.max_steps) { status = GC_FINISHED; break; }
+    }
+    st.r[slot] = (double)X0; st.th[slot] = (double)X1; st.ph[slot] = (double)X2; st.u[slot] = (double)X3;
+    if (kKahan) {
+        st.cr[slot] = (double)c0; st.cth[slot] = (double)c1; st.cph[slot] = (double)c2;
+        st.cu[slot] = (double)c3; st.ct[slot] = (double)cT;
+    }
+    st.t[slot] = (double)T;
+    st.fr[slot] = (double)fp0; st.fth[slot] = (double)fp1; st.fph[slot] = (double)fp2; st.fu[slot] = (double)fp3;
+    st.mu[slot] = (double)mu; st.dtp[slot] = (double)dtp; st.s[slot] = (double)s; st.ell[slot] = (double)ell;
+    st.k[slot] = k; st.flags[slot] = flags; st.status[slot] = status; st.step[slot] = step;
+    return step - step0;
+}
+
+__device__ __forceinline__ void count_steps(const PushArgs &a, uint32_t taken) {
+    // one atomic per wavefront
+    uint32_t v = taken;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(a.steps_done, (unsigned long long)v);
+}
+
+// Grid form: one slot per lane.  Workgroups are dispatched round-robin over
+// the 8 XCDs; the remap gives each XCD a contiguous range of (cell-sorted)
+// slots so that its L2 holds the field cells of its own particles.
+template <int PREC, int FDT>
+__global__ __launch_bounds__(256) void k_push(PushArgs a) {
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb >> 3, rem = nb & 7u, xcd = b & 7u, pos = b >> 3;
+    const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
+    const uint32_t slot = lb * blockDim.x + threadIdx.x;
+    const uint32_t n = *a.n_active;
+    uint32_t taken = 0;
+    if (slot < n) taken = advance_slot<PREC, FDT>(a, slot);
+    count_steps(a, taken);
+}
+
+// Persistent form: a fixed grid pulls tiles of consecutive slots from an
+// atomic counter until the tiles run out (every workgroup reaches the exit).
+template <int PREC, int FDT>
+__global__ __launch_bounds__(256) void k_push_persistent(PushArgs a) {
+    __shared__ uint32_t s_tile;
+    const uint32_t n = *a.n_active;
+    const uint32_t tile = (uint32_t)a.tile;
+    const uint32_t ntiles = (n + tile - 1) / tile;
+    uint32_t taken = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const uint32_t t = s_tile;
+        __syncthreads();
+        if (t >= ntiles) break;
+        const uint32_t end = min(n, (t + 1) * tile);
+        for (uint32_t slot = t * tile + threadIdx.x; slot < end; slot += blockDim.x)
+            taken += advance_slot<PREC, FDT>(a, slot);
+    }
+    count_steps(a, taken);
+}
+
+template <int PREC, int FDT>
+static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int grid_blocks, hipStream_t s) {
+    if (persistent) {
+        hipLaunchKernelGGL((k_push_persistent<PREC, FDT>), dim3(grid_blocks), dim3(block), 0, s, a);
+    } else {
+        const uint32_t nb = (a.n_slots + block - 1) / block;
+        if (nb == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_push<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_p(const PushArgs &a, int block, bool persistent, int grid_blocks, hipStream_t s) {
+    switch (a.f.dtype) {
+        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, grid_blocks, s);
+        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, grid_blocks, s);
+        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, grid_blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int grid_blocks,
+                       hipStream_t s) {
+    switch (precision) {
+        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, grid_blocks, s);
+        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, grid_blocks, s);
+        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, grid_blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gc
