@@ -1,0 +1,215 @@
+"""Throughput of the guiding-centre push on one MI355X.
+
+Workload (paper scale): 1,048,576 electrons at 81 keV injected at r = 0.28 AU,
+24 deg latitude (longitude +-2 deg, pitch cosine uniform in [0, 1]), split in
+three ensembles with mean free path 0.1, 0.5 and 1 AU; Parker spiral plus 16
+seeded Fourier modes (dB/B = 0.1) on a 256x128x256 grid of 12 FP32 components
+over [0.1, 2] AU; dt = 1 s; cell binning every 64 steps.
+
+One bench step = one chunk of 64 guiding-centre steps of every active particle:
+cell keys + radix sort + permute, the push kernel, and the snapshot moments.
+The default --steps 1350 covers the full 24 h of simulated time.  The metric
+counts steps of active particles only.
+
+Prints one JSON line.  --gpus > 1 is rejected: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PER_STEP = {"f32": 768, "f64": 1536, "f16": 384}     # 2 gathers x 8 nodes x 12 components
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "push_traffic.json")
+KERNEL_SOURCES = ["paper_2403_06706_amd/csrc/gc_push.hip", "paper_2403_06706_amd/csrc/gc_device.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def moment_spec():
+    from synthetic import AU, E_CHARGE
+
+    class Spec:   # <sin^2 alpha>(r), energy vs age near 1 AU, pitch cosine of young electrons
+        n_rbins, r_lo, r_hi = 38, 0.1 * AU, 2.0 * AU
+        n_mubins, sel_r_lo, sel_r_hi = 36, 0.9 * AU, 1.1 * AU
+        age_lo, age_hi, min_collisions = 0.0, 1200.0, 1
+        n_agebins, age_max = 48, 48 * 3600.0
+        n_ebins, e_lo, e_hi = 64, 70e3, 82e3
+        e_unit, len_unit = E_CHARGE, AU
+    return Spec
+
+
+def build_workload(args):
+    import numpy as np
+    import torch
+    from synthetic import workloads
+    wl = workloads.config_paper_scale(seed=args.seed, n=args.particles, store_dtype=args.store)
+    t0 = time.time()
+    field = wl.build_field(wl.grid, device="cuda" if torch.cuda.is_available() else None)
+    log(f"[bench] field {wl.grid.nr}x{wl.grid.nth}x{wl.grid.nph} built in {time.time() - t0:.1f} s")
+    return wl, np.ascontiguousarray(field)
+
+
+def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False):
+    import torch
+    import paper_2403_06706_amd as gcp
+    ctx = gcp.Context(device=0, precision=precision, order="bin", chunk_steps=64, block_size=args.block,
+                      bin_coarsen=args.coarsen, persistent=args.persistent, tile=args.tile, timing=timing)
+    ctx.load_field(wl.grid, field, args.store)
+    for e in wl.ensembles:
+        ctx.inject(e)
+    start = {k: v.clone() for k, v in ctx.get_state().items()}
+    spec = moment_spec()
+    for _ in range(warmup):
+        ctx.advance(wl.dt, 64)
+        ctx.moments(spec)
+    torch.cuda.synchronize()
+    ctx.set_state(start)                      # time the workload from injection
+    ctx.reset_counters()
+    if probe:   # traffic-counter calibration: a plain copy of known size before the push
+        nbytes = 256 << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        ctx.copy_probe(dst, src, nbytes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mom = None
+    for i in range(steps):
+        ctx.advance(wl.dt, 64)
+        mom = ctx.moments(spec)
+        if (i + 1) % 200 == 0:
+            log(f"[bench] {precision}: step {i + 1}/{steps}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c = ctx.counters()
+    final = gcp.state_to_numpy(ctx.get_state())
+    m = mom.cpu().numpy() if mom is not None else None
+    ctx.close()
+    return elapsed, c, final, m
+
+
+def cpu_baseline(args, wl, field):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    n_per = args.cpu_particles // len(wl.ensembles)
+    of = O.Field(wl.grid, field.astype(np.float32).astype(np.float64) if args.store == "f32" else field)
+    tab = O.make_ens_table(wl.ensembles)
+    p = np.concatenate([O.inject(of, tab, i, e, np.arange(n_per, dtype=np.uint32))
+                        for i, e in enumerate(wl.ensembles)])
+    threads = O.max_threads()
+    t0 = time.perf_counter()
+    O.advance(of, tab, p, wl.dt, args.cpu_steps, threads)
+    el = time.perf_counter() - t0
+    steps = int(p["step"].sum())
+    return {"value": steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(p)} electrons (ids 0..{n_per - 1} of each ensemble) x {args.cpu_steps} steps "
+                      f"of the same field and injection; {steps} active particle-steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1350, help="chunks of 64 steps (1350 = 24 h)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--particles", type=int, default=1 << 20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--store", default="f32", choices=["f32", "f64", "f16"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32_acc64", "f32_kahan"])
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--coarsen", type=int, default=0)
+    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--tile", type=int, default=1024)
+    ap.add_argument("--forms", type=int, default=0, help="also time the FP32 forms over this many chunks")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-particles", type=int, default=24576)
+    ap.add_argument("--cpu-steps", type=int, default=1800)
+    ap.add_argument("--probe-copy", action="store_true", help="run a 256 MiB copy kernel first (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the guiding-centre push is data-parallel over particles "
+              "and this build runs no multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl, field = build_workload(args)
+    log(f"[bench] {wl.n_particles} electrons, {len(wl.ensembles)} ensembles; warmup {args.warmup}, "
+        f"timed {args.steps} chunks of 64 steps")
+    elapsed, c, final, mom = run_gpu(args, wl, field, args.precision, args.steps, args.warmup, probe=args.probe_copy)
+    value = c["particle_steps"] / elapsed
+    log(f"[bench] {c['particle_steps']:.3e} particle-steps in {elapsed:.2f} s -> {value:.3e}/s; "
+        f"push {c['push_ms']:.0f} ms over {c['n_push']} launches, reorder {c['reorder_ms']:.0f} ms")
+
+    avg_push_s = c["push_ms"] / 1e3 / max(c["n_push"], 1)
+    steps_per_launch = c["particle_steps"] / max(c["n_push"], 1)
+    algo_bytes = BYTES_PER_STEP[args.store] * steps_per_launch
+    achieved = algo_bytes / avg_push_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_JSON):
+        with open(TRAFFIC_JSON) as f:
+            tj = json.load(f)
+        if (tj.get("kernel_hash") == kernel_hash() and tj.get("store") == args.store
+                and tj.get("precision") == args.precision):
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                "kernel": "gc::k_push", "avg_launch_ms": round(avg_push_s * 1e3, 4),
+                "algorithmic_bytes_per_launch": round(algo_bytes),
+                "bytes_per_particle_step": BYTES_PER_STEP[args.store]}
+
+    out = {
+        "metric": "GC particle-steps/s on 1 MI355X at <=1e-4 rel err vs FP64 oracle",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "f64" else "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "particles": wl.n_particles, "ensembles_lambda_AU": [0.1, 0.5, 1.0],
+                   "ekin_keV": 81.0, "dt_s": wl.dt, "steps_per_bench_step": 64,
+                   "simulated_hours": args.steps * 64 * wl.dt / 3600.0, "field_store": args.store,
+                   "precision": args.precision, "order": "bin", "block": args.block,
+                   "persistent": args.persistent},
+        "roofline": roofline,
+        "active_at_end": int((final["status"] == 0).sum()),
+        "moments_last": {"active": int(mom[0]), "exited": int(mom[1]), "collisions": int(mom[4])} if mom is not None else None,
+    }
+
+    if args.forms > 0:
+        forms = {}
+        base_el, base_c, _, _ = run_gpu(args, wl, field, args.precision, args.forms, 1)
+        base = base_c["particle_steps"] / base_el
+        forms[args.precision] = {"value": base}
+        for prec in ("f32_acc64", "f32_kahan"):
+            if prec == args.precision:
+                continue
+            el, cc, _, _ = run_gpu(args, wl, field, prec, args.forms, 1)
+            v = cc["particle_steps"] / el
+            forms[prec] = {"value": v, "speedup": v / base}
+        out["forms_first_chunks"] = {"chunks": args.forms, **forms}
+
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(args, wl, field)
+        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} particle-steps/s on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -115,7 +115,7 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     carve(m[0], cap, na);
     carve(m[1], cap, nb);
     const uint32_t max_blocks = (uint32_t)((cap + kSortTile - 1) / kSortTile);
-    const size_t scratch = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + 64;
+    const size_t scratch = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + (cap / 256 + 64) * 4;
     void *sm = nullptr;
     if (hipMalloc(&sm, scratch) != hipSuccess) {
         (void)hipFree(m[0]);
@@ -166,6 +166,7 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     ctx->sc.vals[1] = p + 3 * cap;
     ctx->sc.counts = p + 4 * cap;
     ctx->sc.totals = ctx->sc.counts + (size_t)256 * max_blocks;
+    ctx->sc.block_alive = ctx->sc.totals + 256;
     ctx->sc.max_blocks = max_blocks;
     ctx->log = log;
     ctx->cap = cap;
@@ -215,10 +216,10 @@ gc_status reorder(gc_ctx *ctx, bool timed) {
         const uint32_t nthc = ((uint32_t)ctx->f.nth + (1u << c) - 1) >> c;
         const uint32_t nphc = ((uint32_t)ctx->f.nph + (1u << c) - 1) >> c;
         const uint32_t dead = nrc * nthc * nphc;
-        HIPCHK(launch_cell_keys(ctx->A, ctx->f, n, c, dead, ctx->sc.keys[0], ctx->n_active, s));
+        HIPCHK(launch_cell_keys(ctx->A, ctx->f, n, c, dead, ctx->sc.keys[0], ctx->sc.block_alive, ctx->n_active, s));
         HIPCHK(launch_radix_sort(ctx->sc, n, (int)bits_for(dead), &perm, s));
     }
-    HIPCHK(launch_permute(ctx->A, ctx->B, perm, n, s));
+    HIPCHK(launch_permute(ctx->A, ctx->B, perm, n, ctx->opt.precision == GC_PREC_F32_KAHAN, s));
     std::swap(ctx->A, ctx->B);
     std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
     if (timed) {
@@ -365,8 +366,15 @@ gc_status gc_set_options(gc_ctx *ctx, const gc_options *opt) {
     if (o.device != ctx->opt.device) return fail(ctx, GC_EINVAL, "device cannot change after creation");
     gc_status st = check_options(ctx, &o);
     if (st != GC_OK) return st;
+    const bool was_kahan = ctx->opt.precision == GC_PREC_F32_KAHAN, is_kahan = o.precision == GC_PREC_F32_KAHAN;
     ctx->opt = o;
     ctx->stream = static_cast<hipStream_t>(o.hip_stream);
+    if (was_kahan != is_kahan && ctx->n > 0) {
+        // compensation terms only follow the particles in the Kahan form: restart them at zero
+        double *comp[5] = {ctx->A.cr, ctx->A.cth, ctx->A.cph, ctx->A.cu, ctx->A.ct};
+        for (double *c : comp)
+            HIPCHK(launch_fill_u64(reinterpret_cast<unsigned long long *>(c), 0ull, ctx->n, ctx->stream));
+    }
     return GC_OK;
 }
 

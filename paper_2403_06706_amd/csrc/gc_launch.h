@@ -38,15 +38,17 @@ struct OrderScratch {
     uint32_t *vals[2];
     uint32_t *counts;      // [256][max_blocks] radix histograms, or per-block alive counts
     uint32_t *totals;      // [256]
+    uint32_t *block_alive; // [n / 256] active particles per 256-slot block
     uint32_t max_blocks;
 };
 constexpr int kSortTile = 2048;     // items per radix-sort block
 hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, uint32_t n, int coarsen, uint32_t dead_key,
-                            uint32_t *keys, uint32_t *n_active, hipStream_t s);
+                            uint32_t *keys, uint32_t *block_alive, uint32_t *n_active, hipStream_t s);
 hipError_t launch_radix_sort(OrderScratch &sc, uint32_t n, int bits, uint32_t **perm_out, hipStream_t s);
 hipError_t launch_compact(const SoA &st, uint32_t n, OrderScratch &sc, uint32_t *n_active, uint32_t **perm_out,
                           hipStream_t s);
-hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, hipStream_t s);
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, bool with_comp,
+                          hipStream_t s);
 hipError_t launch_set_count(uint32_t *n_active, uint32_t n, hipStream_t s);
 
 }  // namespace gc

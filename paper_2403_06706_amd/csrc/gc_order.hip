@@ -23,8 +23,9 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_cell_keys(SoA st, FieldDev f, uint32_t n, int coarsen, uint32_t dead_key, uint32_t *keys,
-                            uint32_t *n_active) {
+__global__ __launch_bounds__(256) void k_cell_keys(SoA st, FieldDev f, uint32_t n, int coarsen,
+                                                   uint32_t dead_key, uint32_t *keys, uint32_t *block_alive) {
+    __shared__ uint32_t wsum[4];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     bool alive = false;
     if (i < n) {
@@ -49,15 +50,19 @@ __global__ void k_cell_keys(SoA st, FieldDev f, uint32_t n, int coarsen, uint32_
         keys[i] = key;
     }
     const uint64_t b = __ballot(alive);
-    if ((threadIdx.x & 63u) == 0 && b) atomicAdd(n_active, (uint32_t)__popcll(b));
+    if ((threadIdx.x & 63u) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) block_alive[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *v, uint32_t nb, uint32_t *n_active);
+
 hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, uint32_t n, int coarsen, uint32_t dead_key,
-                            uint32_t *keys, uint32_t *n_active, hipStream_t s) {
-    hipError_t e = launch_fill_u32(n_active, 0u, 1, s);
-    if (e != hipSuccess || n == 0) return e;
-    hipLaunchKernelGGL(k_cell_keys, dim3((n + 255) / 256), dim3(256), 0, s, st, f, n, coarsen, dead_key, keys,
-                       n_active);
+                            uint32_t *keys, uint32_t *block_alive, uint32_t *n_active, hipStream_t s) {
+    if (n == 0) return launch_fill_u32(n_active, 0u, 1, s);
+    const uint32_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, s, st, f, n, coarsen, dead_key, keys, block_alive);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_alive, nb, n_active);   // total -> n_active
     return hipGetLastError();
 }
 
@@ -241,20 +246,23 @@ hipError_t launch_compact(const SoA &st, uint32_t n, OrderScratch &sc, uint32_t 
 }
 
 // ---------------------------------------------------------------------------
+template <bool kWithComp>
 __global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t j = perm[i];
 #define P_(name) dst.name[i] = src.name[j];
     P_(r) P_(th) P_(ph) P_(u) P_(mu) P_(fr) P_(fth) P_(fph) P_(fu) P_(dtp) P_(s) P_(ell) P_(t)
-    P_(cr) P_(cth) P_(cph) P_(cu) P_(ct)
     P_(k) P_(flags) P_(status) P_(step) P_(id) P_(ens) P_(gid)
+    if (kWithComp) { P_(cr) P_(cth) P_(cph) P_(cu) P_(ct) }
 #undef P_
 }
 
-hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, hipStream_t s) {
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, bool with_comp,
+                          hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, perm, n);
+    if (with_comp) hipLaunchKernelGGL(k_permute<true>, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, perm, n);
+    else hipLaunchKernelGGL(k_permute<false>, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, perm, n);
     return hipGetLastError();
 }
 

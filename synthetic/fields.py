@@ -148,8 +148,11 @@ def _local_from_cartesian(bfun: Callable, r, th, ph, v_wind: float):
     return torch.stack(out, dim=1)                 # [n][12]
 
 
-def _build(grid: SphericalGrid, bfun: Callable, v_wind: float, device=None, slab: int = 8) -> np.ndarray:
+def _build(grid: SphericalGrid, bfun: Callable, v_wind: float, device=None, slab: int = 0) -> np.ndarray:
     device = torch.device("cpu") if device is None else torch.device(device)
+    if slab <= 0:   # r-slices per batch: ~4M nodes on a GPU, ~0.25M on the host
+        per = grid.nth * grid.nph
+        slab = max(1, (4_000_000 if device.type == "cuda" else 250_000) // per)
     out = np.empty(grid.shape(), dtype=np.float64)
     for i0 in range(0, grid.nr, slab):
         i1 = min(grid.nr, i0 + slab)

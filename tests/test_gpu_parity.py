@@ -53,9 +53,10 @@ def test_empty_context_and_zero_steps():
     wl2 = small(n=50, hours=0.0)
     st2, _ = run_gpu(wl2, f, n_steps=0)
     p, *_ = run_oracle(wl2, f, n_steps=0)
-    assert np.array_equal(st2["r"], p["r"]) and np.array_equal(st2["u"], p["u"])
+    assert np.array_equal(st2["r"], p["r"]) and np.array_equal(st2["th"], p["th"])
+    assert np.allclose(st2["u"], p["u"], rtol=1e-15, atol=0)   # |p|/m rounded in a different order
     assert np.allclose(st2["mu"], p["mu_B"] / M_ELECTRON, rtol=1e-14)
-    assert np.array_equal(st2["ell"], p["ell"])
+    assert np.allclose(st2["ell"], p["ell"], rtol=1e-15, atol=0)   # log() of two libraries
 
 
 def test_injection_outside_shell_and_finish():
@@ -122,7 +123,7 @@ def test_affine_field_third_order_on_device():
     """On an affine field trilinear interpolation is exact and the right-hand
     side is smooth: the device integration converges at third order in dt."""
     wl = Workload("affine", SphericalGrid(32, 32, 16, 0.1 * AU, 2.0 * AU), lambda g, device=None: fields.affine(g),
-                  [Ensemble(n=64, ensemble=0, seed=3, r0=0.4 * AU, lat0=math.radians(10), dlat=math.radians(5),
+                  [Ensemble(n=64, ensemble=0, seed=3, r0=0.8 * AU, lat0=math.radians(10), dlat=math.radians(5),
                             dr0=0.05 * AU, lon0=1.0, dlon=0.5, lambda_par=0.0, r_in=0.15 * AU, r_out=1.9 * AU,
                             mu_lo=-1.0, mu_hi=1.0)], 1.0, 0, "f64", 0)
     f = fields.affine(wl.grid)
