@@ -75,11 +75,11 @@ typedef struct {
     int32_t order;          /* GC_ORDER_* */
     int32_t chunk_steps;    /* steps per push launch (and per reorder); > 0 */
     int32_t bin_coarsen;    /* cells per bin along each axis = 2^bin_coarsen (GC_ORDER_BIN) */
-    int32_t block_size;     /* push workgroup size: 64, 128, 256, 512 or 1024 */
+    int32_t block_size;     /* push workgroup size: 64, 128 or 256 */
     int32_t persistent;     /* 1: persistent push with a tile work queue */
     int32_t tile;           /* particles per work-queue tile (persistent mode, multiple of block_size) */
     int32_t log_depth;      /* per particle, record the step of the first log_depth collisions (0: off) */
-    int32_t timing;         /* 1: record HIP events around each push launch (see gc_timing) */
+    int32_t timing;         /* 1: record HIP events around each push launch (see gc_get_counters) */
 } gc_options;
 
 /* Fill *opt with the defaults (FP64, binning every 64 steps, 256 threads). */
@@ -242,6 +242,35 @@ typedef struct {
 } gc_counters;
 gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out);
 gc_status gc_reset_counters(gc_ctx *ctx);
+
+/* ------------------------------------------------------------ autotuner */
+/* Choose launch parameters by timing the context's own workload: coordinate
+ * descent over workgroup size, then bin coarsening, then steps per chunk,
+ * then the persistent form and its tile size.  Each candidate starts from the
+ * same saved state and runs probe_steps steps of size dt, timed with HIP
+ * events; the state is restored afterwards, so the particles do not advance.
+ * Candidate lists with n_* = 0 keep the current value.  The best options are
+ * applied to the context and returned with their rate (active particle-steps
+ * per second).  Waits for the stream.  Errors: GC_ESTATE without field or
+ * particles; GC_EINVAL for probe_steps < 1 or invalid candidates. */
+typedef struct {
+    int32_t n_block;   int32_t block[3];
+    int32_t n_coarsen; int32_t coarsen[4];
+    int32_t n_chunk;   int32_t chunk[6];
+    int32_t n_tile;    int32_t tile[4];     /* persistent-form tiles (0 candidates: grid form only) */
+    int64_t probe_steps;
+    double dt;
+} gc_tune_space;
+
+typedef struct {
+    gc_options best;
+    double best_rate;        /* particle-steps/s of the best candidate */
+    double default_rate;     /* ... of the options the context had on entry */
+    int32_t n_tried;
+    int32_t pad;
+} gc_tune_result;
+
+gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *space, gc_tune_result *out);
 
 /* Copy n_bytes from src to dst (both device) with a plain streaming kernel;
  * used to calibrate hardware traffic counters against a known byte count. */

@@ -95,9 +95,9 @@ class Context:
         o = _abi.gc_options()
         self._check(lib.gc_get_options(self._h, C.byref(o)))
         for k, v in kw.items():
-            if k == "precision":
+            if k == "precision" and isinstance(v, str):
                 v = _PRECS[v]
-            elif k == "order":
+            elif k == "order" and isinstance(v, str):
                 v = _ORDERS[v]
             elif k == "stream":
                 self._stream = v
@@ -189,6 +189,51 @@ class Context:
 
     def reset_counters(self):
         self._check(lib.gc_reset_counters(self._h))
+
+    def options(self) -> dict:
+        o = _abi.gc_options()
+        self._check(lib.gc_get_options(self._h, C.byref(o)))
+        return {"precision": o.precision, "order": o.order, "chunk_steps": o.chunk_steps,
+                "bin_coarsen": o.bin_coarsen, "block_size": o.block_size, "persistent": o.persistent,
+                "tile": o.tile}
+
+    def autotune(self, dt: float, probe_steps: int = 128, blocks=(64, 128, 256), coarsen=(0, 1, 2),
+                 chunks=(), tiles=(256, 1024, 4096), cache: Optional[str] = None, key: Optional[str] = None) -> dict:
+        """Time candidate launch parameters on this context's particles (see
+        gc_autotune) and apply the best.  With cache and key, a stored choice is
+        applied without timing, and a new choice is stored."""
+        import json
+        import os
+        if cache and key and os.path.exists(cache):
+            with open(cache) as f:
+                stored_all = json.load(f)
+            if key in stored_all:
+                chosen = stored_all[key]
+                self.set_options(**{k: v for k, v in chosen["options"].items() if k != "precision"})
+                return dict(chosen, cached=True)
+        sp = _abi.gc_tune_space()
+        for name, vals, cap in (("block", blocks, 3), ("coarsen", coarsen, 4), ("chunk", chunks, 6), ("tile", tiles, 4)):
+            vals = list(vals)[:cap]
+            setattr(sp, "n_" + name, len(vals))
+            arr = getattr(sp, name)
+            for i, v in enumerate(vals):
+                arr[i] = int(v)
+        sp.probe_steps = int(probe_steps)
+        sp.dt = float(dt)
+        res = _abi.gc_tune_result()
+        self._check(lib.gc_autotune(self._h, C.byref(sp), C.byref(res)))
+        out = {"options": self.options(), "best_rate": res.best_rate, "default_rate": res.default_rate,
+               "n_tried": res.n_tried, "cached": False}
+        if cache and key:
+            stored_all = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    stored_all = json.load(f)
+            stored_all[key] = {k: out[k] for k in ("options", "best_rate", "default_rate", "n_tried")}
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(stored_all, f, indent=1)
+        return out
 
     def copy_probe(self, dst, src, n_bytes: int):
         self._check(lib.gc_copy_probe(self._h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(n_bytes)))

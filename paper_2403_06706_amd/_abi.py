@@ -58,6 +58,17 @@ class gc_counters(C.Structure):
                 ("n_reorder", C.c_int64), ("particle_steps", C.c_uint64)]
 
 
+class gc_tune_space(C.Structure):
+    _fields_ = [("n_block", C.c_int32), ("block", C.c_int32 * 3), ("n_coarsen", C.c_int32), ("coarsen", C.c_int32 * 4),
+                ("n_chunk", C.c_int32), ("chunk", C.c_int32 * 6), ("n_tile", C.c_int32), ("tile", C.c_int32 * 4),
+                ("probe_steps", C.c_int64), ("dt", C.c_double)]
+
+
+class gc_tune_result(C.Structure):
+    _fields_ = [("best", gc_options), ("best_rate", C.c_double), ("default_rate", C.c_double),
+                ("n_tried", C.c_int32), ("pad", C.c_int32)]
+
+
 def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -88,6 +99,7 @@ def load():
         "gc_get_counters": (S, [P, C.POINTER(gc_counters)]),
         "gc_reset_counters": (S, [P]),
         "gc_copy_probe": (S, [P, P, P, C.c_uint64]),
+        "gc_autotune": (S, [P, C.POINTER(gc_tune_space), C.POINTER(gc_tune_result)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -100,5 +112,5 @@ DECLARED = (
     "gc_default_options", "gc_create", "gc_destroy", "gc_last_error", "gc_set_options", "gc_get_options",
     "gc_load_field", "gc_inject", "gc_advance", "gc_advance_graph", "gc_moments_size", "gc_moments",
     "gc_count", "gc_get_state", "gc_set_state", "gc_get_log", "gc_get_counters", "gc_reset_counters",
-    "gc_copy_probe",
+    "gc_copy_probe", "gc_autotune",
 )

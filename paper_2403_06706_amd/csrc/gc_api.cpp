@@ -44,6 +44,8 @@ struct gc_ctx {
     void *scratch_mem = nullptr;
     uint32_t *n_active = nullptr;
     uint32_t *queue = nullptr;
+    uint32_t *n_bound = nullptr;      // live prefix: slots at or past it hold no active particle
+    bool bound_dirty = true;          // the bound must be reset to n before the next reorder
     unsigned long long *steps = nullptr;
     uint32_t *log = nullptr;
     // timing
@@ -170,6 +172,7 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     ctx->sc.max_blocks = max_blocks;
     ctx->log = log;
     ctx->cap = cap;
+    ctx->bound_dirty = true;
     if (ctx->gexec) {
         (void)hipGraphExecDestroy(ctx->gexec);
         ctx->gexec = nullptr;
@@ -199,6 +202,7 @@ gc_status reorder(gc_ctx *ctx, bool timed) {
     const uint32_t n = (uint32_t)ctx->n;
     if (ctx->opt.order == GC_ORDER_NONE) {
         HIPCHK(launch_set_count(ctx->n_active, n, s));
+        ctx->bound_dirty = true;    // active particles may sit anywhere until the next reorder
         return GC_OK;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -207,19 +211,28 @@ gc_status reorder(gc_ctx *ctx, bool timed) {
         e1 = take_event(ctx);
         HIPCHK(hipEventRecord(e0, s));
     }
+    if (ctx->bound_dirty) {
+        HIPCHK(launch_set_count(ctx->n_bound, n, s));
+        ctx->bound_dirty = false;
+    }
+    const bool comp = ctx->opt.precision == GC_PREC_F32_KAHAN;
     uint32_t *perm = nullptr;
     if (ctx->opt.order == GC_ORDER_COMPACT) {
-        HIPCHK(launch_compact(ctx->A, n, ctx->sc, ctx->n_active, &perm, s));
+        HIPCHK(launch_compact(ctx->A, ctx->n_bound, n, ctx->sc, ctx->n_active, &perm, s));
     } else {
         const int c = ctx->opt.bin_coarsen;
         const uint32_t nrc = ((uint32_t)ctx->f.nr + (1u << c) - 1) >> c;
         const uint32_t nthc = ((uint32_t)ctx->f.nth + (1u << c) - 1) >> c;
         const uint32_t nphc = ((uint32_t)ctx->f.nph + (1u << c) - 1) >> c;
         const uint32_t dead = nrc * nthc * nphc;
-        HIPCHK(launch_cell_keys(ctx->A, ctx->f, n, c, dead, ctx->sc.keys[0], ctx->sc.block_alive, ctx->n_active, s));
-        HIPCHK(launch_radix_sort(ctx->sc, n, (int)bits_for(dead), &perm, s));
+        HIPCHK(launch_cell_keys(ctx->A, ctx->f, ctx->n_bound, n, c, dead, ctx->sc.keys[0], ctx->sc.block_alive,
+                                ctx->n_active, s));
+        HIPCHK(launch_radix_sort(ctx->sc, ctx->n_bound, n, (int)bits_for(dead), &perm, s));
     }
-    HIPCHK(launch_permute(ctx->A, ctx->B, perm, n, ctx->opt.precision == GC_PREC_F32_KAHAN, s));
+    HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
+    // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
+    HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, s));
+    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, s));
     std::swap(ctx->A, ctx->B);
     std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
     if (timed) {
@@ -330,8 +343,9 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     HIPCHK(hipMalloc(&small, 256));
     ctx->n_active = static_cast<uint32_t *>(small);
     ctx->queue = ctx->n_active + 1;
+    ctx->n_bound = ctx->n_active + 2;
     ctx->steps = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 64);
-    HIPCHK(launch_fill_u32(ctx->n_active, 0u, 2, ctx->stream));
+    HIPCHK(launch_fill_u32(ctx->n_active, 0u, 3, ctx->stream));
     HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return GC_OK;
@@ -367,6 +381,7 @@ gc_status gc_set_options(gc_ctx *ctx, const gc_options *opt) {
     gc_status st = check_options(ctx, &o);
     if (st != GC_OK) return st;
     const bool was_kahan = ctx->opt.precision == GC_PREC_F32_KAHAN, is_kahan = o.precision == GC_PREC_F32_KAHAN;
+    if (o.order != ctx->opt.order || was_kahan != is_kahan) ctx->bound_dirty = true;
     ctx->opt = o;
     ctx->stream = static_cast<hipStream_t>(o.hip_stream);
     if (was_kahan != is_kahan && ctx->n > 0) {
@@ -492,6 +507,7 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
     HIPCHK(launch_inject(ctx->A, ctx->f, e, ip, (uint32_t)ctx->n, (uint32_t)d->n, d->first_id, d->ensemble,
                          ctx->stream));
     ctx->n += d->n;
+    ctx->bound_dirty = true;
     return GC_OK;
 }
 
@@ -610,6 +626,7 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
     if (st != GC_OK) return st;
     HIPCHK(launch_state_in(ctx->A, *src, (uint32_t)n, ctx->stream));
     ctx->n = n;
+    ctx->bound_dirty = true;
     if (ctx->gexec) {
         (void)hipGraphExecDestroy(ctx->gexec);
         ctx->gexec = nullptr;
@@ -664,6 +681,135 @@ gc_status gc_reset_counters(gc_ctx *ctx) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return GC_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// Device copy of the whole state in global order, for the autotuner.
+struct Snapshot {
+    void *mem = nullptr;
+    gc_state_view v{};
+    uint64_t n = 0;
+    ~Snapshot() {
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+gc_status take_snapshot(gc_ctx *ctx, Snapshot &sn) {
+    sn.n = ctx->n;
+    const size_t bytes = (size_t)sn.n * (kNumDoubleArrays * 8 + 6 * 4) + 64;
+    if (hipMalloc(&sn.mem, bytes) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate tuning snapshot");
+    double *d = static_cast<double *>(sn.mem);
+    double **dp[kNumDoubleArrays] = {&sn.v.r, &sn.v.th, &sn.v.ph, &sn.v.u, &sn.v.mu, &sn.v.fr, &sn.v.fth, &sn.v.fph,
+                                     &sn.v.fu, &sn.v.dtp, &sn.v.s, &sn.v.ell, &sn.v.t, &sn.v.cr, &sn.v.cth, &sn.v.cph,
+                                     &sn.v.cu, &sn.v.ct};
+    for (int i = 0; i < kNumDoubleArrays; ++i) *dp[i] = d + (size_t)i * sn.n;
+    uint32_t *u = reinterpret_cast<uint32_t *>(d + (size_t)kNumDoubleArrays * sn.n);
+    uint32_t **up[6] = {&sn.v.k, &sn.v.flags, &sn.v.status, &sn.v.step, &sn.v.id, &sn.v.ens};
+    for (int i = 0; i < 6; ++i) *up[i] = u + (size_t)i * sn.n;
+    return gc_get_state(ctx, &sn.v);
+}
+
+// Rate of one candidate: restore, advance probe_steps, time with events.
+gc_status time_candidate(gc_ctx *ctx, const Snapshot &sn, const gc_options &o, double dt, int64_t steps,
+                         double *rate) {
+    gc_status st = gc_set_options(ctx, &o);
+    if (st != GC_OK) return st;
+    st = gc_set_state(ctx, &sn.v, sn.n);
+    if (st != GC_OK) return st;
+    hipStream_t s = ctx->stream;
+    HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, s));
+    hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
+    HIPCHK(hipEventRecord(e0, s));
+    st = enqueue_advance(ctx, dt, steps, false);
+    if (st != GC_OK) return st;
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    ctx->ev_pool.push_back(e0);
+    ctx->ev_pool.push_back(e1);
+    unsigned long long done = 0;
+    HIPCHK(hipMemcpy(&done, ctx->steps, sizeof done, hipMemcpyDeviceToHost));
+    *rate = ms > 0 ? (double)done / (ms * 1e-3) : 0.0;
+    return GC_OK;
+}
+
+}  // namespace
+
+gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *sp, gc_tune_result *out) {
+    if (!ctx || !sp || !out) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_autotune before gc_load_field");
+    if (ctx->n == 0) return fail(ctx, GC_ESTATE, "gc_autotune needs particles");
+    if (sp->probe_steps < 1) return fail(ctx, GC_EINVAL, "probe_steps must be >= 1");
+    if (!(std::isfinite(sp->dt) && sp->dt > 0.0)) return fail(ctx, GC_EINVAL, "dt must be finite and > 0");
+    if (sp->n_block < 0 || sp->n_block > 3 || sp->n_coarsen < 0 || sp->n_coarsen > 4 || sp->n_chunk < 0 ||
+        sp->n_chunk > 6 || sp->n_tile < 0 || sp->n_tile > 4)
+        return fail(ctx, GC_EINVAL, "too many candidates");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    Snapshot sn;
+    gc_status st = take_snapshot(ctx, sn);
+    if (st != GC_OK) return st;
+    const gc_options entry = ctx->opt;
+    unsigned long long counter_saved = 0;
+    HIPCHK(hipMemcpy(&counter_saved, ctx->steps, sizeof counter_saved, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    gc_options best = entry;
+    best.timing = 0;
+    double best_rate = 0;
+    st = time_candidate(ctx, sn, best, sp->dt, sp->probe_steps, &best_rate);
+    if (st != GC_OK) return st;
+    out->default_rate = best_rate;
+    out->n_tried = 1;
+    auto consider = [&](gc_options cand) -> gc_status {
+        double r = 0;
+        gc_status s2 = time_candidate(ctx, sn, cand, sp->dt, sp->probe_steps, &r);
+        if (s2 != GC_OK) return s2;
+        out->n_tried += 1;
+        if (r > best_rate) {
+            best_rate = r;
+            best = cand;
+        }
+        return GC_OK;
+    };
+    for (int i = 0; i < sp->n_block; ++i) {
+        gc_options c = best;
+        c.block_size = sp->block[i];
+        c.persistent = 0;
+        if (c.block_size != best.block_size && (st = consider(c)) != GC_OK) return st;
+    }
+    for (int i = 0; i < sp->n_coarsen; ++i) {
+        gc_options c = best;
+        c.bin_coarsen = sp->coarsen[i];
+        if (c.bin_coarsen != best.bin_coarsen && (st = consider(c)) != GC_OK) return st;
+    }
+    for (int i = 0; i < sp->n_chunk; ++i) {
+        gc_options c = best;
+        c.chunk_steps = sp->chunk[i];
+        if (c.chunk_steps != best.chunk_steps && (st = consider(c)) != GC_OK) return st;
+    }
+    for (int i = 0; i < sp->n_tile; ++i) {
+        gc_options c = best;
+        c.persistent = 1;
+        c.tile = (sp->tile[i] + c.block_size - 1) / c.block_size * c.block_size;
+        if ((st = consider(c)) != GC_OK) return st;
+    }
+    // apply the winner, restore the particles and the step counter
+    best.timing = entry.timing;
+    best.hip_stream = entry.hip_stream;
+    st = gc_set_options(ctx, &best);
+    if (st != GC_OK) return st;
+    st = gc_set_state(ctx, &sn.v, sn.n);
+    if (st != GC_OK) return st;
+    HIPCHK(hipMemcpyAsync(ctx->steps, &counter_saved, sizeof counter_saved, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    out->best = best;
+    out->best_rate = best_rate;
+    return GC_OK;
+}
+
+extern "C" {
 
 gc_status gc_copy_probe(gc_ctx *ctx, void *dst, const void *src, uint64_t n_bytes) {
     if (!ctx || !dst || !src) return GC_EINVAL;

@@ -116,7 +116,7 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
     const uint32_t row = (uint32_t)(f.nph + 1) * 12u;
     const uint32_t o00 = (i * (uint32_t)f.nth + j) * row + k * 12u;
     const uint32_t dI = (uint32_t)f.nth * row;
-    // sum over the four (r, theta) corners of w_ab * (phi-lerp of the node pair)
+    // sum over the eight corners: (r, theta) weight of the node pair times (1 - w_ph) or w_ph
     const R w[4] = {((R)1 - wr) * ((R)1 - wt), ((R)1 - wr) * wt, wr * ((R)1 - wt), wr * wt};
     const uint32_t off[4] = {o00, o00 + row, o00 + dI, o00 + dI + row};
 #pragma unroll
@@ -125,17 +125,75 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
     for (int q = 0; q < 4; ++q) {
         Pair<FDT> p;
         p.load(f.data, off[q]);
+        const R wa = w[q] * ((R)1 - wp), wb = w[q] * wp;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            const R a = (R)p.get(c, f), b = (R)p.get(c + 12, f);
-            out[c] = fma(w[q], fma(wp, b - a, a), out[c]);
-        }
+        for (int c = 0; c < 12; ++c) out[c] = fma(wb, (R)p.get(c + 12, f), fma(wa, (R)p.get(c, f), out[c]));
         if (q & 1) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
     }
     R sum = (R)0;
 #pragma unroll
     for (int c = 0; c < 12; ++c) sum += out[c];
     return isfinite(sum);
+}
+
+// ---------------------------------------------------------------------------
+// Reciprocal, inverse square root and sine for the right-hand side.
+// Hardware estimates refined by Newton steps (two in double, one in float:
+// each step doubles the correct bits), faithful to about one ulp for the
+// normal, finite arguments met here.  sin on [0, pi] (theta of a particle
+// inside the grid) folds to [0, pi/4] and sums the Taylor series of sin or
+// cos up to the z^17 / z^16 term (truncation below 1e-19).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx, y * y, 1.5);
+    return y * fma(-hx, y * y, 1.5);
+}
+__device__ __forceinline__ float rsqrt_nr(float x) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    return y * fmaf(-0.5f * x, y * y, 1.5f);
+}
+
+template <typename R>
+__device__ __forceinline__ R sin_0_pi(R x) {
+    const R half_pi = (R)1.5707963267948966, pi = (R)3.141592653589793, quarter_pi = (R)0.7853981633974483;
+    const R y = x > half_pi ? pi - x : x;            // sin(x) = sin(pi - x)
+    const bool use_cos = y > quarter_pi;
+    const R z = use_cos ? half_pi - y : y;           // sin(y) = cos(pi/2 - y)
+    const R z2 = z * z;
+    // sin z = z (1 - z^2/3! + z^4/5! - ... + z^16/17!)
+    R ps = (R)(1.0 / 355687428096000.0);
+    ps = fma(ps, -z2, (R)(1.0 / 1307674368000.0));
+    ps = fma(ps, -z2, (R)(1.0 / 6227020800.0));
+    ps = fma(ps, -z2, (R)(1.0 / 39916800.0));
+    ps = fma(ps, -z2, (R)(1.0 / 362880.0));
+    ps = fma(ps, -z2, (R)(1.0 / 5040.0));
+    ps = fma(ps, -z2, (R)(1.0 / 120.0));
+    ps = fma(ps, -z2, (R)(1.0 / 6.0));
+    ps = fma(ps, -z2, (R)1);
+    // cos z = 1 - z^2/2! + z^4/4! - ... + z^16/16!
+    R pc = (R)(1.0 / 20922789888000.0);
+    pc = fma(pc, -z2, (R)(1.0 / 87178291200.0));
+    pc = fma(pc, -z2, (R)(1.0 / 479001600.0));
+    pc = fma(pc, -z2, (R)(1.0 / 3628800.0));
+    pc = fma(pc, -z2, (R)(1.0 / 40320.0));
+    pc = fma(pc, -z2, (R)(1.0 / 720.0));
+    pc = fma(pc, -z2, (R)(1.0 / 24.0));
+    pc = fma(pc, -z2, (R)0.5);
+    pc = fma(pc, -z2, (R)1);
+    return use_cos ? pc : z * ps;
 }
 
 // ---------------------------------------------------------------------------
@@ -155,11 +213,13 @@ __device__ __forceinline__ void gc_rhs(R r, R th, R u, R mu, R qm, R iqm, bool d
     const R Ex = g[3], Ey = g[4], Ez = g[5];
     const R Gx = g[6], Gy = g[7], Gz = g[8];
     const R Kx = g[9], Ky = g[10], Kz = g[11];
-    const R B = sqrt(Bx * Bx + By * By + Bz * Bz);
-    const R iB = (R)1 / B;
+    const R B2 = Bx * Bx + By * By + Bz * Bz;
+    const R iB = rsqrt_nr(B2);
+    const R B = B2 * iB;
     const R bx = Bx * iB, by = By * iB, bz = Bz * iB;
-    const R gamma = sqrt((R)1 + (u * u + (R)2 * mu * B) * (R)kInvC2);
-    const R ig = (R)1 / gamma;
+    const R g2 = (R)1 + (u * u + (R)2 * mu * B) * (R)kInvC2;
+    const R ig = rsqrt_nr(g2);
+    const R gamma = g2 * ig;
     vpar = u * ig;
     const R Epar = Ex * bx + Ey * by + Ez * bz;
     const R vEx = (Ey * bz - Ez * by) * iB;
@@ -183,10 +243,10 @@ __device__ __forceinline__ void gc_rhs(R r, R th, R u, R mu, R qm, R iqm, bool d
         Vz = vpar * bz + vEz + pref * (bx * ay - by * ax);
         udot = qm * Epar - mu * ig * bG + gamma * vpar * (vEx * Kx + vEy * Ky + vEz * Kz);
     }
-    const R ir = (R)1 / r;
+    const R ir = rcp_nr(r);
     F[0] = Vx;
     F[1] = Vy * ir;
-    F[2] = Vz * ir / sin(th);
+    F[2] = Vz * ir * rcp_nr(sin_0_pi(th));
     F[3] = udot;
 }
 

@@ -88,6 +88,11 @@ __device__ __forceinline__ unsigned long long fixp(double x, double scale) {
     return (unsigned long long)(long long)floor(x * scale);
 }
 
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 template <int FDT>
 __global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, MomDev m, unsigned long long *out) {
     extern __shared__ unsigned long long h[];
@@ -96,16 +101,18 @@ __global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, Mom
     unsigned long long *rb = h + 8;
     unsigned long long *mh = rb + 3 * m.n_rbins;
     unsigned long long *eh = mh + m.n_mubins;
+    // the eight scalar moments are summed in registers, then once per wavefront
+    unsigned long long acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const uint32_t status = st.status[i];
-        if (status <= GC_NONFINITE) atomicAdd(&h[status], 1ull);
-        atomicAdd(&h[4], (unsigned long long)st.k[i]);
-        atomicAdd(&h[5], (unsigned long long)st.step[i]);
+        if (status <= GC_NONFINITE) acc[status] += 1;
+        acc[4] += st.k[i];
+        acc[5] += st.step[i];
         if (status != GC_ACTIVE) continue;
         const double r = st.r[i], th = st.th[i], ph = st.ph[i], u = st.u[i], mu = st.mu[i], t = st.t[i];
         const uint32_t k = st.k[i];
-        atomicAdd(&h[6], fixp(r / m.len_unit, 4294967296.0));
-        if (k >= 1) atomicAdd(&h[7], 1ull);
+        acc[6] += fixp(r / m.len_unit, 4294967296.0);
+        if (k >= 1) acc[7] += 1;
         double g[12];
         if (!gather<FDT, double>(f, r, th, ph, g)) continue;
         const double B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -137,6 +144,11 @@ __global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, Mom
             if (xa >= 0.0 && xa < (double)m.n_agebins && xe >= 0.0 && xe < (double)m.n_ebins)
                 atomicAdd(&eh[(int)floor(xa) * m.n_ebins + (int)floor(xe)], 1ull);
         }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const unsigned long long v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63u) == 0 && v) atomicAdd(&h[q], v);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < m.total; i += blockDim.x)

@@ -42,13 +42,20 @@ struct OrderScratch {
     uint32_t max_blocks;
 };
 constexpr int kSortTile = 2048;     // items per radix-sort block
-hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, uint32_t n, int coarsen, uint32_t dead_key,
-                            uint32_t *keys, uint32_t *block_alive, uint32_t *n_active, hipStream_t s);
-hipError_t launch_radix_sort(OrderScratch &sc, uint32_t n, int bits, uint32_t **perm_out, hipStream_t s);
-hipError_t launch_compact(const SoA &st, uint32_t n, OrderScratch &sc, uint32_t *n_active, uint32_t **perm_out,
-                          hipStream_t s);
-hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, bool with_comp,
-                          hipStream_t s);
+// Reorder kernels act on the live prefix [0, *np) of the slots (np in device
+// memory); n_max (host) is an upper bound used to size the grids.
+hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, const uint32_t *np, uint32_t n_max, int coarsen,
+                            uint32_t dead_key, uint32_t *keys, uint32_t *block_alive, uint32_t *n_active,
+                            hipStream_t s);
+hipError_t launch_radix_sort(OrderScratch &sc, const uint32_t *np, uint32_t n_max, int bits, uint32_t **perm_out,
+                             hipStream_t s);
+hipError_t launch_compact(const SoA &st, const uint32_t *np, uint32_t n_max, OrderScratch &sc, uint32_t *n_active,
+                          uint32_t **perm_out, hipStream_t s);
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *np, uint32_t n_max,
+                          bool with_comp, hipStream_t s);
+hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,
+                             bool with_comp, hipStream_t s);
+hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, hipStream_t s);
 hipError_t launch_set_count(uint32_t *n_active, uint32_t n, hipStream_t s);
 
 }  // namespace gc

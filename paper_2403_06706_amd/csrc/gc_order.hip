@@ -23,9 +23,10 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cell_keys(SoA st, FieldDev f, uint32_t n, int coarsen,
+__global__ __launch_bounds__(256) void k_cell_keys(SoA st, FieldDev f, const uint32_t *np, int coarsen,
                                                    uint32_t dead_key, uint32_t *keys, uint32_t *block_alive) {
     __shared__ uint32_t wsum[4];
+    const uint32_t n = *np;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     bool alive = false;
     if (i < n) {
@@ -57,11 +58,12 @@ __global__ __launch_bounds__(256) void k_cell_keys(SoA st, FieldDev f, uint32_t 
 
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *v, uint32_t nb, uint32_t *n_active);
 
-hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, uint32_t n, int coarsen, uint32_t dead_key,
-                            uint32_t *keys, uint32_t *block_alive, uint32_t *n_active, hipStream_t s) {
-    if (n == 0) return launch_fill_u32(n_active, 0u, 1, s);
-    const uint32_t nb = (n + 255) / 256;
-    hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, s, st, f, n, coarsen, dead_key, keys, block_alive);
+hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, const uint32_t *np, uint32_t n_max, int coarsen,
+                            uint32_t dead_key, uint32_t *keys, uint32_t *block_alive, uint32_t *n_active,
+                            hipStream_t s) {
+    if (n_max == 0) return launch_fill_u32(n_active, 0u, 1, s);
+    const uint32_t nb = (n_max + 255) / 256;
+    hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, s, st, f, np, coarsen, dead_key, keys, block_alive);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_alive, nb, n_active);   // total -> n_active
     return hipGetLastError();
 }
@@ -71,9 +73,10 @@ hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, uint32_t n, int co
 // digit across blocks, stable scatter with per-wavefront ranking by ballots.
 // counts layout: [digit][block].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t *keys, uint32_t n, int shift,
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t *keys, const uint32_t *np, int shift,
                                                        uint32_t *counts, uint32_t nblocks) {
     __shared__ uint32_t h[256];
+    const uint32_t n = *np;
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * kSortTile;
@@ -109,9 +112,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t *counts, 
 }
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
-                                                          uint32_t *keys_out, uint32_t *vals_out, uint32_t n,
-                                                          int shift, const uint32_t *counts, const uint32_t *totals,
-                                                          uint32_t nblocks) {
+                                                          uint32_t *keys_out, uint32_t *vals_out,
+                                                          const uint32_t *np, int shift, const uint32_t *counts,
+                                                          const uint32_t *totals, uint32_t nblocks) {
+    const uint32_t n = *np;
+    if (blockIdx.x * kSortTile >= n) return;   // no slot of this tile is live
     __shared__ uint32_t base[256];          // running output offset per digit for this block
     __shared__ uint32_t wcnt[kWaves][256];  // per-wave digit counts, then per-wave offsets
     __shared__ uint32_t tot[256];
@@ -160,17 +165,18 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t *keys_
     }
 }
 
-hipError_t launch_radix_sort(OrderScratch &sc, uint32_t n, int bits, uint32_t **perm_out, hipStream_t s) {
-    const uint32_t nblocks = (n + kSortTile - 1) / kSortTile;
+hipError_t launch_radix_sort(OrderScratch &sc, const uint32_t *np, uint32_t n_max, int bits, uint32_t **perm_out,
+                             hipStream_t s) {
+    const uint32_t nblocks = (n_max + kSortTile - 1) / kSortTile;
     if (nblocks > sc.max_blocks) return hipErrorInvalidValue;
     int cur = 0;
     const uint32_t *vals_in = nullptr;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kRsThreads), 0, s, sc.keys[cur], n, shift, sc.counts,
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kRsThreads), 0, s, sc.keys[cur], np, shift, sc.counts,
                            nblocks);
         hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(kRsThreads), 0, s, sc.counts, nblocks, sc.totals);
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kRsThreads), 0, s, sc.keys[cur], vals_in,
-                           sc.keys[cur ^ 1], sc.vals[cur ^ 1], n, shift, sc.counts, sc.totals, nblocks);
+                           sc.keys[cur ^ 1], sc.vals[cur ^ 1], np, shift, sc.counts, sc.totals, nblocks);
         vals_in = sc.vals[cur ^ 1];
         cur ^= 1;
     }
@@ -181,8 +187,10 @@ hipError_t launch_radix_sort(OrderScratch &sc, uint32_t n, int bits, uint32_t **
 // ---------------------------------------------------------------------------
 // Compaction: stable partition (active first) from wavefront ballots.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_compact_count(const uint32_t *status, uint32_t n, uint32_t *block_alive) {
+__global__ __launch_bounds__(256) void k_compact_count(const uint32_t *status, const uint32_t *np,
+                                                       uint32_t *block_alive) {
     __shared__ uint32_t wsum[4];
+    const uint32_t n = *np;
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     const bool alive = i < n && status[i] == GC_ACTIVE;
     const uint64_t b = __ballot(alive);
@@ -213,10 +221,11 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *v, uint32_t nb, 
     if (threadIdx.x == 0) *n_active = carry;
 }
 
-__global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t *status, uint32_t n,
+__global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t *status, const uint32_t *np,
                                                          const uint32_t *block_off, const uint32_t *n_active,
                                                          uint32_t *perm) {
     __shared__ uint32_t wsum[4];
+    const uint32_t n = *np;
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
     const bool valid = i < n;
     const bool alive = valid && status[i] == GC_ACTIVE;
@@ -233,23 +242,23 @@ __global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t *status,
     }
 }
 
-hipError_t launch_compact(const SoA &st, uint32_t n, OrderScratch &sc, uint32_t *n_active, uint32_t **perm_out,
-                          hipStream_t s) {
-    const uint32_t nb = (n + 255) / 256;
+hipError_t launch_compact(const SoA &st, const uint32_t *np, uint32_t n_max, OrderScratch &sc, uint32_t *n_active,
+                          uint32_t **perm_out, hipStream_t s) {
+    const uint32_t nb = (n_max + 255) / 256;
     if (nb == 0) return launch_fill_u32(n_active, 0u, 1, s);
     if (nb > 256u * sc.max_blocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, st.status, n, sc.counts);
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, st.status, np, sc.counts);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, sc.counts, nb, n_active);
-    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, st.status, n, sc.counts, n_active, sc.vals[0]);
+    hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, st.status, np, sc.counts, n_active, sc.vals[0]);
     *perm_out = sc.vals[0];
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 template <bool kWithComp>
-__global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, uint32_t n) {
+__global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, const uint32_t *np) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= *np) return;
     const uint32_t j = perm[i];
 #define P_(name) dst.name[i] = src.name[j];
     P_(r) P_(th) P_(ph) P_(u) P_(mu) P_(fr) P_(fth) P_(fph) P_(fu) P_(dtp) P_(s) P_(ell) P_(t)
@@ -258,11 +267,40 @@ __global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, uint32_t n) {
 #undef P_
 }
 
-hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, uint32_t n, bool with_comp,
-                          hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    if (with_comp) hipLaunchKernelGGL(k_permute<true>, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, perm, n);
-    else hipLaunchKernelGGL(k_permute<false>, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, perm, n);
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *np, uint32_t n_max,
+                          bool with_comp, hipStream_t s) {
+    if (n_max == 0) return hipSuccess;
+    const dim3 grid((n_max + 255) / 256);
+    if (with_comp) hipLaunchKernelGGL(k_permute<true>, grid, dim3(256), 0, s, src, dst, perm, np);
+    else hipLaunchKernelGGL(k_permute<false>, grid, dim3(256), 0, s, src, dst, perm, np);
+    return hipGetLastError();
+}
+
+// Both state buffers hold identical data for the dead tail: slots past the
+// live prefix are never permuted again.  After a permute, the particles that
+// died since the last reorder (slots [*lo, *hi) of the new buffer) are copied
+// back into the other buffer, which keeps the two in agreement on the tail.
+__global__ void k_copy_range(SoA src, SoA dst, const uint32_t *lo, const uint32_t *hi, bool with_comp) {
+    const uint32_t i = *lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *hi) return;
+#define T_(name) dst.name[i] = src.name[i];
+    T_(r) T_(th) T_(ph) T_(u) T_(mu) T_(fr) T_(fth) T_(fph) T_(fu) T_(dtp) T_(s) T_(ell) T_(t)
+    T_(k) T_(flags) T_(status) T_(step) T_(id) T_(ens) T_(gid)
+    if (with_comp) { T_(cr) T_(cth) T_(cph) T_(cu) T_(ct) }
+#undef T_
+}
+
+hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,
+                             bool with_comp, hipStream_t s) {
+    if (n_max == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_range, dim3((n_max + 255) / 256), dim3(256), 0, s, src, dst, lo, hi, with_comp);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_count(uint32_t *dst, const uint32_t *src) { *dst = *src; }
+
+hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, dst, src);
     return hipGetLastError();
 }
 

@@ -120,7 +120,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
                     stage = 1;
                     continue;
                 }
-                tau = h / dtp;
+                tau = dtp == h ? (R)1 : h * rcp_nr(dtp);
             } else {   // stage 1: F^{n-1} of the bootstrap
                 fp0 = F[0]; fp1 = F[1]; fp2 = F[2]; fp3 = F[3];
                 tau = (R)1;
@@ -139,7 +139,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         }
         if (bad) { status = GC_NONFINITE; break; }
         // corrector, Eq. 6: dt/(6(1+tau)) [(1+tau)(3+tau) F^n + (3+2 tau) F* - tau^2 F^{n-1}]
-        const R cf = h / ((R)6 * ((R)1 + tau));
+        const R cf = tau == (R)1 ? h * (R)(1.0 / 12.0) : h * rcp_nr((R)6 * ((R)1 + tau));
         const R an = ((R)1 + tau) * ((R)3 + tau), as = (R)3 + (R)2 * tau, ap = tau * tau;
         const R e0 = cf * (an * Fn[0] + as * Fs[0] - ap * fp0);
         const R e1 = cf * (an * Fn[1] + as * Fs[1] - ap * fp1);
@@ -191,15 +191,19 @@ __device__ __forceinline__ void count_steps(const PushArgs &a, uint32_t taken) {
 }
 
 // Grid form: one slot per lane.  Workgroups are dispatched round-robin over
-// the 8 XCDs; the remap gives each XCD a contiguous range of (cell-sorted)
-// slots so that its L2 holds the field cells of its own particles.
+// the 8 XCDs.  Only the first ceil(n_active / blockDim) workgroups have work
+// (active particles fill a prefix of the slots after reordering); the remap
+// gives each XCD a contiguous range of that prefix, so that (with cell-sorted
+// slots) its L2 holds the field cells of its own particles, and every XCD gets
+// an equal share however small the active prefix is.
 template <int PREC, int FDT>
-__global__ __launch_bounds__(256) void k_push(PushArgs a) {
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
+    const uint32_t n = *a.n_active;
+    const uint32_t nb = (n + blockDim.x - 1) / blockDim.x, b = blockIdx.x;
+    if (b >= nb) return;
     const uint32_t q = nb >> 3, rem = nb & 7u, xcd = b & 7u, pos = b >> 3;
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
     const uint32_t slot = lb * blockDim.x + threadIdx.x;
-    const uint32_t n = *a.n_active;
     uint32_t taken = 0;
     if (slot < n) taken = advance_slot<PREC, FDT>(a, slot);
     count_steps(a, taken);
@@ -208,7 +212,7 @@ __global__ __launch_bounds__(256) void k_push(PushArgs a) {
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
 // atomic counter until the tiles run out (every workgroup reaches the exit).
 template <int PREC, int FDT>
-__global__ __launch_bounds__(256) void k_push_persistent(PushArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
     const uint32_t tile = (uint32_t)a.tile;

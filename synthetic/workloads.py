@@ -99,13 +99,14 @@ def config_paper_scale(seed: int = 0, n: int = 1 << 20, hours: float = 24.0, fie
 
 
 def config_batched(seed: int = 0, n_ens: int = 64, total: int = 4 << 20, field_seed: int = 1,
-                   dt: float = 1.0, store_dtype: str = "f32") -> Workload:
+                   dt: float = 1.0, store_dtype: str = "f32", grid: SphericalGrid = None,
+                   hours_lo: float = 6.0, hours_hi: float = 48.0) -> Workload:
     """64 ensembles of log-uniform size in [1k, 256k] summing to 4M; energies
     log-uniform 20-300 keV, lambda log-uniform 0.05-2 AU, r0 in [0.2, 0.4] AU,
     latitude in +-40 deg, longitude uniform, stop times uniform in 6-48 h."""
     rng = np.random.default_rng(1000 + seed)
-    grid = SphericalGrid(256, 128, 256, 0.1 * AU, 2.0 * AU)
-    lo, hi = 1 << 10, 1 << 18
+    grid = grid or SphericalGrid(256, 128, 256, 0.1 * AU, 2.0 * AU)
+    lo, hi = min(1 << 10, total // n_ens), min(1 << 18, total)
     w = np.exp(rng.uniform(math.log(lo), math.log(hi), n_ens))
     # rescale towards the requested total while respecting [lo, hi]
     for _ in range(100):
@@ -120,15 +121,15 @@ def config_batched(seed: int = 0, n_ens: int = 64, total: int = 4 << 20, field_s
     r0 = rng.uniform(0.2, 0.4, n_ens) * AU
     lat = np.radians(rng.uniform(-40.0, 40.0, n_ens))
     lon = rng.uniform(0.0, 2.0 * math.pi, n_ens)
-    stop_h = rng.uniform(6.0, 48.0, n_ens)
+    stop_h = rng.uniform(hours_lo, hours_hi, n_ens)
     ens = [Ensemble(n=int(counts[i]), ensemble=i, seed=seed, ekin=float(ekin[i]), r0=float(r0[i]),
                     lat0=float(lat[i]), lon0=float(lon[i]), lambda_par=float(lam[i]),
                     r_in=0.15 * AU, r_out=r_out_default(grid),
                     max_steps=int(round(stop_h[i] * HOUR / dt)))
            for i in range(n_ens)]
-    return Workload("batched-64ens-4M", grid,
+    return Workload(f"batched-{n_ens}ens-{total}", grid,
                     lambda g, device=None: fields.perturbed_parker(g, field_seed, device=device),
-                    ens, dt, int(round(48.0 * HOUR / dt)), store_dtype, 64)
+                    ens, dt, int(round(hours_hi * HOUR / dt)), store_dtype, 64)
 
 
 def config_affine(n: int = 64, seed: int = 3) -> Workload:
