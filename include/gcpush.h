@@ -246,7 +246,9 @@ gc_status gc_reset_counters(gc_ctx *ctx);
 /* ------------------------------------------------------------ autotuner */
 /* Choose launch parameters by timing the context's own workload: coordinate
  * descent over workgroup size, then bin coarsening, then steps per chunk,
- * then the persistent form and its tile size.  Each candidate starts from the
+ * then persistent-form tile sizes.  Candidates keep the form (grid or
+ * persistent) the context has on entry, except the tile candidates, which
+ * are always persistent.  Each candidate starts from the
  * same saved state and runs probe_steps steps of size dt, timed with HIP
  * events; the state is restored afterwards, so the particles do not advance.
  * Candidate lists with n_* = 0 keep the current value.  The best options are

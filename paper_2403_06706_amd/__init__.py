@@ -91,6 +91,18 @@ class Context:
     def stream(self):
         return self._stream
 
+    # Library work runs on the context's stream; torch work on the caller's
+    # current stream.  Order them explicitly around buffers that cross.
+    def _inputs_ready(self):
+        self._stream.wait_stream(_torch().cuda.current_stream(self.device))
+
+    def _outputs_ready(self, *tensors):
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        for t in tensors:
+            t.record_stream(self._stream)
+        cur.wait_stream(self._stream)
+
     def set_options(self, **kw):
         o = _abi.gc_options()
         self._check(lib.gc_get_options(self._h, C.byref(o)))
@@ -147,7 +159,9 @@ class Context:
         s = self._spec(spec)
         m = lib.gc_moments_size(C.byref(s))
         out = torch.empty(max(int(m), 1), dtype=torch.int64, device=f"cuda:{self.device}")
+        self._inputs_ready()
         self._check(lib.gc_moments(self._h, C.byref(s), C.c_void_p(out.data_ptr())))
+        self._outputs_ready(out)
         return out[:m]
 
     # --------------------------------------------------------------- state
@@ -158,7 +172,9 @@ class Context:
         out = {k: torch.empty(max(n, 1), dtype=torch.float64, device=dev) for k in STATE_DOUBLES}
         out.update({k: torch.empty(max(n, 1), dtype=torch.int32, device=dev) for k in STATE_U32})
         v = _abi.gc_state_view(**{k: t.data_ptr() for k, t in out.items()})
+        self._inputs_ready()
         self._check(lib.gc_get_state(self._h, C.byref(v)))
+        self._outputs_ready(*out.values())
         return {k: t[:n] for k, t in out.items()}
 
     def set_state(self, state: Dict[str, "object"]):
@@ -170,6 +186,7 @@ class Context:
         for k in STATE_U32:
             keep[k] = state[k].to(device=f"cuda:{self.device}", dtype=torch.int32).contiguous()
         v = _abi.gc_state_view(**{k: t.data_ptr() for k, t in keep.items()})
+        self._inputs_ready()
         self._check(lib.gc_set_state(self._h, C.byref(v), n))
         self._stream.synchronize()   # the buffers above may be freed on return
 
@@ -177,7 +194,9 @@ class Context:
         torch = _torch()
         n = self.count()
         out = torch.empty((max(n, 1), max(self.log_depth, 1)), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._inputs_ready()
         self._check(lib.gc_get_log(self._h, C.c_void_p(out.data_ptr())))
+        self._outputs_ready(out)
         return out[:n]
 
     # ------------------------------------------------------------ counters
@@ -236,7 +255,9 @@ class Context:
         return out
 
     def copy_probe(self, dst, src, n_bytes: int):
+        self._inputs_ready()
         self._check(lib.gc_copy_probe(self._h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(n_bytes)))
+        self._outputs_ready(dst, src)
 
 
 def state_to_numpy(state: Dict[str, "object"]) -> Dict[str, np.ndarray]:

@@ -776,7 +776,7 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *sp, gc_tune_result *out)
     for (int i = 0; i < sp->n_block; ++i) {
         gc_options c = best;
         c.block_size = sp->block[i];
-        c.persistent = 0;
+        if (c.persistent) c.tile = (c.tile + c.block_size - 1) / c.block_size * c.block_size;
         if (c.block_size != best.block_size && (st = consider(c)) != GC_OK) return st;
     }
     for (int i = 0; i < sp->n_coarsen; ++i) {
