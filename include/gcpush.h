@@ -80,7 +80,10 @@ typedef struct {
     int32_t tile;           /* particles per work-queue tile (persistent mode, multiple of block_size) */
     int32_t log_depth;      /* per particle, record the step of the first log_depth collisions (0: off) */
     int32_t timing;         /* 1: record HIP events around each push launch (see gc_get_counters) */
+    int32_t field_source;   /* GC_SOURCE_GRID (trilinear grid) or GC_SOURCE_MLP (neural field, gc_mlp_set) */
 } gc_options;
+
+enum { GC_SOURCE_GRID = 0, GC_SOURCE_MLP = 1 };
 
 /* Fill *opt with the defaults (FP64, binning every 64 steps, 256 threads). */
 void gc_default_options(gc_options *opt);
@@ -242,6 +245,62 @@ typedef struct {
 } gc_counters;
 gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out);
 gc_status gc_reset_counters(gc_ctx *ctx);
+
+/* --------------------------------------------------------- neural field */
+/* A Fourier-feature network that can replace the gridded field in the push
+ * (field_source = GC_SOURCE_MLP); the grid stays loaded as fallback and judge
+ * (injection, binning and moments keep using it).  With x = ((r - r_min) /
+ * (r_max - r_min), th/pi) of the loaded grid:
+ *   psi_j = 2 pi (a_j x_0 + b_j x_1) + n_j ph  (j < 64, n_j integer),
+ *   h0 = [sin psi_0, cos psi_0, sin psi_1, ...]  (128 features),
+ *   h_l = silu(W_l h_{l-1} + c_l) for l = 1..6 (W_l 128 x 128),
+ *   y = W_o h_6 + c_o (6 outputs),
+ *   B_i = S_i (r_ref/r)^p_i y_i, E_i = S_{i+3} (r_ref/r)^p_{i+3} y_{i+3};
+ * grad|B| and (b.grad)b from the derivatives of B along (r, th, ph), carried
+ * forward through the network (three tangents).  Products run in BF16 on the
+ * matrix cores with FP32 accumulation; parameters are kept in FP32. */
+#define GC_MLP_PARAMS 99846   /* W[6][128][128] | c[6][128] | W_o[6][128] | c_o[6], FP32 */
+
+typedef struct {
+    double freq[64][3];       /* a_j, b_j, n_j */
+    double r_ref;             /* m */
+    double scale[6];          /* S_c */
+    double power[6];          /* p_c */
+    const float *params;      /* HOST pointer to GC_MLP_PARAMS values (copied), NULL: all zero */
+} gc_mlp_desc;
+
+/* Install (or replace) the network; resets the optimizer state.  Waits.
+ * Errors: GC_ESTATE before gc_load_field (the input normalization uses its
+ * radial range); GC_EINVAL for non-integer n_j or non-finite values. */
+gc_status gc_mlp_set(gc_ctx *ctx, const gc_mlp_desc *desc);
+/* Copy the FP32 parameters (GC_MLP_PARAMS floats, HOST) out.  Waits. */
+gc_status gc_mlp_get_params(gc_ctx *ctx, float *host_out);
+/* Copy the gradient of the last gc_mlp_train_step out (HOST).  Waits. */
+gc_status gc_mlp_get_grads(gc_ctx *ctx, float *host_out);
+
+typedef struct {
+    double lr, beta1, beta2, eps;   /* Adam */
+    double wc[6];                   /* weights of the six normalized outputs in the loss */
+    double beta_pair;               /* weight of the paired-difference term */
+    int32_t step;                   /* Adam step number (>= 1) */
+    int32_t apply;                  /* 0: compute loss and gradient only */
+} gc_mlp_train_opts;
+
+/* One training step on n_pairs paired points.  pts: DEVICE array of 3 x (2 n)
+ * doubles (r[2n], then th[2n], then ph[2n]); point n_pairs + i is the partner
+ * of point i.  tgt: DEVICE array of (2 n) x 6 doubles, the field (B, E) to fit
+ * at every point.  Loss (normalized outputs y, targets t = tgt / envelope):
+ *   L = (1/n) sum_i sum_c w_c [(y_c(x_i) - t_c(x_i))^2
+ *        + beta ((y_c(x'_i) - y_c(x_i)) - (t_c(x'_i) - t_c(x_i)))^2].
+ * *loss (HOST) receives L.  Waits. */
+gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
+                            const gc_mlp_train_opts *opts, double *loss);
+
+/* Field at n points (DEVICE pts: r[n], th[n], ph[n]; DEVICE out: n x 12, the
+ * components in the order of the grid): gc_mlp_eval from the network,
+ * gc_field_sample by trilinear interpolation of the loaded grid.  Async. */
+gc_status gc_mlp_eval(gc_ctx *ctx, const double *pts, int64_t n, double *out);
+gc_status gc_field_sample(gc_ctx *ctx, const double *pts, int64_t n, double *out);
 
 /* ------------------------------------------------------------ autotuner */
 /* Choose launch parameters by timing the context's own workload: coordinate

@@ -103,6 +103,8 @@ int or_field_eval(const or_field *f, double r, double th, double ph, double out[
     if (!(isfinite(r) && isfinite(th) && isfinite(ph))) return 0;
     if (f->kind == OR_FIELD_PARKER) {
         or_parker_closed_form(f->a0, f->omega, f->v_wind, r, th, out);
+    } else if (f->kind == OR_FIELD_CALLBACK) {
+        if (!f->eval || !f->eval(f->user, r, th, ph, out)) return 0;
     } else {
         const int nr = f->nr, nth = f->nth, nph = f->nph;
         const double dr = (f->r_max - f->r_min) / (nr - 1);

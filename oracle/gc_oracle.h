@@ -21,7 +21,7 @@ extern "C" {
 
 enum { OR_ACTIVE = 0, OR_EXITED = 1, OR_FINISHED = 2, OR_NONFINITE = 3 };
 enum { OR_BOOTSTRAP = 1u, OR_PENDING = 2u };
-enum { OR_FIELD_GRID = 0, OR_FIELD_PARKER = 1 };
+enum { OR_FIELD_GRID = 0, OR_FIELD_PARKER = 1, OR_FIELD_CALLBACK = 2 };
 
 typedef struct {
     int32_t kind;          /* OR_FIELD_GRID or OR_FIELD_PARKER (closed form) */
@@ -31,6 +31,11 @@ typedef struct {
     double a0;             /* PARKER: B_r r^2 (T m^2) */
     double omega;          /* PARKER: rotation rate (rad/s) */
     double v_wind;         /* PARKER: radial wind speed (m/s) */
+    /* CALLBACK: the 12 components at a point from a caller-supplied function
+     * (the test suite's FP64 neural field); returns 0 where undefined.  Runs
+     * single-threaded: pass nthreads = 1 to the advance calls. */
+    int (*eval)(void *user, double r, double th, double ph, double out[12]);
+    void *user;
 } or_field;
 
 typedef struct {

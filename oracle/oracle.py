@@ -13,7 +13,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 ACTIVE, EXITED, FINISHED, NONFINITE = 0, 1, 2, 3
 BOOTSTRAP, PENDING = 1, 2
-FIELD_GRID, FIELD_PARKER = 0, 1
+FIELD_GRID, FIELD_PARKER, FIELD_CALLBACK = 0, 1, 2
+EVAL_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_double, C.c_double, C.c_double, C.POINTER(C.c_double))
 
 PARTICLE_DTYPE = np.dtype([
     ("r", "f8"), ("th", "f8"), ("ph", "f8"), ("u", "f8"), ("mu_B", "f8"),
@@ -26,7 +27,8 @@ assert PARTICLE_DTYPE.itemsize == 128
 class _Field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nr", C.c_int32), ("nth", C.c_int32), ("nph", C.c_int32),
                 ("r_min", C.c_double), ("r_max", C.c_double), ("data", C.c_void_p),
-                ("a0", C.c_double), ("omega", C.c_double), ("v_wind", C.c_double)]
+                ("a0", C.c_double), ("omega", C.c_double), ("v_wind", C.c_double),
+                ("eval", EVAL_FN), ("user", C.c_void_p)]
 
 
 class _Ens(C.Structure):
@@ -91,11 +93,26 @@ def _ptr(a: np.ndarray):
 
 # ----------------------------------------------------------------------------
 class Field:
-    """A gridded field ([nr][nth][nph][12] float64) or the closed-form Parker spiral."""
+    """A gridded field ([nr][nth][nph][12] float64), the closed-form Parker
+    spiral, or a callback fn(r, th, ph) -> 12 components (or None where
+    undefined); advance calls with a callback field must use nthreads=1."""
 
-    def __init__(self, grid, data: Optional[np.ndarray] = None, parker: Optional[dict] = None):
+    def __init__(self, grid, data: Optional[np.ndarray] = None, parker: Optional[dict] = None, callback=None):
         self.grid = grid
-        if data is not None:
+        self.callback = callback
+        if callback is not None:
+            def _eval(_user, r, th, ph, out):
+                g = callback(r, th, ph)
+                if g is None or not np.all(np.isfinite(g)):
+                    return 0
+                for c in range(12):
+                    out[c] = float(g[c])
+                return 1
+            self._fn = EVAL_FN(_eval)
+            self.data = None
+            self._s = _Field(FIELD_CALLBACK, grid.nr, grid.nth, grid.nph, grid.r_min, grid.r_max,
+                             None, 0.0, 0.0, 0.0, self._fn, None)
+        elif data is not None:
             self.data = np.ascontiguousarray(data, dtype=np.float64)
             assert self.data.shape == (grid.nr, grid.nth, grid.nph, 12)
             self._s = _Field(FIELD_GRID, grid.nr, grid.nth, grid.nph, grid.r_min, grid.r_max,
@@ -186,6 +203,8 @@ def advance(field: Field, ens_table, particles: np.ndarray, dt: float, n_steps: 
         logs = (np.full((n, log_depth), 0xFFFFFFFF, dtype=np.uint32),
                 np.full((n, log_depth), np.nan), np.full((n, log_depth), np.nan))
         log = _Log(log_depth, 0, logs[0].ctypes.data, logs[1].ctypes.data, logs[2].ctypes.data)
+    if field.callback is not None:
+        nthreads = 1
     lib.or_advance(field.ref, C.cast(ens_table, C.c_void_p), _ptr(particles), n, dt, int(n_steps),
                    int(nthreads), C.byref(log))
     return logs
@@ -198,6 +217,8 @@ def advance_replay(field: Field, ens_table, particles: np.ndarray, dt: float, ta
     ts = np.ascontiguousarray(target_steps, dtype=np.uint32)
     cs = np.ascontiguousarray(coll_steps, dtype=np.uint32)
     assert cs.shape[0] == len(particles) and len(ts) == len(particles)
+    if field.callback is not None:
+        nthreads = 1
     lib.or_advance_replay(field.ref, C.cast(ens_table, C.c_void_p), _ptr(particles), len(particles), dt,
                           _ptr(ts), _ptr(cs), int(cs.shape[1]), int(nthreads))
 

@@ -15,13 +15,41 @@ import numpy as np
 from . import _abi
 from ._abi import (GC_F64, GC_F32, GC_F16, GC_PREC_F64, GC_PREC_F32_ACC64, GC_PREC_F32_KAHAN,  # noqa: F401
                    GC_ACTIVE, GC_EXITED, GC_FINISHED, GC_NONFINITE, GC_FLAG_BOOTSTRAP, GC_FLAG_PENDING,
-                   GC_ORDER_NONE, GC_ORDER_COMPACT, GC_ORDER_BIN, STATE_DOUBLES, STATE_U32)
+                   GC_ORDER_NONE, GC_ORDER_COMPACT, GC_ORDER_BIN, GC_SOURCE_GRID, GC_SOURCE_MLP,
+                   GC_MLP_PARAMS, STATE_DOUBLES, STATE_U32)
 
 lib = _abi.load()
 
 _DTYPES = {"f64": GC_F64, "f32": GC_F32, "f16": GC_F16}
 _PRECS = {"f64": GC_PREC_F64, "f32_acc64": GC_PREC_F32_ACC64, "f32_kahan": GC_PREC_F32_KAHAN}
 _ORDERS = {"none": GC_ORDER_NONE, "compact": GC_ORDER_COMPACT, "bin": GC_ORDER_BIN}
+_SOURCES = {"grid": GC_SOURCE_GRID, "mlp": GC_SOURCE_MLP}
+MLP_DEPTH, MLP_WIDTH, MLP_OUT = 6, 128, 6
+
+
+def mlp_flatten(params: Dict[str, np.ndarray]) -> np.ndarray:
+    """{W1..W6 [128,128], c1..c6 [128], Wo [6,128], co [6]} -> the GC_MLP_PARAMS float32 block."""
+    parts = [np.asarray(params[f"W{l}"]).ravel() for l in range(1, MLP_DEPTH + 1)]
+    parts += [np.asarray(params[f"c{l}"]).ravel() for l in range(1, MLP_DEPTH + 1)]
+    parts += [np.asarray(params["Wo"]).ravel(), np.asarray(params["co"]).ravel()]
+    flat = np.concatenate(parts).astype(np.float32)
+    if flat.size != GC_MLP_PARAMS:
+        raise ValueError(f"expected {GC_MLP_PARAMS} parameters, got {flat.size}")
+    return flat
+
+
+def mlp_unflatten(flat: np.ndarray) -> Dict[str, np.ndarray]:
+    out, o = {}, 0
+    for l in range(1, MLP_DEPTH + 1):
+        out[f"W{l}"] = flat[o:o + MLP_WIDTH * MLP_WIDTH].reshape(MLP_WIDTH, MLP_WIDTH)
+        o += MLP_WIDTH * MLP_WIDTH
+    for l in range(1, MLP_DEPTH + 1):
+        out[f"c{l}"] = flat[o:o + MLP_WIDTH]
+        o += MLP_WIDTH
+    out["Wo"] = flat[o:o + MLP_OUT * MLP_WIDTH].reshape(MLP_OUT, MLP_WIDTH)
+    o += MLP_OUT * MLP_WIDTH
+    out["co"] = flat[o:o + MLP_OUT]
+    return out
 
 
 class GCError(RuntimeError):
@@ -40,7 +68,7 @@ class Context:
 
     def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
                  bin_coarsen: int = 0, block_size: int = 256, persistent: bool = False, tile: int = 1024,
-                 log_depth: int = 0, timing: bool = False, stream=None):
+                 log_depth: int = 0, timing: bool = False, field_source: str = "grid", stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the guiding-centre pusher runs only on the device")
@@ -59,6 +87,7 @@ class Context:
         o.tile = tile
         o.log_depth = log_depth
         o.timing = int(timing)
+        o.field_source = _SOURCES[field_source]
         self._opt = o
         h = C.c_void_p()
         st = lib.gc_create(C.byref(h), C.byref(o))
@@ -111,6 +140,8 @@ class Context:
                 v = _PRECS[v]
             elif k == "order" and isinstance(v, str):
                 v = _ORDERS[v]
+            elif k == "field_source" and isinstance(v, str):
+                v = _SOURCES[v]
             elif k == "stream":
                 self._stream = v
                 k, v = "hip_stream", v.cuda_stream
@@ -214,7 +245,7 @@ class Context:
         self._check(lib.gc_get_options(self._h, C.byref(o)))
         return {"precision": o.precision, "order": o.order, "chunk_steps": o.chunk_steps,
                 "bin_coarsen": o.bin_coarsen, "block_size": o.block_size, "persistent": o.persistent,
-                "tile": o.tile}
+                "tile": o.tile, "field_source": o.field_source}
 
     def autotune(self, dt: float, probe_steps: int = 128, blocks=(64, 128, 256), coarsen=(0, 1, 2),
                  chunks=(), tiles=(256, 1024, 4096), cache: Optional[str] = None, key: Optional[str] = None) -> dict:
@@ -253,6 +284,78 @@ class Context:
             with open(cache, "w") as f:
                 json.dump(stored_all, f, indent=1)
         return out
+
+    # -------------------------------------------------------- neural field
+    def mlp_set(self, freq, r_ref: float, scale, power, params: Optional[Dict[str, np.ndarray]] = None):
+        """Install the network (gc_mlp_set).  freq [64, 3] (a_j, b_j, n_j)."""
+        d = _abi.gc_mlp_desc()
+        fq = np.asarray(freq, dtype=np.float64)
+        for j in range(64):
+            for i in range(3):
+                d.freq[j][i] = float(fq[j, i])
+        d.r_ref = float(r_ref)
+        for c in range(6):
+            d.scale[c] = float(scale[c])
+            d.power[c] = float(power[c])
+        keep = None
+        if params is not None:
+            keep = mlp_flatten(params)
+            d.params = keep.ctypes.data_as(C.POINTER(C.c_float))
+        self._inputs_ready()
+        self._check(lib.gc_mlp_set(self._h, C.byref(d)))
+
+    def _mlp_block(self, fn) -> Dict[str, np.ndarray]:
+        flat = np.empty(GC_MLP_PARAMS, dtype=np.float32)
+        self._check(fn(self._h, flat.ctypes.data_as(C.POINTER(C.c_float))))
+        return mlp_unflatten(flat)
+
+    def mlp_params(self) -> Dict[str, np.ndarray]:
+        return self._mlp_block(lib.gc_mlp_get_params)
+
+    def mlp_grads(self) -> Dict[str, np.ndarray]:
+        return self._mlp_block(lib.gc_mlp_get_grads)
+
+    def mlp_train_step(self, pts, tgt, wc=(1.0,) * 6, beta_pair: float = 0.0, lr: float = 1e-3,
+                       betas=(0.9, 0.999), eps: float = 1e-8, step: int = 1, apply: bool = True) -> float:
+        """One training step (gc_mlp_train_step).  pts: device float64 [3, 2n]
+        (point n + i pairs with point i); tgt: device float64 [2n, 6]."""
+        n2 = int(pts.shape[1])
+        if pts.shape[0] != 3 or n2 % 2 or tuple(tgt.shape) != (n2, 6):
+            raise ValueError("pts must be [3, 2n] and tgt [2n, 6]")
+        for t in (pts, tgt):
+            if not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float64"):
+                raise TypeError("pts and tgt must be contiguous float64 device tensors")
+        o = _abi.gc_mlp_train_opts()
+        o.lr, o.beta1, o.beta2, o.eps = float(lr), float(betas[0]), float(betas[1]), float(eps)
+        for c in range(6):
+            o.wc[c] = float(wc[c])
+        o.beta_pair = float(beta_pair)
+        o.step = int(step)
+        o.apply = int(apply)
+        loss = C.c_double()
+        self._inputs_ready()
+        self._check(lib.gc_mlp_train_step(self._h, C.c_void_p(pts.data_ptr()), C.c_void_p(tgt.data_ptr()), n2 // 2,
+                                          C.byref(o), C.byref(loss)))
+        return loss.value
+
+    def _points(self, fn, pts):
+        torch = _torch()
+        if not (pts.is_cuda and pts.is_contiguous() and pts.dtype == torch.float64 and pts.shape[0] == 3):
+            raise TypeError("pts must be a contiguous float64 device tensor [3, n]")
+        n = int(pts.shape[1])
+        out = torch.empty((n, 12), dtype=torch.float64, device=pts.device)
+        self._inputs_ready()
+        self._check(fn(self._h, C.c_void_p(pts.data_ptr()), n, C.c_void_p(out.data_ptr())))
+        self._outputs_ready(out, pts)
+        return out
+
+    def mlp_eval(self, pts):
+        """Neural field at points (device float64 [3, n]) -> [n, 12]."""
+        return self._points(lib.gc_mlp_eval, pts)
+
+    def field_sample(self, pts):
+        """Trilinear grid field at points (device float64 [3, n]) -> [n, 12]."""
+        return self._points(lib.gc_field_sample, pts)
 
     def copy_probe(self, dst, src, n_bytes: int):
         self._inputs_ready()

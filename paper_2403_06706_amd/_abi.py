@@ -11,13 +11,15 @@ GC_PREC_F64, GC_PREC_F32_ACC64, GC_PREC_F32_KAHAN = 0, 1, 2
 GC_ACTIVE, GC_EXITED, GC_FINISHED, GC_NONFINITE = 0, 1, 2, 3
 GC_FLAG_BOOTSTRAP, GC_FLAG_PENDING = 1, 2
 GC_ORDER_NONE, GC_ORDER_COMPACT, GC_ORDER_BIN = 0, 1, 2
+GC_SOURCE_GRID, GC_SOURCE_MLP = 0, 1
+GC_MLP_PARAMS = 99846
 
 
 class gc_options(C.Structure):
     _fields_ = [("hip_stream", C.c_void_p), ("device", C.c_int32), ("precision", C.c_int32),
                 ("order", C.c_int32), ("chunk_steps", C.c_int32), ("bin_coarsen", C.c_int32),
                 ("block_size", C.c_int32), ("persistent", C.c_int32), ("tile", C.c_int32),
-                ("log_depth", C.c_int32), ("timing", C.c_int32)]
+                ("log_depth", C.c_int32), ("timing", C.c_int32), ("field_source", C.c_int32)]
 
 
 class gc_field_desc(C.Structure):
@@ -69,6 +71,16 @@ class gc_tune_result(C.Structure):
                 ("n_tried", C.c_int32), ("pad", C.c_int32)]
 
 
+class gc_mlp_desc(C.Structure):
+    _fields_ = [("freq", (C.c_double * 3) * 64), ("r_ref", C.c_double), ("scale", C.c_double * 6),
+                ("power", C.c_double * 6), ("params", C.POINTER(C.c_float))]
+
+
+class gc_mlp_train_opts(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("wc", C.c_double * 6), ("beta_pair", C.c_double), ("step", C.c_int32), ("apply", C.c_int32)]
+
+
 def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -100,6 +112,12 @@ def load():
         "gc_reset_counters": (S, [P]),
         "gc_copy_probe": (S, [P, P, P, C.c_uint64]),
         "gc_autotune": (S, [P, C.POINTER(gc_tune_space), C.POINTER(gc_tune_result)]),
+        "gc_mlp_set": (S, [P, C.POINTER(gc_mlp_desc)]),
+        "gc_mlp_get_params": (S, [P, C.POINTER(C.c_float)]),
+        "gc_mlp_get_grads": (S, [P, C.POINTER(C.c_float)]),
+        "gc_mlp_train_step": (S, [P, P, P, C.c_int64, C.POINTER(gc_mlp_train_opts), C.POINTER(C.c_double)]),
+        "gc_mlp_eval": (S, [P, P, C.c_int64, P]),
+        "gc_field_sample": (S, [P, P, C.c_int64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -112,5 +130,6 @@ DECLARED = (
     "gc_default_options", "gc_create", "gc_destroy", "gc_last_error", "gc_set_options", "gc_get_options",
     "gc_load_field", "gc_inject", "gc_advance", "gc_advance_graph", "gc_moments_size", "gc_moments",
     "gc_count", "gc_get_state", "gc_set_state", "gc_get_log", "gc_get_counters", "gc_reset_counters",
-    "gc_copy_probe", "gc_autotune",
+    "gc_copy_probe", "gc_autotune", "gc_mlp_set", "gc_mlp_get_params", "gc_mlp_get_grads", "gc_mlp_train_step",
+    "gc_mlp_eval", "gc_field_sample",
 )

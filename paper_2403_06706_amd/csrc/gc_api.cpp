@@ -12,6 +12,8 @@
 
 #include "gc_internal.h"
 #include "gc_launch.h"
+#include "gc_mlp.h"
+#include "gc_mlp_launch.h"
 #include "gcpush.h"
 
 using namespace gc;
@@ -21,6 +23,23 @@ struct GraphKey {
     int64_t n_steps = -1;
     uint64_t n = 0;
     gc_options opt{};
+};
+
+// Neural field: FP32 master parameters (padded device layout), Adam moments,
+// gradient and the BF16 copies used by the matrix-core products; training
+// workspace sized for ws_rows rows.
+struct MlpState {
+    bool set = false;
+    MlpArgs args{};
+    void *mem = nullptr;
+    float *p = nullptr, *mo = nullptr, *ve = nullptr, *g = nullptr;
+    __bf16 *W = nullptr, *WT = nullptr, *Wo = nullptr;
+    void *ws = nullptr;
+    int64_t ws_rows = 0;
+    __bf16 *H = nullptr, *dZ = nullptr;                  // H: activations H0..H6, [7][rows][128]
+    float *Z = nullptr, *Y = nullptr, *dY = nullptr;     // Z: pre-activations [6][rows][128]
+    float *dH = nullptr, *part = nullptr;
+    double *loss_part = nullptr;
 };
 
 struct gc_ctx {
@@ -54,6 +73,8 @@ struct gc_ctx {
     // graph
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey{};
+    // neural field
+    MlpState mlp;
 };
 
 namespace {
@@ -86,6 +107,8 @@ gc_status check_options(gc_ctx *ctx, const gc_options *o) {
     if (o->persistent && (o->tile <= 0 || o->tile % o->block_size != 0))
         return fail(ctx, GC_EINVAL, "tile must be a positive multiple of block_size");
     if (o->log_depth < 0 || o->log_depth > 4096) return fail(ctx, GC_EINVAL, "log_depth must be in [0, 4096]");
+    if (o->field_source != GC_SOURCE_GRID && o->field_source != GC_SOURCE_MLP)
+        return fail(ctx, GC_EINVAL, "unknown field_source %d", o->field_source);
     return GC_OK;
 }
 
@@ -266,7 +289,10 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
         e1 = take_event(ctx);
         HIPCHK(hipEventRecord(e0, s));
     }
-    HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, grid_blocks, s));
+    if (ctx->opt.field_source == GC_SOURCE_MLP)
+        HIPCHK(launch_push_mlp(a, ctx->mlp.args, ctx->opt.precision, s));
+    else
+        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, grid_blocks, s));
     if (timed) {
         HIPCHK(hipEventRecord(e1, s));
         ctx->ev_push.emplace_back(e0, e1);
@@ -292,6 +318,8 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
     if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_advance before gc_load_field");
     if (!(std::isfinite(dt) && dt > 0.0)) return fail(ctx, GC_EINVAL, "dt must be finite and > 0 (got %g)", dt);
     if (n_steps < 0) return fail(ctx, GC_EINVAL, "n_steps must be >= 0");
+    if (ctx->opt.field_source == GC_SOURCE_MLP && !ctx->mlp.set)
+        return fail(ctx, GC_ESTATE, "field_source is the neural field but gc_mlp_set was not called");
     return GC_OK;
 }
 
@@ -366,6 +394,8 @@ void gc_destroy(gc_ctx *ctx) {
     if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);
     if (ctx->log) (void)hipFree(ctx->log);
     if (ctx->field_buf) (void)hipFree(ctx->field_buf);
+    if (ctx->mlp.mem) (void)hipFree(ctx->mlp.mem);
+    if (ctx->mlp.ws) (void)hipFree(ctx->mlp.ws);
     if (ctx->ens_dev) (void)hipFree(ctx->ens_dev);
     if (ctx->n_active) (void)hipFree(ctx->n_active);
     delete ctx;
@@ -816,6 +846,235 @@ gc_status gc_copy_probe(gc_ctx *ctx, void *dst, const void *src, uint64_t n_byte
     if (n_bytes % 16) return fail(ctx, GC_EINVAL, "n_bytes must be a multiple of 16");
     HIPCHK(hipSetDevice(ctx->opt.device));
     HIPCHK(launch_copy_probe(dst, src, n_bytes, ctx->stream));
+    return GC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Neural field
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kUserParams = GC_MLP_PARAMS;             // W | c | W_o[6][128] | c_o[6]
+constexpr int kUserOffWo = kMlpOffWo, kUserOffCo = kMlpOffWo + kMlpOut * kMlpWidth;
+static_assert(kUserOffCo + kMlpOut == kUserParams, "GC_MLP_PARAMS does not match the network shape");
+constexpr int kTrainGroups = 256;                     // row groups of the split-K gradient sums
+constexpr int kLossBlocks = 512;
+
+void to_device_layout(const float *u, std::vector<float> &d) {
+    d.assign(kMlpParams, 0.0f);
+    if (!u) return;
+    std::copy(u, u + kUserOffWo, d.begin());          // W and c share the layout
+    std::copy(u + kUserOffWo, u + kUserOffCo, d.begin() + kMlpOffWo);
+    std::copy(u + kUserOffCo, u + kUserParams, d.begin() + kMlpOffCo);
+}
+
+void to_user_layout(const std::vector<float> &d, float *u) {
+    std::copy(d.begin(), d.begin() + kUserOffWo, u);
+    std::copy(d.begin() + kMlpOffWo, d.begin() + kMlpOffWo + kMlpOut * kMlpWidth, u + kUserOffWo);
+    std::copy(d.begin() + kMlpOffCo, d.begin() + kMlpOffCo + kMlpOut, u + kUserOffCo);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+gc_status mlp_workspace(gc_ctx *ctx, int64_t rows) {
+    MlpState &m = ctx->mlp;
+    if (rows <= m.ws_rows) return GC_OK;
+    const int64_t cap = std::max<int64_t>(rows, 2 * m.ws_rows);
+    const size_t R = (size_t)cap;
+    const size_t part = std::max<size_t>((size_t)kTrainGroups * kMlpWidth * kMlpWidth,
+                                         (size_t)(kTrainGroups + 1) * (kMlpOut * kMlpWidth + kMlpOut));
+    const size_t sz[] = {align256(7 * R * kMlpWidth * 2), align256(R * kMlpWidth * 2),
+                         align256(6 * R * kMlpWidth * 4), align256(R * kMlpOut * 4), align256(R * kMlpOut * 4),
+                         align256(R * kMlpWidth * 4), align256(part * 4), align256(kLossBlocks * 8)};
+    size_t total = 0;
+    for (size_t b : sz) total += b;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, total) != hipSuccess)
+        return fail(ctx, GC_ENOMEM, "cannot allocate the training workspace for %lld rows", (long long)cap);
+    if (m.ws) (void)hipFree(m.ws);
+    m.ws = mem;
+    m.ws_rows = cap;
+    char *c = static_cast<char *>(mem);
+    m.H = reinterpret_cast<__bf16 *>(c); c += sz[0];
+    m.dZ = reinterpret_cast<__bf16 *>(c); c += sz[1];
+    m.Z = reinterpret_cast<float *>(c); c += sz[2];
+    m.Y = reinterpret_cast<float *>(c); c += sz[3];
+    m.dY = reinterpret_cast<float *>(c); c += sz[4];
+    m.dH = reinterpret_cast<float *>(c); c += sz[5];
+    m.part = reinterpret_cast<float *>(c); c += sz[6];
+    m.loss_part = reinterpret_cast<double *>(c);
+    return GC_OK;
+}
+
+gc_status check_mlp_points(gc_ctx *ctx, const double *pts, int64_t n, const double *out) {
+    if (n < 0) return fail(ctx, GC_EINVAL, "n must be >= 0");
+    if (n > 0x7FFFFF00ll) return fail(ctx, GC_EINVAL, "too many points (%lld)", (long long)n);
+    if (n > 0 && (!pts || !out)) return fail(ctx, GC_EINVAL, "pts and out must be set");
+    return GC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gc_status gc_mlp_set(gc_ctx *ctx, const gc_mlp_desc *d) {
+    if (!ctx || !d) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_mlp_set before gc_load_field");
+    for (int j = 0; j < kMlpFreq; ++j) {
+        const double a = d->freq[j][0], b = d->freq[j][1], n = d->freq[j][2];
+        if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(n))
+            return fail(ctx, GC_EINVAL, "frequency %d is not finite", j);
+        if (n != std::floor(n) || std::fabs(n) > 4096.0)
+            return fail(ctx, GC_EINVAL, "n_%d must be an integer of magnitude <= 4096 (got %g)", j, n);
+    }
+    if (!(d->r_ref > 0.0) || !std::isfinite(d->r_ref)) return fail(ctx, GC_EINVAL, "r_ref must be finite and > 0");
+    for (int c = 0; c < kMlpOut; ++c)
+        if (!std::isfinite(d->scale[c]) || !std::isfinite(d->power[c]))
+            return fail(ctx, GC_EINVAL, "scale and power must be finite");
+    if (d->params)
+        for (int i = 0; i < kUserParams; ++i)
+            if (!std::isfinite(d->params[i])) return fail(ctx, GC_EINVAL, "parameter %d is not finite", i);
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    MlpState &m = ctx->mlp;
+    hipStream_t s = ctx->stream;
+    const size_t nw = (size_t)kMlpDepth * kMlpWidth * kMlpWidth;
+    const size_t fbytes = align256((size_t)kMlpParams * 4);
+    const size_t total = 4 * fbytes + 2 * align256(nw * 2) + align256((size_t)kMlpOutPad * kMlpWidth * 2);
+    if (!m.mem) {
+        if (hipMalloc(&m.mem, total) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate the network");
+        char *c = static_cast<char *>(m.mem);
+        m.p = reinterpret_cast<float *>(c); c += fbytes;
+        m.mo = reinterpret_cast<float *>(c); c += fbytes;
+        m.ve = reinterpret_cast<float *>(c); c += fbytes;
+        m.g = reinterpret_cast<float *>(c); c += fbytes;
+        m.W = reinterpret_cast<__bf16 *>(c); c += align256(nw * 2);
+        m.WT = reinterpret_cast<__bf16 *>(c); c += align256(nw * 2);
+        m.Wo = reinterpret_cast<__bf16 *>(c);
+    }
+    std::vector<float> host;
+    to_device_layout(d->params, host);
+    HIPCHK(hipMemcpyAsync(m.p, host.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice, s));
+    for (float *z : {m.mo, m.ve, m.g}) HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(z), 0u, kMlpParams, s));
+    HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, s));
+    MlpArgs &a = m.args;
+    a = MlpArgs{};
+    a.W = m.W;
+    a.Wo = m.Wo;
+    a.c = m.p + kMlpOffC;
+    a.co = m.p + kMlpOffCo;
+    for (int j = 0; j < kMlpFreq; ++j) {
+        a.fa[j] = (float)d->freq[j][0];
+        a.fb[j] = (float)d->freq[j][1];
+        a.fn[j] = (float)d->freq[j][2];
+    }
+    const double r_span = (double)(ctx->f.nr - 1) / ctx->f.inv_dr;
+    a.r_min = (float)ctx->f.r_min;
+    a.inv_rspan = (float)(1.0 / r_span);
+    a.r_ref = (float)d->r_ref;
+    for (int c = 0; c < kMlpOut; ++c) {
+        a.scale[c] = (float)d->scale[c];
+        a.power[c] = (float)d->power[c];
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    m.set = true;
+    if (ctx->gexec) {
+        (void)hipGraphExecDestroy(ctx->gexec);
+        ctx->gexec = nullptr;
+    }
+    return GC_OK;
+}
+
+static gc_status mlp_copy_out(gc_ctx *ctx, const float *src, float *host_out) {
+    if (!ctx) return GC_EINVAL;
+    if (!host_out) return fail(ctx, GC_EINVAL, "host_out is NULL");
+    if (!ctx->mlp.set) return fail(ctx, GC_ESTATE, "no neural field (gc_mlp_set)");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    std::vector<float> host(kMlpParams);
+    HIPCHK(hipMemcpyAsync(host.data(), src, (size_t)kMlpParams * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    to_user_layout(host, host_out);
+    return GC_OK;
+}
+
+gc_status gc_mlp_get_params(gc_ctx *ctx, float *host_out) {
+    return mlp_copy_out(ctx, ctx ? ctx->mlp.p : nullptr, host_out);
+}
+
+gc_status gc_mlp_get_grads(gc_ctx *ctx, float *host_out) {
+    return mlp_copy_out(ctx, ctx ? ctx->mlp.g : nullptr, host_out);
+}
+
+gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
+                            const gc_mlp_train_opts *o, double *loss) {
+    if (!ctx || !o) return GC_EINVAL;
+    if (!ctx->mlp.set) return fail(ctx, GC_ESTATE, "no neural field (gc_mlp_set)");
+    if (n_pairs <= 0 || n_pairs > (1 << 26)) return fail(ctx, GC_EINVAL, "n_pairs must be in [1, 2^26]");
+    if (!pts || !tgt) return fail(ctx, GC_EINVAL, "pts and tgt must be set");
+    if (o->apply && (o->step < 1 || !(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) ||
+                     !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps > 0.0)))
+        return fail(ctx, GC_EINVAL, "Adam needs step >= 1, lr > 0, 0 <= beta1, beta2 < 1 and eps > 0");
+    if (!(o->beta_pair >= 0.0) || !std::isfinite(o->beta_pair)) return fail(ctx, GC_EINVAL, "beta_pair must be >= 0");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const int rows = (int)(2 * n_pairs);
+    gc_status st = mlp_workspace(ctx, rows);
+    if (st != GC_OK) return st;
+    MlpState &m = ctx->mlp;
+    hipStream_t s = ctx->stream;
+    const size_t RW = (size_t)rows * kMlpWidth, WW = (size_t)kMlpWidth * kMlpWidth;
+    // forward: H0 = features, H_{l+1} = silu(H_l W_l^T + c_l), Y = H6 W_o^T + c_o
+    HIPCHK(mlp_launch_features(m.args, pts, rows, m.H, s));
+    for (int l = 0; l < kMlpDepth; ++l)
+        HIPCHK(mlp_launch_forward_layer(m.H + l * RW, m.W + l * WW, m.p + kMlpOffC + l * kMlpWidth, rows, m.Z + l * RW,
+                                        m.H + (l + 1) * RW, s));
+    HIPCHK(mlp_launch_output(m.H + kMlpDepth * RW, m.Wo, m.p + kMlpOffCo, rows, m.Y, s));
+    // loss and its gradient with respect to the outputs
+    MlpLoss L{};
+    for (int c = 0; c < kMlpOut; ++c) L.wc[c] = o->wc[c];
+    L.beta = o->beta_pair;
+    const int lb = (int)std::min<int64_t>(kLossBlocks, (n_pairs + 255) / 256);
+    HIPCHK(mlp_launch_loss(m.args, pts, tgt, m.Y, (int)n_pairs, L, m.dY, m.loss_part, lb, s));
+    // backward
+    HIPCHK(mlp_launch_out_grad(m.dY, m.H + kMlpDepth * RW, rows, kTrainGroups, m.part, m.g + kMlpOffWo,
+                               m.g + kMlpOffCo, s));
+    HIPCHK(mlp_launch_out_back(m.dY, m.p + kMlpOffWo, m.Z + (kMlpDepth - 1) * RW, rows, m.dH, s));
+    for (int l = kMlpDepth - 1; l >= 0; --l) {
+        HIPCHK(mlp_launch_dz(m.dH, m.Z + l * RW, rows, kTrainGroups, m.dZ, m.part, m.g + kMlpOffC + l * kMlpWidth, s));
+        HIPCHK(mlp_launch_wgrad(m.dZ, m.H + l * RW, rows, kTrainGroups, m.part, m.g + kMlpOffW + l * WW, s));
+        if (l > 0) HIPCHK(mlp_launch_backward_data(m.dZ, m.WT + l * WW, rows, m.dH, s));
+    }
+    if (o->apply) {
+        HIPCHK(mlp_launch_adam(m.p, m.mo, m.ve, m.g, kMlpParams, (float)o->lr, (float)o->beta1, (float)o->beta2,
+                               (float)o->eps, o->step, s));
+        HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, s));
+    }
+    std::vector<double> lp(lb);
+    HIPCHK(hipMemcpyAsync(lp.data(), m.loss_part, lb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double sum = 0.0;
+    for (double v : lp) sum += v;
+    if (loss) *loss = sum;
+    return GC_OK;
+}
+
+gc_status gc_mlp_eval(gc_ctx *ctx, const double *pts, int64_t n, double *out) {
+    if (!ctx) return GC_EINVAL;
+    if (!ctx->mlp.set) return fail(ctx, GC_ESTATE, "no neural field (gc_mlp_set)");
+    gc_status st = check_mlp_points(ctx, pts, n, out);
+    if (st != GC_OK || n == 0) return st;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(mlp_launch_eval(ctx->mlp.args, pts, (int)n, out, ctx->stream));
+    return GC_OK;
+}
+
+gc_status gc_field_sample(gc_ctx *ctx, const double *pts, int64_t n, double *out) {
+    if (!ctx) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_field_sample before gc_load_field");
+    gc_status st = check_mlp_points(ctx, pts, n, out);
+    if (st != GC_OK || n == 0) return st;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(launch_field_sample(ctx->f, pts, (int)n, out, ctx->stream));
     return GC_OK;
 }
 

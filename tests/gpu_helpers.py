@@ -97,6 +97,21 @@ def compare(st, p, m, tol, what=""):
     return pos, u, mu
 
 
+def oracle_to_state(p, m):
+    """Oracle particles as a device state (gc_set_state layout: mu = mu_B / m,
+    zero compensation terms)."""
+    import torch
+    d = {"r": p["r"], "th": p["th"], "ph": p["ph"], "u": p["u"], "mu": p["mu_B"] / m,
+         "fr": p["fp"][:, 0], "fth": p["fp"][:, 1], "fph": p["fp"][:, 2], "fu": p["fp"][:, 3],
+         "dtp": p["dtp"], "s": p["s"], "ell": p["ell"], "t": p["t"]}
+    for k in ("cr", "cth", "cph", "cu", "ct"):
+        d[k] = np.zeros(len(p))
+    out = {k: torch.tensor(np.ascontiguousarray(v, dtype=np.float64)) for k, v in d.items()}
+    for k in ("k", "flags", "status", "step", "id", "ens"):
+        out[k] = torch.tensor(np.ascontiguousarray(p[k]).view(np.int32))
+    return out
+
+
 def small(n=1024, hours=2.0, **kw):
     wl = workloads.config_small(n=n, hours=hours)
     if kw:

@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_c(tmp_path):
     from paper_2403_06706_amd import _abi
-    structs = ["gc_options", "gc_field_desc", "gc_inject_desc", "gc_moment_spec", "gc_state_view", "gc_counters"]
+    structs = ["gc_options", "gc_field_desc", "gc_inject_desc", "gc_moment_spec", "gc_state_view", "gc_counters",
+               "gc_tune_space", "gc_tune_result", "gc_mlp_desc", "gc_mlp_train_opts"]
     src = tmp_path / "sz.c"
     body = "".join(f'printf("{s} %zu\\n", sizeof({s}));' for s in structs)
     src.write_text(f'#include <stdio.h>\n#include "gcpush.h"\nint main(void){{{body}return 0;}}\n')
@@ -59,6 +60,14 @@ def test_host_side_errors_without_device():
     assert st == _abi.GC_EINVAL
     assert b"block_size" in lib.gc_last_error(h)
     lib.gc_destroy(h)
+    o.block_size = 256
+    o.field_source = 7
+    st = lib.gc_create(C.byref(h), C.byref(o))
+    assert st == _abi.GC_EINVAL
+    assert b"field_source" in lib.gc_last_error(h)
+    lib.gc_destroy(h)
+    assert lib.gc_mlp_eval(None, None, 0, None) == _abi.GC_EINVAL
+    assert lib.gc_mlp_train_step(None, None, None, 1, None, None) == _abi.GC_EINVAL
 
 
 def test_create_reports_missing_device():
