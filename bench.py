@@ -168,6 +168,142 @@ def run_batched(args):
     }
 
 
+# matrix-core work of one network evaluation: value + 3 tangent rows through
+# 6 layers of 128 x 128 and the 128 -> 6 output layer, 2 flops per multiply-add
+MLP_FLOPS_PER_EVAL = 4 * 2 * (6 * 128 * 128 + 6 * 128)
+MLP_EVALS_PER_STEP = 2
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def run_mlp(args):
+    """Neural-field workload: electrons at 81 keV (lambda 0.5 AU) injected as in
+    the small spiral workload, pushed through the network trained by the
+    library on 49M positions drawn along trajectories of that workload (8,192
+    electrons over 2 h on the 64x32x64 grid).  The grid stays loaded as fallback
+    (cell binning) and as judge; the same particles are also timed through the
+    grid for the speed-up."""
+    import math
+    from dataclasses import replace
+    import numpy as np
+    import torch
+    import paper_2403_06706_amd as gcp
+    from paper_2403_06706_amd import neural
+    from synthetic import fields, workloads
+    from synthetic.mlp_setup import init_params, make_spec
+    small = workloads.config_small(n=8192)
+    f = fields.parker(small.grid)
+    t0 = time.time()
+    tr = gcp.Context(device=0)
+    tr.load_field(small.grid, f, "f64")
+    tr.inject(small.ensembles[0])
+    pos = neural.collect_positions(tr, small.dt, small.n_steps, every=16)
+    spec = make_spec(small.grid, f, seed=1)
+    tr.mlp_set(spec.freq, spec.r_ref, spec.scale, spec.power, init_params(seed=4))
+    g = small.grid
+    sigma = [0.1 * (g.r_max - g.r_min) / (g.nr - 1), 0.1 * math.pi / g.nth, 0.1 * 2 * math.pi / g.nph]
+    torch.cuda.synchronize()
+    t1 = time.time()
+    losses = neural.train(tr, pos, steps=3000, n_pairs=8192, sigma=sigma, beta_pair=100.0, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    held = gcp.Context(device=0)
+    held.load_field(small.grid, f, "f64")
+    held.inject(replace(small.ensembles[0], n=1024, seed=7))
+    hold = neural.collect_positions(held, small.dt, small.n_steps, every=64)
+    held.close()
+    ferr = neural.field_errors(tr, hold)
+    params = tr.mlp_params()
+    tr.close()
+    log(f"[bench] network trained in {t_train:.1f} s (set-up {t1 - t0:.1f} s), loss {losses[-1]:.3e}, "
+        f"field error vs grid {ferr}")
+
+    ens = replace(small.ensembles[0], n=args.mlp_particles, seed=args.seed)
+    steps = args.steps if args.steps is not None else 4
+
+    def timed(source):
+        ctx = gcp.Context(device=0, precision=args.precision, field_source=source, timing=True)
+        ctx.load_field(small.grid, f, args.store)
+        ctx.mlp_set(spec.freq, spec.r_ref, spec.scale, spec.power, params)
+        ctx.inject(ens)
+        start = {k: v.clone() for k, v in ctx.get_state().items()}
+        for _ in range(args.warmup):
+            ctx.advance(small.dt, 64)
+        torch.cuda.synchronize()
+        ctx.set_state(start)
+        del start
+        ctx.reset_counters()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            ctx.advance(small.dt, 64)
+            log(f"[bench] {source}: chunk {i + 1}/{steps}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        c = ctx.counters()
+        st = gcp.state_to_numpy(ctx.get_state())
+        ctx.close()
+        return el, c, st
+
+    el, c, st = timed("mlp")
+    value = c["particle_steps"] / el
+    gel, gc_, gst = timed("grid")
+    grid_value = gc_["particle_steps"] / gel
+    avg = c["push_ms"] / 1e3 / max(c["n_push"], 1)
+    per_launch = c["particle_steps"] / max(c["n_push"], 1)
+    flops = MLP_FLOPS_PER_EVAL * MLP_EVALS_PER_STEP * per_launch
+    achieved = flops / avg / 1e12
+    # trajectory difference network vs grid over the window (same particles, same draws)
+    both = (st["status"] == 0) & (gst["status"] == 0)
+    R = lambda s: np.stack([s["r"] * np.sin(s["th"]) * np.cos(s["ph"]), s["r"] * np.sin(s["th"]) * np.sin(s["ph"]),
+                            s["r"] * np.cos(s["th"])], 1)
+    same_k = both & (st["k"] == gst["k"])
+    d = np.linalg.norm(R(st)[same_k] - R(gst)[same_k], axis=1) / np.linalg.norm(R(gst)[same_k], axis=1)
+    out = {
+        "metric": "GC particle-steps/s on 1 MI355X, neural-field push",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": el / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"neural-field-spiral-{ens.n}", "particles": ens.n, "lambda_AU": ens.lambda_par / 1.495978707e11,
+                   "ekin_keV": 81.0, "dt_s": small.dt, "steps_per_bench_step": 64,
+                   "simulated_seconds": steps * 64 * small.dt, "state_precision": args.precision,
+                   "network": "64 Fourier frequencies -> 6 x 128 SiLU -> 6, BF16 weights, FP32 accumulation",
+                   "training": {"positions": int(pos.shape[1]), "samples": 3000 * 8192 * 2, "steps": 3000,
+                                "seconds": round(t_train, 2), "final_loss": losses[-1]},
+                   "field_error_vs_grid_rms": ferr},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None, "kernel": "gc::k_push_mlp",
+                     "avg_launch_ms": round(avg * 1e3, 3), "flops_per_particle_step": MLP_FLOPS_PER_EVAL * MLP_EVALS_PER_STEP,
+                     "algorithmic_flops_per_launch": flops},
+        "grid_push_same_particles": {"value": grid_value, "speedup_network_over_grid": value / grid_value},
+        "trajectory_difference_vs_grid": {"particles": int(same_k.sum()), "median": float(np.median(d)) if len(d) else None,
+                                          "max": float(d.max()) if len(d) else None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_mlp(args, small, f, spec, params)
+    return out
+
+
+def cpu_baseline_mlp(args, small, f, spec, params):
+    """The oracle integrator driven by the FP64 NumPy network, one point per
+    call (as it stands, single-threaded), on a bounded sample of the workload."""
+    from dataclasses import replace
+    import numpy as np
+    import oracle as O
+    from oracle import mlp_oracle as M
+    ens = replace(small.ensembles[0], n=96, seed=args.seed)
+    tab = O.make_ens_table([ens])
+    p = O.inject(O.Field(small.grid, f), tab, 0, ens, np.arange(ens.n, dtype=np.uint32))
+    pd = {k: np.asarray(v, dtype=np.float64) for k, v in params.items()}
+    cb = O.Field(small.grid, callback=lambda r, th, ph: M.field(spec, pd, np.array([r]), np.array([th]), np.array([ph]))[0])
+    t0 = time.perf_counter()
+    O.advance(cb, tab, p, small.dt, 64, 1)
+    el = time.perf_counter() - t0
+    steps = int(p["step"].sum())
+    return {"value": steps / el, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ens.n} electrons x 64 steps through the FP64 NumPy network (one point per call); "
+                      f"{steps} particle-steps in {el:.1f} s"}
+
+
 def cpu_baseline(args, wl, field):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import numpy as np
@@ -190,7 +326,8 @@ def cpu_baseline(args, wl, field):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1350, help="chunks of 64 steps (1350 = 24 h)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="chunks of 64 steps (default: 1350 = 24 h for the paper workload, 4 for the network)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--particles", type=int, default=1 << 20)
     ap.add_argument("--seed", type=int, default=0)
@@ -205,7 +342,8 @@ def main():
     ap.add_argument("--cpu-particles", type=int, default=98304)
     ap.add_argument("--cpu-steps", type=int, default=14400)
     ap.add_argument("--probe-copy", action="store_true", help="run a 256 MiB copy kernel first (counter calibration)")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batched"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "mlp"])
+    ap.add_argument("--mlp-particles", type=int, default=10 << 20)
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (batched workload)")
     args = ap.parse_args()
 
@@ -219,6 +357,11 @@ def main():
     if args.workload == "batched":
         print(json.dumps(run_batched(args)), flush=True)
         return
+    if args.workload == "mlp":
+        print(json.dumps(run_mlp(args)), flush=True)
+        return
+    if args.steps is None:
+        args.steps = 1350
     wl, field = build_workload(args)
     log(f"[bench] {wl.n_particles} electrons, {len(wl.ensembles)} ensembles; warmup {args.warmup}, "
         f"timed {args.steps} chunks of 64 steps")

@@ -33,7 +33,8 @@ struct MlpState {
     MlpArgs args{};
     void *mem = nullptr;
     float *p = nullptr, *mo = nullptr, *ve = nullptr, *g = nullptr;
-    __bf16 *W = nullptr, *WT = nullptr, *Wo = nullptr;
+    __bf16 *W = nullptr, *WT = nullptr, *Wo = nullptr;   // natural order (training)
+    __bf16 *We = nullptr, *Woe = nullptr;                 // evaluation order (mlp_perm)
     void *ws = nullptr;
     int64_t ws_rows = 0;
     __bf16 *H = nullptr, *dZ = nullptr;                  // H: activations H0..H6, [7][rows][128]
@@ -941,7 +942,8 @@ gc_status gc_mlp_set(gc_ctx *ctx, const gc_mlp_desc *d) {
     hipStream_t s = ctx->stream;
     const size_t nw = (size_t)kMlpDepth * kMlpWidth * kMlpWidth;
     const size_t fbytes = align256((size_t)kMlpParams * 4);
-    const size_t total = 4 * fbytes + 2 * align256(nw * 2) + align256((size_t)kMlpOutPad * kMlpWidth * 2);
+    const size_t total = 4 * fbytes + 3 * align256(nw * 2) + align256((size_t)kMlpOutPad * kMlpWidth * 2) +
+                         align256((size_t)kMlpEvalRows * kMlpWidth * 2);
     if (!m.mem) {
         if (hipMalloc(&m.mem, total) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate the network");
         char *c = static_cast<char *>(m.mem);
@@ -951,17 +953,19 @@ gc_status gc_mlp_set(gc_ctx *ctx, const gc_mlp_desc *d) {
         m.g = reinterpret_cast<float *>(c); c += fbytes;
         m.W = reinterpret_cast<__bf16 *>(c); c += align256(nw * 2);
         m.WT = reinterpret_cast<__bf16 *>(c); c += align256(nw * 2);
-        m.Wo = reinterpret_cast<__bf16 *>(c);
+        m.We = reinterpret_cast<__bf16 *>(c); c += align256(nw * 2);
+        m.Wo = reinterpret_cast<__bf16 *>(c); c += align256((size_t)kMlpOutPad * kMlpWidth * 2);
+        m.Woe = reinterpret_cast<__bf16 *>(c);
     }
     std::vector<float> host;
     to_device_layout(d->params, host);
     HIPCHK(hipMemcpyAsync(m.p, host.data(), (size_t)kMlpParams * 4, hipMemcpyHostToDevice, s));
     for (float *z : {m.mo, m.ve, m.g}) HIPCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(z), 0u, kMlpParams, s));
-    HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, s));
+    HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, m.We, m.Woe, s));
     MlpArgs &a = m.args;
     a = MlpArgs{};
-    a.W = m.W;
-    a.Wo = m.Wo;
+    a.W = m.We;
+    a.Wo = m.Woe;
     a.c = m.p + kMlpOffC;
     a.co = m.p + kMlpOffCo;
     for (int j = 0; j < kMlpFreq; ++j) {
@@ -1047,7 +1051,7 @@ gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, i
     if (o->apply) {
         HIPCHK(mlp_launch_adam(m.p, m.mo, m.ve, m.g, kMlpParams, (float)o->lr, (float)o->beta1, (float)o->beta2,
                                (float)o->eps, o->step, s));
-        HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, s));
+        HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, m.We, m.Woe, s));
     }
     std::vector<double> lp(lb);
     HIPCHK(hipMemcpyAsync(lp.data(), m.loss_part, lb * sizeof(double), hipMemcpyDeviceToHost, s));

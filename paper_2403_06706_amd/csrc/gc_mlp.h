@@ -29,151 +29,222 @@ constexpr int kMlpParams = kMlpOffCo + kMlpOutPad;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+
 // Everything an evaluation needs (passed by value to kernels).
 struct MlpArgs {
-    const __bf16 *W;      // [6][128][128] bf16, row = output unit
-    const __bf16 *Wo;     // [32][128] bf16 (rows >= 6 are zero)
+    const __bf16 *W;      // [6][128][128] bf16 in evaluation order: row = output unit; the
+                          // columns of layers 2..6 permuted within each 32-block (mlp_perm)
+    const __bf16 *Wo;     // [16][128] bf16, columns permuted like W, rows >= 6 zero
     const float *c;       // [6][128]
     const float *co;      // [32]
     float fa[kMlpFreq], fb[kMlpFreq], fn[kMlpFreq];   // frequencies a_j, b_j, n_j
     float r_min, inv_rspan, r_ref;
     float scale[kMlpOut], power[kMlpOut];
 };
+constexpr int kMlpEvalRows = 16;   // rows of the evaluation copy of the output layer
 
-// Per-wavefront LDS: 64 rows x (128 + 8) bf16 activations + 16 x 4 x 6 outputs.
-constexpr int kMlpLdsRow = kMlpWidth + 8;
-constexpr int kMlpLdsWaveBytes = 64 * kMlpLdsRow * 2 + 16 * 4 * kMlpOut * 4;
+// Column order of the evaluation weights of layers 2..6 and of the output
+// layer: slot kappa of a 32-column block holds the weight of hidden unit
+// mlp_perm(kappa) of that block.  With it, the hidden units a lane holds after
+// one layer (the 16x16 accumulator layout) are exactly the input slots it must
+// supply to the next (the B-operand layout), so activations never leave the
+// registers.
+__host__ __device__ constexpr int mlp_perm(int kappa) {
+    return 16 * ((kappa & 7) >> 2) + 4 * (kappa >> 3) + (kappa & 3);
+}
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float sigmoid_f(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_f(float z) { return z * sigmoid_f(z); }
 __device__ __forceinline__ float dsilu_f(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid_f(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
-// Evaluate the network and its three tangents for the 64 particles of this
-// wavefront (one per lane).  Must be called by all 64 lanes together.  Output
-// per lane: y[6] and dy[d][6] = dy / d(r, th, ph)[d].
+// Workgroup LDS of the evaluation: two staged weight matrices (rows padded to
+// 136 BF16 so that the 16 rows read by a 16-lane group start in distinct bank
+// quads) and the biases.
+constexpr int kMlpLdsRowW = kMlpWidth + 8;
+constexpr int kMlpLdsMat = kMlpWidth * kMlpLdsRowW;
+struct MlpLds {
+    __bf16 w[2][kMlpLdsMat];
+    float c[kMlpDepth * kMlpWidth];
+    float co[kMlpEvalRows];
+    float fa[kMlpFreq], fb[kMlpFreq], fn[kMlpFreq];
+};
+
+// Biases and frequencies into LDS (all threads of the workgroup; followed by
+// a barrier).
+__device__ __forceinline__ void mlp_lds_init(const MlpArgs &m, MlpLds &L) {
+    for (int i = threadIdx.x; i < kMlpDepth * kMlpWidth; i += blockDim.x) L.c[i] = m.c[i];
+    if (threadIdx.x < kMlpEvalRows) L.co[threadIdx.x] = threadIdx.x < kMlpOut ? m.co[threadIdx.x] : 0.0f;
+    if (threadIdx.x < kMlpFreq) {
+        L.fa[threadIdx.x] = m.fa[threadIdx.x];
+        L.fb[threadIdx.x] = m.fb[threadIdx.x];
+        L.fn[threadIdx.x] = m.fn[threadIdx.x];
+    }
+    __syncthreads();
+}
+
+// Matrix mi of the evaluation (0..5 hidden layers, 6 output layer), in 16-byte
+// pieces: 256 threads x 8 pieces cover a 128 x 128 matrix.  Branch-free: for
+// the 16-row output matrix the surplus pieces repeat its last piece and land in
+// rows that are never read.
+__device__ __forceinline__ void mlp_fetch(const MlpArgs &m, int mi, u32x4 v[8]) {
+    const bool hidden = mi < kMlpDepth;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(hidden ? m.W + (size_t)mi * kMlpWidth * kMlpWidth : m.Wo);
+    const int last = (hidden ? kMlpWidth : kMlpEvalRows) * (kMlpWidth / 8) - 1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[min(u * 256 + (int)threadIdx.x, last)];
+}
+
+__device__ __forceinline__ void mlp_store(const u32x4 v[8], __bf16 *dst) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = u * 256 + (int)threadIdx.x;
+        *reinterpret_cast<u32x4 *>(dst + (e >> 4) * kMlpLdsRowW + (e & 15) * 8) = v[u];
+    }
+}
+
+// Evaluate the network and its three tangents for the particles of a
+// 256-thread workgroup (one per thread).  All 256 threads must call it
+// together (it synchronizes the workgroup); the biases must be in L
+// (mlp_lds_init).  Output per thread: y[6] and dy[d][6] = dy / d(r, th, ph)[d].
 //
-// Matrix-core tiling (v_mfma_f32_32x32x16_bf16): particles are taken 16 at a
-// time; their 64 rows are [16 values | 16 d/dr] (row tile 0) and
-// [16 d/dth | 16 d/dph] (row tile 1).  In the MFMA accumulator layout a lane
-// holds the same rows of both tiles, so a value row and its three tangent rows
-// meet in one lane and the activation (silu, and silu' times the tangent) is
-// lane-local.  Between layers the activations go through the wavefront's LDS
-// tile to reach the input-operand layout.
-__device__ __forceinline__ void mlp_wave(const MlpArgs &m, float r, float th, float ph, unsigned char *lds,
-                                         float y[kMlpOut], float dy[3][kMlpOut]) {
+// Matrix-core tiling (v_mfma_f32_16x16x32_bf16; each wavefront takes its 64
+// particles in 4 passes of 16): the products are taken transposed, Z^T = W H^T,
+// so that the weights are the A operand and the activations the B operand.
+// The B operand has four column tiles: the values of the 16 particles and
+// their derivatives along r, th and ph.  In the 16x16 accumulator layout a lane
+// then holds, for its particle column, the same hidden units in all four
+// tiles: the activation (silu of the value, silu' times each tangent) is
+// lane-local, and with the column permutation of the weights (mlp_perm) its
+// results are already the next layer's B operand; activations never leave the
+// registers.  The weights go through LDS, one matrix at a time, shared by the
+// four wavefronts; the next matrix is fetched from global memory while the
+// current one is in use.  Per pass and hidden layer: 8 unit tiles x 4 k-blocks
+// x 4 column tiles = 128 MFMAs.
+__device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, float ph, MlpLds &L,
+                                          float y[kMlpOut], float dy[3][kMlpOut]) {
     const int l = threadIdx.x & 63;
-    const int half = l >> 5, mrow = l & 31;
-    __bf16 *act = reinterpret_cast<__bf16 *>(lds);
-    float *yout = reinterpret_cast<float *>(lds + 64 * kMlpLdsRow * 2);
+    const int g = l >> 4, col = l & 15;
     const float two_pi = 6.283185307179586f;
-    for (int q = 0; q < 4; ++q) {
-        // position of the particle of this lane's rows
-        const int src = 16 * q + (mrow & 15);
+    float out[4][kMlpOut];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int o = 0; o < kMlpOut; ++o) out[q][o] = 0.0f;
+    u32x4 pf[8];
+    __syncthreads();                                      // the previous call is done with both buffers
+    mlp_fetch(m, 0, pf);
+    mlp_store(pf, L.w[0]);
+    int cur = 0;
+    for (int p = 0; p < 4; ++p) {
+        const int src = 16 * p + col;                       // the particle of this lane's column
         const float pr = __shfl(r, src), pth = __shfl(th, src), pph = __shfl(ph, src);
         const float rt = (pr - m.r_min) * m.inv_rspan, tt = pth * 0.3183098861837907f;
-        const int kind0 = mrow >> 4;           // tile 0: 0 value, 1 d/dr; tile 1: 2 d/dth, 3 d/dph
-        floatx16 acc[2][4];
-        // ---------------- layer 1: inputs are the Fourier features
-        for (int t = 0; t < 2; ++t)
-            for (int nt = 0; nt < 4; ++nt) acc[t][nt] = floatx16{};
-        for (int s = 0; s < 8; ++s) {
-            bf16x8 a0, a1;
+        // layer-1 inputs: features 32s + 8g + i (phases 16s + 4g + i/2), natural order
+        bf16x8 B[4][4];                                     // [k block][value, d/dr, d/dth, d/dph]
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int j = 8 * s + 4 * half + i;            // phase index of features 2j, 2j+1
-                const float psi = two_pi * (m.fa[j] * rt + m.fb[j] * tt) + m.fn[j] * pph;
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+            for (int i2 = 0; i2 < 4; ++i2) {
+                const int j = 16 * s + 4 * g + i2;
+                const float fa = L.fa[j], fb = L.fb[j], fn = L.fn[j];
+                const float psi = two_pi * (fa * rt + fb * tt) + fn * pph;
                 float sn, cs;
                 __sincosf(psi, &sn, &cs);
-                const float dr = two_pi * m.fa[j] * m.inv_rspan, dth = 2.0f * m.fb[j], dph = m.fn[j];
-                // tile 0: value (kind 0) or d/dr (kind 1); tile 1: d/dth (2) or d/dph (3)
-                const float d0 = kind0 ? dr : 0.0f, d1 = kind0 ? dph : dth;
-                a0[2 * i] = (__bf16)(kind0 ? cs * d0 : sn);
-                a0[2 * i + 1] = (__bf16)(kind0 ? -sn * d0 : cs);
-                a1[2 * i] = (__bf16)(cs * d1);
-                a1[2 * i + 1] = (__bf16)(-sn * d1);
-            }
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(m.W + (size_t)(32 * nt + mrow) * kMlpWidth + 16 * s + 8 * half);
-                acc[0][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][nt], 0, 0, 0);
-                acc[1][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][nt], 0, 0, 0);
+                const float dr = two_pi * fa * m.inv_rspan, dth = 2.0f * fb;
+                B[s][0][2 * i2] = (__bf16)sn;
+                B[s][0][2 * i2 + 1] = (__bf16)cs;
+                B[s][1][2 * i2] = (__bf16)(cs * dr);
+                B[s][1][2 * i2 + 1] = (__bf16)(-sn * dr);
+                B[s][2][2 * i2] = (__bf16)(cs * dth);
+                B[s][2][2 * i2 + 1] = (__bf16)(-sn * dth);
+                B[s][3][2 * i2] = (__bf16)(cs * fn);
+                B[s][3][2 * i2 + 1] = (__bf16)(-sn * fn);
             }
         }
-        for (int layer = 0; layer < kMlpDepth; ++layer) {
-            if (layer > 0) {
-                // ---------------- layers 2..6: inputs from the LDS tile
-                for (int t = 0; t < 2; ++t)
-                    for (int nt = 0; nt < 4; ++nt) acc[t][nt] = floatx16{};
-                const __bf16 *Wl = m.W + (size_t)layer * kMlpWidth * kMlpWidth;
-                for (int s = 0; s < 8; ++s) {
-                    const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(act + mrow * kMlpLdsRow + 16 * s + 8 * half);
-                    const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(act + (32 + mrow) * kMlpLdsRow + 16 * s + 8 * half);
+        for (int mi = 0; mi <= kMlpDepth; ++mi) {
+            __syncthreads();                                // L.w[cur] holds matrix mi
+            mlp_fetch(m, mi < kMlpDepth ? mi + 1 : 0, pf);  // the next one (after the last: unused)
+            const __bf16 *Wl = L.w[cur] + col * kMlpLdsRowW + 8 * g;
+            if (mi < kMlpDepth) {
+                bf16x8 Bn[4][4];
+                const float *cl = L.c + mi * kMlpWidth + 4 * g;
+                // software pipeline over the 8 unit tiles: the products of tile t are
+                // issued before the activation of tile t - 1, which overlaps them
+                floatx4 prev[4];
 #pragma unroll
-                    for (int nt = 0; nt < 4; ++nt) {
-                        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Wl + (size_t)(32 * nt + mrow) * kMlpWidth + 16 * s + 8 * half);
-                        acc[0][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, acc[0][nt], 0, 0, 0);
-                        acc[1][nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, acc[1][nt], 0, 0, 0);
+                for (int t = 0; t <= 8; ++t) {
+                    floatx4 acc[4] = {floatx4{}, floatx4{}, floatx4{}, floatx4{}};
+                    if (t < 8) {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Wl + t * 16 * kMlpLdsRowW + 32 * s);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[s][q], acc[q], 0, 0, 0);
+                        }
                     }
+                    if (t > 0) {
+                        // lane holds units 16u + 4g + jj (u = t - 1): slots 8g + 4(u&1) + jj of k block u/2
+                        const int u = t - 1;
+                        const floatx4 bias = *reinterpret_cast<const floatx4 *>(cl + 16 * u);
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const float z = prev[0][jj] + bias[jj];
+                            const float sg = sigmoid_f(z);
+                            const float h = z * sg;
+                            const float ds = sg + h * (1.0f - sg);
+                            const int s2 = u >> 1, i = (u & 1) * 4 + jj;
+                            Bn[s2][0][i] = (__bf16)h;
+                            Bn[s2][1][i] = (__bf16)(ds * prev[1][jj]);
+                            Bn[s2][2][i] = (__bf16)(ds * prev[2][jj]);
+                            Bn[s2][3][i] = (__bf16)(ds * prev[3][jj]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) prev[q] = acc[q];
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            // epilogue: bias + silu on value rows, silu'(z) * tangent on tangent rows
-            const float *cl = m.c + layer * kMlpWidth;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int n = 32 * nt + mrow;
-                const float bias = cl[n];
+                for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int row = (j / 4) * 8 + half * 4 + (j % 4);        // value row of a particle
-                    const float z = acc[0][nt][j] + bias;
-                    const float ds = dsilu_f(z);
-                    act[row * kMlpLdsRow + n] = (__bf16)silu_f(z);
-                    act[(row + 16) * kMlpLdsRow + n] = (__bf16)(ds * acc[0][nt][j + 8]);
-                    act[(32 + row) * kMlpLdsRow + n] = (__bf16)(ds * acc[1][nt][j]);
-                    act[(48 + row) * kMlpLdsRow + n] = (__bf16)(ds * acc[1][nt][j + 8]);
+                    for (int q = 0; q < 4; ++q) B[s][q] = Bn[s][q];
+            } else {
+                // output layer: one 16-row tile (rows >= 6 zero)
+                floatx4 o[4] = {floatx4{}, floatx4{}, floatx4{}, floatx4{}};
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Wl + 32 * s);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        o[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[s][q], o[q], 0, 0, 0);
                 }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-        // ---------------- output layer (one padded 32-wide tile)
-        floatx16 o0 = {}, o1 = {};
-        for (int s = 0; s < 8; ++s) {
-            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(act + mrow * kMlpLdsRow + 16 * s + 8 * half);
-            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(act + (32 + mrow) * kMlpLdsRow + 16 * s + 8 * half);
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(m.Wo + (size_t)mrow * kMlpWidth + 16 * s + 8 * half);
-            o0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b, o0, 0, 0, 0);
-            o1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b, o1, 0, 0, 0);
-        }
-        if (mrow < kMlpOut) {
-            const float bias = m.co[mrow];
+                // outputs 0..3 of particle col sit in lane col, outputs 4..5 in lane 16 + col;
+                // the particle's own lane is 16p + col
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int p = (j / 4) * 8 + half * 4 + (j % 4);              // particle within the pass
-                yout[(p * 4 + 0) * kMlpOut + mrow] = o0[j] + bias;
-                yout[(p * 4 + 1) * kMlpOut + mrow] = o0[j + 8];
-                yout[(p * 4 + 2) * kMlpOut + mrow] = o1[j];
-                yout[(p * 4 + 3) * kMlpOut + mrow] = o1[j + 8];
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if ((l >> 4) == q) {
-            const int p = l & 15;
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int c = 0; c < kMlpOut; ++c) {
-                y[c] = yout[(p * 4 + 0) * kMlpOut + c];
-                dy[0][c] = yout[(p * 4 + 1) * kMlpOut + c];
-                dy[1][c] = yout[(p * 4 + 2) * kMlpOut + c];
-                dy[2][c] = yout[(p * 4 + 3) * kMlpOut + c];
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const float v0 = __shfl(o[q][jj], col);
+                        const float v1 = __shfl(o[q][jj], 16 + col);
+                        out[q][jj] = g == p ? v0 : out[q][jj];
+                        if (jj < 2) out[q][4 + jj] = g == p ? v1 : out[q][4 + jj];
+                    }
             }
+            mlp_store(pf, L.w[cur ^ 1]);
+            cur ^= 1;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int o = 0; o < kMlpOut; ++o) {
+        y[o] = out[0][o] + L.co[o];
+        dy[0][o] = out[1][o];
+        dy[1][o] = out[2][o];
+        dy[2][o] = out[3][o];
     }
 }
 

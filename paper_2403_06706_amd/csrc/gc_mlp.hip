@@ -219,7 +219,9 @@ __global__ void k_adam(float *p, float *mo, float *ve, const float *g, int n, fl
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-__global__ void k_mlp_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo) {
+// W, WT, Wo: natural order (training products); We, Woe: evaluation order
+// (columns of layers 2..6 and of the output layer permuted by mlp_perm).
+__global__ void k_mlp_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, __bf16 *We, __bf16 *Woe) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < kMlpDepth * kMlpWidth * kMlpWidth) {
         const int layer = i / (kMlpWidth * kMlpWidth), e = i % (kMlpWidth * kMlpWidth);
@@ -227,8 +229,14 @@ __global__ void k_mlp_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo)
         const __bf16 v = (__bf16)p[kMlpOffW + i];
         W[i] = v;
         WT[(size_t)layer * kMlpWidth * kMlpWidth + k * kMlpWidth + n] = v;
+        const int ks = layer == 0 ? k : (k & ~31) + mlp_perm(k & 31);
+        We[i] = (__bf16)p[kMlpOffW + (size_t)layer * kMlpWidth * kMlpWidth + n * kMlpWidth + ks];
     }
     if (i < kMlpOutPad * kMlpWidth) Wo[i] = (__bf16)p[kMlpOffWo + i];
+    if (i < kMlpEvalRows * kMlpWidth) {
+        const int n = i / kMlpWidth, k = i % kMlpWidth;
+        Woe[i] = n < kMlpOut ? (__bf16)p[kMlpOffWo + n * kMlpWidth + (k & ~31) + mlp_perm(k & 31)] : (__bf16)0.0f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -236,13 +244,13 @@ __global__ void k_mlp_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo)
 // pts SoA: r[n], th[n], ph[n]; out: [n][12].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_mlp_eval(MlpArgs m, const double *pts, int n, double *out) {
-    extern __shared__ unsigned char lds_raw[];
-    unsigned char *lds = lds_raw + (threadIdx.x >> 6) * kMlpLdsWaveBytes;
+    __shared__ MlpLds L;
+    mlp_lds_init(m, L);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int ii = i < n ? i : n - 1;                 // idle lanes evaluate a valid point
     const double r = pts[ii], th = pts[n + ii], ph = pts[2 * n + ii];
     float y[kMlpOut], dy[3][kMlpOut];
-    mlp_wave(m, (float)r, (float)th, (float)ph, lds, y, dy);
+    mlp_block(m, (float)r, (float)th, (float)ph, L, y, dy);
     double g[12];
     const bool ok = mlp_assemble<double>(m, r, th, y, dy, g);
     if (i < n)
@@ -338,15 +346,16 @@ hipError_t mlp_launch_adam(float *p, float *mo, float *ve, const float *g, int n
     return hipGetLastError();
 }
 
-hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, hipStream_t s) {
+hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, __bf16 *We, __bf16 *Woe,
+                              hipStream_t s) {
     const int n = kMlpDepth * kMlpWidth * kMlpWidth;
-    hipLaunchKernelGGL(k_mlp_refresh, dim3((n + 255) / 256), dim3(256), 0, s, p, W, WT, Wo);
+    hipLaunchKernelGGL(k_mlp_refresh, dim3((n + 255) / 256), dim3(256), 0, s, p, W, WT, Wo, We, Woe);
     return hipGetLastError();
 }
 
 hipError_t mlp_launch_eval(const MlpArgs &m, const double *pts, int n, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_eval, dim3((n + 255) / 256), dim3(256), 4 * kMlpLdsWaveBytes, s, m, pts, n, out);
+    hipLaunchKernelGGL(k_mlp_eval, dim3((n + 255) / 256), dim3(256), 0, s, m, pts, n, out);
     return hipGetLastError();
 }
 

@@ -29,7 +29,8 @@ hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, int 
                                float *dWo, float *dco, hipStream_t s);
 hipError_t mlp_launch_adam(float *p, float *mo, float *ve, const float *g, int n, float lr, float b1, float b2,
                            float eps, int step, hipStream_t s);
-hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, hipStream_t s);
+hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, __bf16 *We, __bf16 *Woe,
+                              hipStream_t s);
 hipError_t mlp_launch_eval(const MlpArgs &m, const double *pts, int n, double *out, hipStream_t s);
 hipError_t launch_field_sample(const FieldDev &f, const double *pts, int n, double *out, hipStream_t s);
 hipError_t launch_push_mlp(const PushArgs &a, const MlpArgs &m, int precision, hipStream_t s);

@@ -236,9 +236,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 // ---------------------------------------------------------------------------
 // Push with the neural field as field source.  The same step as advance_slot,
-// but the field evaluation is a wavefront-wide matrix-core product
-// (mlp_wave), so every lane of the wavefront takes part in every evaluation:
-// lanes without work (exited, finished their stages, or past the active
+// but the field evaluation is a workgroup-wide matrix-core product
+// (mlp_block), so every thread of the workgroup takes part in every
+// evaluation and the step and stage loops run in lockstep over the workgroup:
+// threads without work (exited, finished their stages, or past the active
 // prefix) evaluate at their last position and ignore the result.
 // ---------------------------------------------------------------------------
 template <int PREC>
@@ -246,11 +247,11 @@ __global__ __launch_bounds__(256) void k_push_mlp(PushArgs a, MlpArgs m) {
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
     constexpr bool kKahan = PrecT<PREC>::kKahan;
-    extern __shared__ unsigned char lds_raw[];
-    unsigned char *lds = lds_raw + (threadIdx.x >> 6) * kMlpLdsWaveBytes;
+    __shared__ MlpLds L;
     const uint32_t n = *a.n_active;
     const uint32_t nb = (n + blockDim.x - 1) / blockDim.x, bidx = blockIdx.x;
     if (bidx >= nb) return;                                   // whole workgroup idle
+    mlp_lds_init(m, L);
     const uint32_t q8 = nb >> 3, rem = nb & 7u, xcd = bidx & 7u, pos = bidx >> 3;
     const uint32_t lb = (xcd < rem ? xcd * (q8 + 1) : rem * (q8 + 1) + (xcd - rem) * q8) + pos;
     const uint32_t slot = lb * blockDim.x + threadIdx.x;
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(256) void k_push_mlp(PushArgs a, MlpArgs m) {
     const double r_in = e.r_in, r_out = e.r_out, th_lo = a.f.th_lo, th_hi = a.f.th_hi;
 
     for (int it = 0; it < a.n_steps; ++it) {
-        if (__ballot(alive) == 0) break;                      // uniform
+        if (!__syncthreads_or(alive)) break;                  // uniform over the workgroup
         R Fn[4] = {0, 0, 0, 0}, Fs[4] = {0, 0, 0, 0}, vpn = 0, vps = 0, tau = 1;
         R mun = 0, ell_new = 0;
         if (alive && (flags & GC_FLAG_PENDING)) {
@@ -289,9 +290,9 @@ __global__ __launch_bounds__(256) void k_push_mlp(PushArgs a, MlpArgs m) {
         R px = (R)X0, pth = (R)X1, pph = (R)X2, pu = (R)X3;
         int stage = 0;
         bool need = alive, bad = false;
-        while (__ballot(need) != 0) {                         // uniform
+        while (__syncthreads_or(need)) {                      // uniform over the workgroup
             float y[kMlpOut], dy[3][kMlpOut];
-            mlp_wave(m, (float)px, (float)pth, (float)pph, lds, y, dy);
+            mlp_block(m, (float)px, (float)pth, (float)pph, L, y, dy);
             if (!need) continue;
             R g[12];
             if (!mlp_assemble<R>(m, px, pth, y, dy, g)) { bad = true; need = false; continue; }
@@ -388,7 +389,7 @@ template <int PREC>
 static hipError_t launch_mlp_t(const PushArgs &a, const MlpArgs &m, hipStream_t s) {
     const uint32_t nb = (a.n_slots + 255) / 256;
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_push_mlp<PREC>), dim3(nb), dim3(256), 4 * kMlpLdsWaveBytes, s, a, m);
+    hipLaunchKernelGGL((k_push_mlp<PREC>), dim3(nb), dim3(256), 0, s, a, m);
     return hipGetLastError();
 }
 
