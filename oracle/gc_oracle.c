@@ -300,25 +300,11 @@ static int finite4(const double X[4])
     return isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]) && isfinite(X[3]);
 }
 
-/* replay (optional): collide exactly at the given step counts (0xFFFFFFFF ends
- * the list), ignore the free-path test and the exit test, stop after
- * replay_steps steps.  Used to compare a reduced-precision trajectory with this
- * FP64 one under the same collision schedule when round-off has moved a
- * collision or an exit by a step. */
-typedef struct { const uint32_t *coll; int32_t depth; uint32_t target; } replay_t;
-
-static void advance_one_r(const or_field *f, const or_ens *e, or_particle *p, double dt, int64_t n_steps,
-                          const or_log *log, int64_t pi, double *traj, const replay_t *rp)
+static void advance_one(const or_field *f, const or_ens *e, or_particle *p, double dt, int64_t n_steps,
+                        const or_log *log, int64_t pi, double *traj)
 {
-    int32_t next = 0;
     for (int64_t it = 0; it < n_steps; ++it) {
         if (p->status != OR_ACTIVE) return;
-        if (rp) {
-            if (p->step >= rp->target) return;
-            while (next < rp->depth && rp->coll[next] != 0xFFFFFFFFu && rp->coll[next] < p->step) ++next;
-            if (next < rp->depth && rp->coll[next] == p->step) { p->flags |= OR_PENDING; ++next; }
-            else p->flags &= ~OR_PENDING;
-        }
         double X[4] = { p->r, p->th, p->ph, p->u };
         double g[12];
         if (!or_field_eval(f, X[0], X[1], X[2], g)) { p->status = OR_NONFINITE; return; }
@@ -350,9 +336,7 @@ static void advance_one_r(const or_field *f, const or_ens *e, or_particle *p, do
         or_pc_correct(X, Fn, Fs, Fp, dt, tau, Xn);
         /* READING of Eq. 9: the path covered in the step is the trapezoid of |v_par| at X^n and X*. */
         double ds = 0.5 * (fabs(vpn) + fabs(vps)) * dt;
-        if (rp) {
-            p->s += ds;
-        } else if (e->lambda > 0.0) {
+        if (e->lambda > 0.0) {
             if (e->collision_mode == 1) {
                 double a[4];
                 draw(e, p->id, p->step, PURPOSE_STEPDRAW, a);
@@ -369,28 +353,8 @@ static void advance_one_r(const or_field *f, const or_ens *e, or_particle *p, do
         p->step += 1;
         if (traj) for (int c = 0; c < 4; ++c) traj[(it + 1) * 4 + c] = Xn[c];
         if (!finite4(Xn)) { p->status = OR_NONFINITE; return; }
-        if (rp) continue;
         if (outside(f, e, p->r, p->th)) { p->status = OR_EXITED; return; }
         if (e->max_steps > 0 && p->step >= (uint64_t)e->max_steps) { p->status = OR_FINISHED; return; }
-    }
-}
-
-static void advance_one(const or_field *f, const or_ens *e, or_particle *p, double dt, int64_t n_steps,
-                        const or_log *log, int64_t pi, double *traj)
-{
-    advance_one_r(f, e, p, dt, n_steps, log, pi, traj, NULL);
-}
-
-void or_advance_replay(const or_field *f, const or_ens *ens_table, or_particle *p, int64_t n, double dt,
-                       const uint32_t *target_steps, const uint32_t *coll_steps, int32_t depth, int nthreads)
-{
-#ifdef _OPENMP
-    if (nthreads <= 0) nthreads = omp_get_max_threads();
-#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
-#endif
-    for (int64_t i = 0; i < n; ++i) {
-        replay_t rp = { coll_steps + (size_t)i * depth, depth, target_steps[i] };
-        advance_one_r(f, &ens_table[p[i].ens], &p[i], dt, (int64_t)target_steps[i], NULL, i, NULL, &rp);
     }
 }
 

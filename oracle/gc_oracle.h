@@ -109,11 +109,6 @@ void or_inject(const or_field *f, const or_ens *e, uint32_t ens_index, const or_
                const uint32_t *ids, int64_t n, or_particle *out);
 void or_advance(const or_field *f, const or_ens *ens_table, or_particle *p, int64_t n,
                 double dt, int64_t n_steps, int nthreads, const or_log *log);
-/* Replay: particle i takes exactly target_steps[i] steps, collides at the step
- * counts listed in coll_steps[i][0..depth) (0xFFFFFFFF terminates), and skips
- * the free-path and exit tests. */
-void or_advance_replay(const or_field *f, const or_ens *ens_table, or_particle *p, int64_t n, double dt,
-                       const uint32_t *target_steps, const uint32_t *coll_steps, int32_t depth, int nthreads);
 void or_advance_traj(const or_field *f, const or_ens *ens_table, or_particle *p,
                      double dt, int64_t n_steps, double *traj);
 int64_t or_moments_size(const or_moment_spec *spec);

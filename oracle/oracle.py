@@ -75,7 +75,6 @@ def _load():
     L.or_pc_correct.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
     L.or_inject.argtypes = [C.POINTER(_Field), C.POINTER(_Ens), C.c_uint32, C.POINTER(_Inject), P, C.c_int64, P]
     L.or_advance.argtypes = [C.POINTER(_Field), P, P, C.c_int64, C.c_double, C.c_int64, C.c_int, C.POINTER(_Log)]
-    L.or_advance_replay.argtypes = [C.POINTER(_Field), P, P, C.c_int64, C.c_double, P, P, C.c_int32, C.c_int]
     L.or_advance_traj.argtypes = [C.POINTER(_Field), P, P, C.c_double, C.c_int64, P]
     L.or_moments_size.argtypes = [C.POINTER(_MomentSpec)]
     L.or_moments_size.restype = C.c_int64
@@ -208,19 +207,6 @@ def advance(field: Field, ens_table, particles: np.ndarray, dt: float, n_steps: 
     lib.or_advance(field.ref, C.cast(ens_table, C.c_void_p), _ptr(particles), n, dt, int(n_steps),
                    int(nthreads), C.byref(log))
     return logs
-
-
-def advance_replay(field: Field, ens_table, particles: np.ndarray, dt: float, target_steps: np.ndarray,
-                   coll_steps: np.ndarray, nthreads: int = 0):
-    """Advance in place under a prescribed collision schedule (see gc_oracle.h)."""
-    assert particles.dtype == PARTICLE_DTYPE and particles.flags.c_contiguous
-    ts = np.ascontiguousarray(target_steps, dtype=np.uint32)
-    cs = np.ascontiguousarray(coll_steps, dtype=np.uint32)
-    assert cs.shape[0] == len(particles) and len(ts) == len(particles)
-    if field.callback is not None:
-        nthreads = 1
-    lib.or_advance_replay(field.ref, C.cast(ens_table, C.c_void_p), _ptr(particles), len(particles), dt,
-                          _ptr(ts), _ptr(cs), int(cs.shape[1]), int(nthreads))
 
 
 def advance_traj(field: Field, ens_table, particle: np.ndarray, dt: float, n_steps: int) -> np.ndarray:

@@ -4,11 +4,14 @@ Forms: FP32 field interpolation and right-hand side with FP64 position/u/time
 accumulators; FP32 throughout with Kahan-compensated accumulation; the latter
 with FP16 field storage (per-component power-of-two scales).
 
-Round-off can move a collision (or an exit) by a step.  Each device run logs
-its collision steps; the oracle then replays the same collision schedule and
-step count, and the trajectories are compared at identical times.  Bar: 1e-4
-relative position error over 2 h for the FP32 forms with FP32 fields (the
-spec tolerance); the FP16-field form is reported, not bounded.
+The oracle runs on its own (FP64) and logs its collision steps; so does the
+device.  Round-off can move a collision (or an exit) by a step, a decision
+taken in floating point.  Particles whose decisions agree are compared to the
+1e-4 bar (relative position over 2 h); a particle whose decisions differ must
+have been marginal: at the first differing decision the oracle's own free-path
+margin |s - l| / l (or its distance to the exit shell) is within the reach of
+FP32 round-off.  The FP16-field forms move the field itself; their errors are
+reported, not bounded.
 """
 import json
 import os
@@ -23,6 +26,8 @@ from synthetic import M_ELECTRON, C_LIGHT, E_CHARGE
 
 pytestmark = pytest.mark.gpu
 DEPTH = 256
+FLIP_MARGIN = 1e-4        # relative: free-path or exit-shell margin a FP32 run may decide the other way
+NONE = 0xFFFFFFFF
 OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
 
 
@@ -37,6 +42,24 @@ def _energy_ev(field, r, th, ph, u, mu):
     return out
 
 
+def _decision_margin(wl, of, tab, i, st, glog, p, olog):
+    """Oracle margin at the first decision on which device and oracle differ
+    for particle i: |s - l| / l after the step whose end decided a collision,
+    else the relative distance to the exit shell after the earlier exit."""
+    e = wl.ensembles[0]
+    diff = np.nonzero(glog[i] != olog[i])[0]
+    q = O.inject(of, tab, 0, e, np.array([i], dtype=np.uint32))
+    if len(diff):
+        d = diff[0]
+        n0 = int(min(glog[i][d], olog[i][d]))
+        O.advance(of, tab, q, wl.dt, n0, 1)
+        return abs(q["s"][0] - q["ell"][0]) / q["ell"][0]
+    n0 = int(min(st["step"][i], p["step"][i]))
+    O.advance(of, tab, q, wl.dt, n0 - 1, 1)        # the last step both sides took
+    r = q["r"][0]
+    return min(abs(r - e.r_in) / e.r_in, abs(r - e.r_out) / e.r_out)
+
+
 @pytest.mark.parametrize("prec,store,tol", [("f32_acc64", "f32", 1e-4), ("f32_kahan", "f32", 1e-4),
                                             ("f32_kahan", "f16", None), ("f64", "f16", None)])
 def test_form_error_against_fp64_oracle(prec, store, tol):
@@ -44,34 +67,33 @@ def test_form_error_against_fp64_oracle(prec, store, tol):
     f64 = field_of(wl)
     f_ref = stored(f64, "f32")                    # FP64 state with FP32 fields is the reference
     say(f"precision form {prec} / fields {store}")
-    st, log = run_gpu(wl, f_ref if store == "f32" else f64, store_dtype=store, precision=prec, log_depth=DEPTH)
-    normal, *_ = run_oracle(wl, f_ref)
-    flips = int(np.sum((st["k"] != normal["k"]) | (st["step"] != normal["step"]) | (st["status"] != normal["status"])))
-    over = int(np.sum(st["k"] > DEPTH))
-    of = O.Field(wl.grid, f_ref)
-    tab = O.make_ens_table(wl.ensembles)
-    rep = O.inject(of, tab, 0, wl.ensembles[0], np.arange(wl.ensembles[0].n, dtype=np.uint32))
-    O.advance_replay(of, tab, rep, wl.dt, st["step"], log)
-    ok = st["k"] <= DEPTH
-    sub = {k: v[ok] for k, v in st.items()}
-    pos, u, mu = rel_errors(sub, rep[ok], M_ELECTRON)
+    st, glog = run_gpu(wl, f_ref if store == "f32" else f64, store_dtype=store, precision=prec, log_depth=DEPTH)
+    p, logs, of, tab = run_oracle(wl, f_ref, log_depth=DEPTH)
+    olog = logs[0]
+    assert int(np.sum(st["k"] > DEPTH)) == 0 and int(np.sum(p["k"] > DEPTH)) == 0
+    same = ((st["k"] == p["k"]) & (st["step"] == p["step"]) & (st["status"] == p["status"])
+            & np.all(glog == olog, axis=1))
+    flipped = np.nonzero(~same)[0]
+    sub = {k: v[same] for k, v in st.items()}
+    pos, u, mu = rel_errors(sub, p[same], M_ELECTRON)
     e_gpu = _energy_ev(of, sub["r"], sub["th"], sub["ph"], sub["u"], sub["mu"])
-    e_ora = _energy_ev(of, rep["r"][ok], rep["th"][ok], rep["ph"][ok], rep["u"][ok], rep["mu_B"][ok] / M_ELECTRON)
+    e_ora = _energy_ev(of, p["r"][same], p["th"][same], p["ph"][same], p["u"][same], p["mu_B"][same] / M_ELECTRON)
     de = np.abs(e_gpu - e_ora)
     report = {"form": prec, "fields": store, "particles": int(len(st["r"])), "steps": wl.n_steps,
-              "flips": flips, "beyond_log": over, "max_rel_pos": float(pos.max()), "median_rel_pos": float(np.median(pos)),
-              "max_rel_u": float(u.max()), "max_rel_mu": float(mu.max()), "max_abs_energy_eV": float(de.max()),
-              "median_abs_energy_eV": float(np.median(de))}
+              "agreeing": int(same.sum()), "flips": int(len(flipped)), "max_rel_pos": float(pos.max()),
+              "median_rel_pos": float(np.median(pos)), "max_rel_u": float(u.max()), "max_rel_mu": float(mu.max()),
+              "max_abs_energy_eV": float(de.max()), "median_abs_energy_eV": float(np.median(de))}
     say("  " + json.dumps(report))
     os.makedirs(OUT, exist_ok=True)
     with open(os.path.join(OUT, f"precision_{prec}_{store}.json"), "w") as fh:
         json.dump(report, fh)
-    assert over == 0
-    # replayed trajectories use the device's collision schedule: same collision count
-    assert np.array_equal(rep["k"][ok], sub["k"])
     if tol is not None:
         assert pos.max() <= tol, report
         assert u.max() <= tol and mu.max() <= tol, report
+        assert len(flipped) <= 0.01 * len(st["r"]), report
+        for i in flipped:
+            m = _decision_margin(wl, of, tab, i, st, glog, p, olog)
+            assert m <= FLIP_MARGIN, (int(i), m)
 
 
 @pytest.mark.parametrize("prec", ["f32_kahan"])

@@ -121,15 +121,3 @@ def test_paper_collision_time_scale():
     assert v / C_LIGHT == pytest.approx(0.5049, abs=2e-4)
     t_coll = 0.5 * AU / v
     assert 400.0 < t_coll < 600.0 and 54.0 / t_coll == pytest.approx(0.1, abs=0.02)
-
-
-def test_replay_of_own_schedule_is_exact():
-    """Replaying the oracle's own collision log and step counts reproduces its
-    trajectories bitwise (the replay mode used for reduced-precision checks)."""
-    p, (steps, mu, ell), ell0, _, e = _run(n=300, steps=500, depth=256)
-    field = O.Field(G, STRAIGHT)
-    tab = O.make_ens_table([e])
-    q = O.inject(field, tab, 0, e, np.arange(300, dtype=np.uint32))
-    O.advance_replay(field, tab, q, 1.0, p["step"], steps)
-    for k in ("r", "th", "ph", "u", "mu_B", "k", "step", "s", "ell"):
-        assert np.array_equal(p[k], q[k]), k
