@@ -15,19 +15,22 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgcpush.so")
-SOURCES = ["gc_api.cpp", "gc_push.hip", "gc_kernels.hip", "gc_order.hip", "gc_mlp.hip"]
+SOURCES = ["gc_api.cpp", "gc_push.hip", "gc_push_mlp.hip", "gc_kernels.hip", "gc_order.hip", "gc_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", "-ffp-contract=fast"]
+# Matrix-core sources: MFMA results in ordinary VGPRs (the activation code reads
+# every accumulator; with AGPR results each read is an extra v_accvgpr_read).
+EXTRA = {"gc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "gc_push_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
-    cmd = [HIPCC] + CFLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + CFLAGS + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     subprocess.run(cmd, check=True, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     return obj
 

@@ -120,13 +120,19 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const __bf16 *D, const __bf16
         }
 }
 
-// out[i] (+)= sum_g partial[g][i], i < count (deterministic order)
+// out[i] (+)= sum_g partial[g][i], i < count (deterministic order; four
+// independent partial sums keep several loads in flight)
 __global__ void k_sum_partials(const float *partial, int groups, int count, float *out, int accumulate) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    float s = 0.0f;
-    for (int g = 0; g < groups; ++g) s += partial[(size_t)g * count + i];
-    out[i] = accumulate ? out[i] + s : s;
+    float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    int g = 0;
+    for (; g + 4 <= groups; g += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += partial[(size_t)(g + u) * count + i];
+    for (; g < groups; ++g) s[0] += partial[(size_t)g * count + i];
+    const float t = (s[0] + s[1]) + (s[2] + s[3]);
+    out[i] = accumulate ? out[i] + t : t;
 }
 
 // ---------------------------------------------------------------------------
