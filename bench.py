@@ -68,7 +68,39 @@ def build_workload(args):
     return wl, np.ascontiguousarray(field)
 
 
-def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False):
+def gather_ceiling(ctx, wl, store):
+    """Gather-only probe (gc_gather_probe) and one push chunk from the same
+    state (after the warmup), each timed with HIP events on the library's
+    stream: the push as a fraction of the achievable gather rate."""
+    import torch
+    snap = {k: v.clone() for k, v in ctx.get_state().items()}
+    out = {}
+    for what in ("probe", "push"):
+        ctx.set_state(snap)
+        ctx.advance(wl.dt, 1)                    # reorder (live prefix, cell order) and one step
+        torch.cuda.synchronize()
+        ctx.reset_counters()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        if what == "probe":
+            ctx.gather_probe(wl.dt, 64)
+        else:
+            ctx.advance(wl.dt, 64)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        c = ctx.counters()
+        ms = e0.elapsed_time(e1) if what == "probe" else c["push_ms"]
+        out[what] = {"particle_steps": c["particle_steps"], "ms": ms,
+                     "rate": c["particle_steps"] / (ms * 1e-3)}
+    ctx.set_state(snap)
+    probe, push = out["probe"], out["push"]
+    return {"kernel": "gc::k_gather_probe", "state": "after the warmup chunks, 64 steps",
+            "gather_rate_particle_steps_per_s": probe["rate"],
+            "gather_GBps": probe["rate"] * BYTES_PER_STEP[store] / 1e9,
+            "push_rate_same_state": push["rate"], "push_frac_of_gather_ceiling": push["rate"] / probe["rate"]}
+
+
+def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False, probe_ceiling=False):
     import torch
     import paper_2403_06706_amd as gcp
     ctx = gcp.Context(device=0, precision=precision, order="bin", chunk_steps=64, block_size=args.block,
@@ -82,6 +114,7 @@ def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False)
         ctx.advance(wl.dt, 64)
         ctx.moments(spec)
     torch.cuda.synchronize()
+    ceiling = gather_ceiling(ctx, wl, store=args.store) if (probe_ceiling and warmup > 0) else None
     ctx.set_state(start)                      # time the workload from injection
     ctx.reset_counters()
     if probe:   # traffic-counter calibration: a plain copy of known size before the push
@@ -103,7 +136,7 @@ def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False)
     final = gcp.state_to_numpy(ctx.get_state())
     m = mom.cpu().numpy() if mom is not None else None
     ctx.close()
-    return elapsed, c, final, m
+    return elapsed, c, final, m, ceiling
 
 
 def run_batched(args):
@@ -366,7 +399,8 @@ def main():
     wl, field = build_workload(args)
     log(f"[bench] {wl.n_particles} electrons, {len(wl.ensembles)} ensembles; warmup {args.warmup}, "
         f"timed {args.steps} chunks of 64 steps")
-    elapsed, c, final, mom = run_gpu(args, wl, field, args.precision, args.steps, args.warmup, probe=args.probe_copy)
+    elapsed, c, final, mom, ceiling = run_gpu(args, wl, field, args.precision, args.steps, args.warmup,
+                                              probe=args.probe_copy, probe_ceiling=not args.probe_copy)
     value = c["particle_steps"] / elapsed
     log(f"[bench] {c['particle_steps']:.3e} particle-steps in {elapsed:.2f} s -> {value:.3e}/s; "
         f"push {c['push_ms']:.0f} ms over {c['n_push']} launches, reorder {c['reorder_ms']:.0f} ms")
@@ -387,7 +421,8 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": "gc::k_push", "avg_launch_ms": round(avg_push_s * 1e3, 4),
                 "algorithmic_bytes_per_launch": round(algo_bytes),
-                "bytes_per_particle_step": BYTES_PER_STEP[args.store]}
+                "bytes_per_particle_step": BYTES_PER_STEP[args.store],
+                "gather_ceiling": ceiling}
 
     out = {
         "metric": "GC particle-steps/s on 1 MI355X at <=1e-4 rel err vs FP64 oracle",
@@ -406,13 +441,13 @@ def main():
 
     if args.forms > 0:
         forms = {}
-        base_el, base_c, _, _ = run_gpu(args, wl, field, args.precision, args.forms, 1)
+        base_el, base_c, _, _, _ = run_gpu(args, wl, field, args.precision, args.forms, 1)
         base = base_c["particle_steps"] / base_el
         forms[args.precision] = {"value": base}
         for prec in ("f32_acc64", "f32_kahan"):
             if prec == args.precision:
                 continue
-            el, cc, _, _ = run_gpu(args, wl, field, prec, args.forms, 1)
+            el, cc, _, _, _ = run_gpu(args, wl, field, prec, args.forms, 1)
             v = cc["particle_steps"] / el
             forms[prec] = {"value": v, "speedup": v / base}
         out["forms_first_chunks"] = {"chunks": args.forms, **forms}

@@ -337,6 +337,16 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *space, gc_tune_result *o
  * used to calibrate hardware traffic counters against a known byte count. */
 gc_status gc_copy_probe(gc_ctx *ctx, void *dst, const void *src, uint64_t n_bytes);
 
+/* Gather ceiling of the push (the denominator of its roofline): every particle
+ * in the live prefix of the last reorder makes the push's two trilinear
+ * gathers per step for n_steps steps while moving on the straight line
+ * X + k dt F^{n-1}, with the push's layout, slot order and launch shape but
+ * none of its arithmetic.  sink: DEVICE array of at least gc_count() doubles
+ * (receives a checksum per slot).  The particle state is not modified; the
+ * probe's particle-steps are added to the particle_steps counter.  Async.
+ * Errors: GC_ESTATE without a field; GC_EINVAL for dt <= 0 or n_steps < 0. */
+gc_status gc_gather_probe(gc_ctx *ctx, double dt, int32_t n_steps, double *sink);
+
 #ifdef __cplusplus
 }
 #endif

@@ -357,6 +357,16 @@ class Context:
         """Trilinear grid field at points (device float64 [3, n]) -> [n, 12]."""
         return self._points(lib.gc_field_sample, pts)
 
+    def gather_probe(self, dt: float, n_steps: int):
+        """Gather-only pass over the live particles (gc_gather_probe); returns the
+        per-slot checksums (device float64)."""
+        torch = _torch()
+        sink = torch.empty(max(self.count(), 1), dtype=torch.float64, device=f"cuda:{self.device}")
+        self._inputs_ready()
+        self._check(lib.gc_gather_probe(self._h, float(dt), int(n_steps), C.c_void_p(sink.data_ptr())))
+        self._outputs_ready(sink)
+        return sink
+
     def copy_probe(self, dst, src, n_bytes: int):
         self._inputs_ready()
         self._check(lib.gc_copy_probe(self._h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(n_bytes)))

@@ -111,6 +111,7 @@ def load():
         "gc_get_counters": (S, [P, C.POINTER(gc_counters)]),
         "gc_reset_counters": (S, [P]),
         "gc_copy_probe": (S, [P, P, P, C.c_uint64]),
+        "gc_gather_probe": (S, [P, C.c_double, C.c_int32, P]),
         "gc_autotune": (S, [P, C.POINTER(gc_tune_space), C.POINTER(gc_tune_result)]),
         "gc_mlp_set": (S, [P, C.POINTER(gc_mlp_desc)]),
         "gc_mlp_get_params": (S, [P, C.POINTER(C.c_float)]),
@@ -131,5 +132,5 @@ DECLARED = (
     "gc_load_field", "gc_inject", "gc_advance", "gc_advance_graph", "gc_moments_size", "gc_moments",
     "gc_count", "gc_get_state", "gc_set_state", "gc_get_log", "gc_get_counters", "gc_reset_counters",
     "gc_copy_probe", "gc_autotune", "gc_mlp_set", "gc_mlp_get_params", "gc_mlp_get_grads", "gc_mlp_train_step",
-    "gc_mlp_eval", "gc_field_sample",
+    "gc_mlp_eval", "gc_field_sample", "gc_gather_probe",
 )

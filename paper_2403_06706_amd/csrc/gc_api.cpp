@@ -842,6 +842,31 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *sp, gc_tune_result *out)
 
 extern "C" {
 
+gc_status gc_gather_probe(gc_ctx *ctx, double dt, int32_t n_steps, double *sink) {
+    if (!ctx) return GC_EINVAL;
+    if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_gather_probe before gc_load_field");
+    if (!(std::isfinite(dt) && dt > 0.0) || n_steps < 0) return fail(ctx, GC_EINVAL, "need dt > 0 and n_steps >= 0");
+    if (ctx->n == 0 || n_steps == 0) return GC_OK;
+    if (!sink) return fail(ctx, GC_EINVAL, "sink is NULL");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    PushArgs a{};
+    a.st = ctx->A;
+    a.f = ctx->f;
+    a.ens = ctx->ens_dev;
+    a.n_active = ctx->bound_dirty ? nullptr : ctx->n_active;
+    a.n_slots = (uint32_t)ctx->n;
+    a.n_steps = n_steps;
+    a.dt = dt;
+    a.steps_done = ctx->steps;
+    if (!a.n_active) {
+        // no reorder since the last change of the particle set: visit all slots
+        HIPCHK(launch_set_count(ctx->queue, (uint32_t)ctx->n, ctx->stream));
+        a.n_active = ctx->queue;
+    }
+    HIPCHK(launch_gather_probe(a, sink, ctx->stream));
+    return GC_OK;
+}
+
 gc_status gc_copy_probe(gc_ctx *ctx, void *dst, const void *src, uint64_t n_bytes) {
     if (!ctx || !dst || !src) return GC_EINVAL;
     if (n_bytes % 16) return fail(ctx, GC_EINVAL, "n_bytes must be a multiple of 16");
