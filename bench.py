@@ -209,7 +209,7 @@ MLP_EVALS_PER_STEP = 2
 PEAK_BF16_TFLOPS = 2500.0
 
 
-def run_mlp(args):
+def run_mlp(args, n_particles=None, steps=None, with_cpu=True):
     """Neural-field workload: electrons at 81 keV (lambda 0.5 AU) injected as in
     the small spiral workload, pushed through the network trained by the
     library on 49M positions drawn along trajectories of that workload (8,192
@@ -251,8 +251,9 @@ def run_mlp(args):
     log(f"[bench] network trained in {t_train:.1f} s (set-up {t1 - t0:.1f} s), loss {losses[-1]:.3e}, "
         f"field error vs grid {ferr}")
 
-    ens = replace(small.ensembles[0], n=args.mlp_particles, seed=args.seed)
-    steps = args.steps if args.steps is not None else 4
+    ens = replace(small.ensembles[0], n=n_particles or args.mlp_particles, seed=args.seed)
+    if steps is None:
+        steps = args.steps if args.steps is not None else 4
 
     def timed(source):
         ctx = gcp.Context(device=0, precision=args.precision, field_source=source, timing=True)
@@ -312,7 +313,7 @@ def run_mlp(args):
         "trajectory_difference_vs_grid": {"particles": int(same_k.sum()), "median": float(np.median(d)) if len(d) else None,
                                           "max": float(d.max()) if len(d) else None},
     }
-    if not args.no_cpu_baseline:
+    if with_cpu and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_mlp(args, small, f, spec, params)
     return out
 
@@ -371,7 +372,9 @@ def main():
     ap.add_argument("--coarsen", type=int, default=0)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--tile", type=int, default=1024)
-    ap.add_argument("--forms", type=int, default=0, help="also time the FP32 forms over this many chunks")
+    ap.add_argument("--forms", type=int, default=None,
+                    help="time the FP32 forms over this many chunks (default: the whole run; 0: skip)")
+    ap.add_argument("--no-neural", action="store_true", help="skip the neural-field summary of the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-particles", type=int, default=98304)
     ap.add_argument("--cpu-steps", type=int, default=14400)
@@ -439,18 +442,29 @@ def main():
         "moments_last": {"active": int(mom[0]), "exited": int(mom[1]), "collisions": int(mom[4])} if mom is not None else None,
     }
 
-    if args.forms > 0:
+    forms_steps = args.steps if args.forms is None else args.forms
+    if forms_steps > 0 and not args.probe_copy:
+        # the FP32 forms over the same job, as speed-ups over the plain push (their error
+        # against the FP64 oracle is bounded by the precision tests)
         forms = {}
-        base_el, base_c, _, _, _ = run_gpu(args, wl, field, args.precision, args.forms, 1)
-        base = base_c["particle_steps"] / base_el
-        forms[args.precision] = {"value": base}
         for prec in ("f32_acc64", "f32_kahan"):
             if prec == args.precision:
                 continue
-            el, cc, _, _, _ = run_gpu(args, wl, field, prec, args.forms, 1)
+            el, cc, _, _, _ = run_gpu(args, wl, field, prec, forms_steps, 1)
             v = cc["particle_steps"] / el
-            forms[prec] = {"value": v, "speedup": v / base}
-        out["forms_first_chunks"] = {"chunks": args.forms, **forms}
+            forms[prec] = {"value": v, "speedup": v / value if forms_steps == args.steps else None}
+            log(f"[bench] form {prec}: {v:.3e} particle-steps/s")
+        out["forms"] = {"chunks": forms_steps, **forms}
+
+    if not args.no_neural and not args.probe_copy:
+        log("[bench] neural-field summary ...")
+        nf = run_mlp(args, n_particles=2 << 20, steps=2, with_cpu=False)
+        out["neural_field"] = {"value": nf["value"], "particles": nf["config"]["particles"],
+                               "chunks": nf["steps"], "roofline": nf["roofline"],
+                               "grid_push_same_particles": nf["grid_push_same_particles"],
+                               "field_error_vs_grid_rms": nf["config"]["field_error_vs_grid_rms"],
+                               "trajectory_difference_vs_grid": nf["trajectory_difference_vs_grid"],
+                               "note": "full measurement: bench.py --workload mlp"}
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")

@@ -81,6 +81,10 @@ typedef struct {
     int32_t log_depth;      /* per particle, record the step of the first log_depth collisions (0: off) */
     int32_t timing;         /* 1: record HIP events around each push launch (see gc_get_counters) */
     int32_t field_source;   /* GC_SOURCE_GRID (trilinear grid) or GC_SOURCE_MLP (neural field, gc_mlp_set) */
+    int32_t tail_threshold; /* grid form, eager gc_advance: chunks whose live count (as read back from an
+                               earlier reorder) is below this use the latency form of the push, with
+                               every field load of a gather in flight; 0 disables.  Results are
+                               bitwise identical in both forms. */
 } gc_options;
 
 enum { GC_SOURCE_GRID = 0, GC_SOURCE_MLP = 1 };

@@ -68,7 +68,8 @@ class Context:
 
     def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
                  bin_coarsen: int = 0, block_size: int = 256, persistent: bool = False, tile: int = 1024,
-                 log_depth: int = 0, timing: bool = False, field_source: str = "grid", stream=None):
+                 log_depth: int = 0, timing: bool = False, field_source: str = "grid", tail_threshold: Optional[int] = None,
+                 stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the guiding-centre pusher runs only on the device")
@@ -88,6 +89,8 @@ class Context:
         o.log_depth = log_depth
         o.timing = int(timing)
         o.field_source = _SOURCES[field_source]
+        if tail_threshold is not None:
+            o.tail_threshold = int(tail_threshold)
         self._opt = o
         h = C.c_void_p()
         st = lib.gc_create(C.byref(h), C.byref(o))
@@ -245,7 +248,7 @@ class Context:
         self._check(lib.gc_get_options(self._h, C.byref(o)))
         return {"precision": o.precision, "order": o.order, "chunk_steps": o.chunk_steps,
                 "bin_coarsen": o.bin_coarsen, "block_size": o.block_size, "persistent": o.persistent,
-                "tile": o.tile, "field_source": o.field_source}
+                "tile": o.tile, "field_source": o.field_source, "tail_threshold": o.tail_threshold}
 
     def autotune(self, dt: float, probe_steps: int = 128, blocks=(64, 128, 256), coarsen=(0, 1, 2),
                  chunks=(), tiles=(256, 1024, 4096), cache: Optional[str] = None, key: Optional[str] = None) -> dict:

@@ -19,7 +19,8 @@ class gc_options(C.Structure):
     _fields_ = [("hip_stream", C.c_void_p), ("device", C.c_int32), ("precision", C.c_int32),
                 ("order", C.c_int32), ("chunk_steps", C.c_int32), ("bin_coarsen", C.c_int32),
                 ("block_size", C.c_int32), ("persistent", C.c_int32), ("tile", C.c_int32),
-                ("log_depth", C.c_int32), ("timing", C.c_int32), ("field_source", C.c_int32)]
+                ("log_depth", C.c_int32), ("timing", C.c_int32), ("field_source", C.c_int32),
+                ("tail_threshold", C.c_int32)]
 
 
 class gc_field_desc(C.Structure):

@@ -22,6 +22,7 @@ struct GraphKey {
     double dt = 0;
     int64_t n_steps = -1;
     uint64_t n = 0;
+    const void *state = nullptr;    // buffer holding the state at capture (eager reorders swap buffers)
     gc_options opt{};
 };
 
@@ -68,6 +69,9 @@ struct gc_ctx {
     bool bound_dirty = true;          // the bound must be reset to n before the next reorder
     unsigned long long *steps = nullptr;
     uint32_t *log = nullptr;
+    volatile uint32_t *count_host = nullptr;   // live count of the latest completed reorder (pinned)
+    bool capturing = false;
+    int tail_skip = 0;                         // reorders still to skip in the tail
     // timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_push, ev_reorder;
     std::vector<hipEvent_t> ev_pool;   // recorded and read events, ready for reuse
@@ -110,6 +114,7 @@ gc_status check_options(gc_ctx *ctx, const gc_options *o) {
     if (o->log_depth < 0 || o->log_depth > 4096) return fail(ctx, GC_EINVAL, "log_depth must be in [0, 4096]");
     if (o->field_source != GC_SOURCE_GRID && o->field_source != GC_SOURCE_MLP)
         return fail(ctx, GC_EINVAL, "unknown field_source %d", o->field_source);
+    if (o->tail_threshold < 0) return fail(ctx, GC_EINVAL, "tail_threshold must be >= 0");
     return GC_OK;
 }
 
@@ -221,10 +226,25 @@ uint32_t bits_for(uint32_t max_key) {
     return b;
 }
 
-gc_status reorder(gc_ctx *ctx, bool timed) {
+// Tail of a run (eager advance only): once the live count read back from an
+// earlier reorder is below tail_threshold, the machine is far from full and the
+// push is bound by each wavefront's chain of dependent memory round trips.
+// Then the push takes its latency form, and the reorder runs only every
+// kTailReorderEvery chunks (particles cross about two cells per 64 steps, so
+// the cell order decays slowly, while a reorder costs a fixed ~80 us of
+// launches).  Neither choice changes any particle's trajectory.
+constexpr int kTailReorderEvery = 8;
+
+bool tail_mode(const gc_ctx *ctx) {
+    if (ctx->opt.tail_threshold <= 0 || ctx->capturing || !ctx->count_host) return false;
+    const uint32_t seen = *ctx->count_host;
+    return seen != 0xFFFFFFFFu && seen < (uint32_t)ctx->opt.tail_threshold;
+}
+
+gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     hipStream_t s = ctx->stream;
     const uint32_t n = (uint32_t)ctx->n;
-    if (ctx->opt.order == GC_ORDER_NONE) {
+    if (order == GC_ORDER_NONE) {
         HIPCHK(launch_set_count(ctx->n_active, n, s));
         ctx->bound_dirty = true;    // active particles may sit anywhere until the next reorder
         return GC_OK;
@@ -241,7 +261,7 @@ gc_status reorder(gc_ctx *ctx, bool timed) {
     }
     const bool comp = ctx->opt.precision == GC_PREC_F32_KAHAN;
     uint32_t *perm = nullptr;
-    if (ctx->opt.order == GC_ORDER_COMPACT) {
+    if (order == GC_ORDER_COMPACT) {
         HIPCHK(launch_compact(ctx->A, ctx->n_bound, n, ctx->sc, ctx->n_active, &perm, s));
     } else {
         const int c = ctx->opt.bin_coarsen;
@@ -256,7 +276,7 @@ gc_status reorder(gc_ctx *ctx, bool timed) {
     HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
     // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
     HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, s));
-    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, s));
+    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->capturing ? nullptr : ctx->count_host, s));
     std::swap(ctx->A, ctx->B);
     std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
     if (timed) {
@@ -290,10 +310,11 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
         e1 = take_event(ctx);
         HIPCHK(hipEventRecord(e0, s));
     }
+    const bool latency = tail_mode(ctx);
     if (ctx->opt.field_source == GC_SOURCE_MLP)
         HIPCHK(launch_push_mlp(a, ctx->mlp.args, ctx->opt.precision, s));
     else
-        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, grid_blocks, s));
+        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, latency, grid_blocks, s));
     if (timed) {
         HIPCHK(hipEventRecord(e1, s));
         ctx->ev_push.emplace_back(e0, e1);
@@ -305,7 +326,14 @@ gc_status enqueue_advance(gc_ctx *ctx, double dt, int64_t n_steps, bool timed) {
     int64_t left = n_steps;
     while (left > 0) {
         const int32_t c = (int32_t)std::min<int64_t>(left, ctx->opt.chunk_steps);
-        gc_status st = reorder(ctx, timed);
+        const bool tail = tail_mode(ctx) && ctx->opt.order != GC_ORDER_NONE;   // (NONE: nothing to skip)
+        gc_status st = GC_OK;
+        if (!tail || ctx->bound_dirty || ctx->tail_skip <= 0) {
+            st = reorder(ctx, timed, ctx->opt.order);
+            ctx->tail_skip = kTailReorderEvery - 1;
+        } else {
+            --ctx->tail_skip;
+        }
         if (st != GC_OK) return st;
         st = push(ctx, dt, c, timed);
         if (st != GC_OK) return st;
@@ -339,6 +367,8 @@ void gc_default_options(gc_options *o) {
     o->tile = 1024;
     o->log_depth = 0;
     o->timing = 0;
+    o->field_source = GC_SOURCE_GRID;
+    o->tail_threshold = 65536;
 }
 
 gc_status gc_create(gc_ctx **out, const gc_options *opt) {
@@ -376,6 +406,10 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     ctx->steps = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 64);
     HIPCHK(launch_fill_u32(ctx->n_active, 0u, 3, ctx->stream));
     HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, ctx->stream));
+    void *pinned = nullptr;
+    HIPCHK(hipHostMalloc(&pinned, 64, hipHostMallocCoherent));
+    ctx->count_host = static_cast<volatile uint32_t *>(pinned);
+    *ctx->count_host = 0xFFFFFFFFu;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return GC_OK;
 }
@@ -399,6 +433,7 @@ void gc_destroy(gc_ctx *ctx) {
     if (ctx->mlp.ws) (void)hipFree(ctx->mlp.ws);
     if (ctx->ens_dev) (void)hipFree(ctx->ens_dev);
     if (ctx->n_active) (void)hipFree(ctx->n_active);
+    if (ctx->count_host) (void)hipHostFree(const_cast<uint32_t *>(ctx->count_host));
     delete ctx;
 }
 
@@ -539,6 +574,7 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
                          ctx->stream));
     ctx->n += d->n;
     ctx->bound_dirty = true;
+    if (ctx->count_host) *ctx->count_host = 0xFFFFFFFFu;
     return GC_OK;
 }
 
@@ -557,6 +593,7 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
     if (!ctx->stream) return fail(ctx, GC_EINVAL, "graph capture needs a non-null stream");
     HIPCHK(hipSetDevice(ctx->opt.device));
     const bool same = ctx->gexec && ctx->gkey.dt == dt && ctx->gkey.n_steps == n_steps && ctx->gkey.n == ctx->n &&
+                      ctx->gkey.state == ctx->soa_mem[0] &&
                       std::memcmp(&ctx->gkey.opt, &ctx->opt, sizeof(gc_options)) == 0;
     if (!same) {
         if (ctx->gexec) {
@@ -568,7 +605,9 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
         if (ctx->opt.order != GC_ORDER_NONE && (chunks & 1))
             return fail(ctx, GC_EINVAL, "graph mode needs an even number of chunks (n_steps / chunk_steps)");
         HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        ctx->capturing = true;
         st = enqueue_advance(ctx, dt, n_steps, false);
+        ctx->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamEndCapture(ctx->stream, &g);
         if (st != GC_OK) {
@@ -584,6 +623,7 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
         ctx->gkey.dt = dt;
         ctx->gkey.n_steps = n_steps;
         ctx->gkey.n = ctx->n;
+        ctx->gkey.state = ctx->soa_mem[0];
         ctx->gkey.opt = ctx->opt;
     }
     HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
@@ -658,6 +698,7 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
     HIPCHK(launch_state_in(ctx->A, *src, (uint32_t)n, ctx->stream));
     ctx->n = n;
     ctx->bound_dirty = true;
+    if (ctx->count_host) *ctx->count_host = 0xFFFFFFFFu;
     if (ctx->gexec) {
         (void)hipGraphExecDestroy(ctx->gexec);
         ctx->gexec = nullptr;

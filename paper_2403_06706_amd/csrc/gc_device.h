@@ -95,7 +95,11 @@ template <> struct Pair<GC_F16> {
     }
 };
 
-template <int FDT, typename R>
+// kAllPairs: issue the loads of all four node pairs at once (one memory round
+// trip per gather, more registers); otherwise at most two pairs are in
+// registers at a time, which keeps the push within two wavefronts per SIMD.
+// The arithmetic, and so the result, is the same either way.
+template <int FDT, typename R, bool kAllPairs = false>
 __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
     R x = (r - (R)f.r_min) * (R)f.inv_dr;
     R y = th * (R)f.inv_dth - (R)0.5;
@@ -128,7 +132,7 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
         const R wa = w[q] * ((R)1 - wp), wb = w[q] * wp;
 #pragma unroll
         for (int c = 0; c < 12; ++c) out[c] = fma(wb, (R)p.get(c + 12, f), fma(wa, (R)p.get(c, f), out[c]));
-        if (q & 1) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
+        if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
     }
     R sum = (R)0;
 #pragma unroll

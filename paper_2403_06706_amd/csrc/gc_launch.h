@@ -15,9 +15,9 @@ struct MomDev {
     double r_lo, r_hi, sel_r_lo, sel_r_hi, age_lo, age_hi, age_max, e_lo, e_hi, e_unit, len_unit;
 };
 
-// push (gc_push.hip)
-hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int grid_blocks,
-                       hipStream_t s);
+// push (gc_push.hip); latency: the form with all loads of a gather in flight
+hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, bool latency,
+                       int grid_blocks, hipStream_t s);
 
 // gather ceiling (gc_probe.hip): sink[slot] for every slot below *a.n_active
 hipError_t launch_gather_probe(const PushArgs &a, double *sink, hipStream_t s);
@@ -58,7 +58,8 @@ hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, 
                           bool with_comp, hipStream_t s);
 hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,
                              bool with_comp, hipStream_t s);
-hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, hipStream_t s);
+// *dst = *src; also *host_mirror = *src when host_mirror (host-coherent pinned memory) is set
+hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, hipStream_t s);
 hipError_t launch_set_count(uint32_t *n_active, uint32_t n, hipStream_t s);
 
 }  // namespace gc

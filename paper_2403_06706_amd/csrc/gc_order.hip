@@ -297,10 +297,14 @@ hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo,
     return hipGetLastError();
 }
 
-__global__ void k_copy_count(uint32_t *dst, const uint32_t *src) { *dst = *src; }
+__global__ void k_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror) {
+    const uint32_t v = *src;
+    *dst = v;
+    if (host_mirror) *host_mirror = v;
+}
 
-hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, dst, src);
+hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, dst, src, host_mirror);
     return hipGetLastError();
 }
 

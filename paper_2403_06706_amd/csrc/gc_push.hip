@@ -13,7 +13,7 @@
 
 namespace gc {
 
-template <int PREC, int FDT>
+template <int PREC, int FDT, bool LAT = false>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot) {
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
@@ -59,7 +59,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         bool bad = false;
         for (;;) {
             R g[12];
-            if (!gather<FDT, R>(a.f, px, pth, pph, g)) { bad = true; break; }
+            if (!gather<FDT, R, LAT>(a.f, px, pth, pph, g)) { bad = true; break; }
             if (stage == 0 && (flags & GC_FLAG_PENDING)) {
                 // collision k+1 (Eqs. 9-10): |p| kept, new pitch cosine and free path
                 const R B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -160,8 +160,8 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
 // gives each XCD a contiguous range of that prefix, so that (with cell-sorted
 // slots) its L2 holds the field cells of its own particles, and every XCD gets
 // an equal share however small the active prefix is.
-template <int PREC, int FDT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
+template <int PREC, int FDT, bool LAT>
+__device__ __forceinline__ void push_grid(const PushArgs &a) {
     const uint32_t n = *a.n_active;
     const uint32_t nb = (n + blockDim.x - 1) / blockDim.x, b = blockIdx.x;
     if (b >= nb) return;
@@ -169,8 +169,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
     const uint32_t slot = lb * blockDim.x + threadIdx.x;
     uint32_t taken = 0;
-    if (slot < n) taken = advance_slot<PREC, FDT>(a, slot);
+    if (slot < n) taken = advance_slot<PREC, FDT, LAT>(a, slot);
     count_steps(a, taken);
+}
+
+// Throughput form: at most 256 registers per lane (two wavefronts per SIMD).
+template <int PREC, int FDT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
+    push_grid<PREC, FDT, false>(a);
+}
+
+// Latency form, for few active particles (the machine is far from full and
+// each wavefront's step time is its chain of dependent memory round trips):
+// every gather has all its loads in flight at once.
+template <int PREC, int FDT>
+__global__ __launch_bounds__(256) void k_push_lat(PushArgs a) {
+    push_grid<PREC, FDT, true>(a);
 }
 
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
@@ -197,33 +211,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 
 template <int PREC, int FDT>
-static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int grid_blocks, hipStream_t s) {
+static hipError_t launch_t(const PushArgs &a, int block, bool persistent, bool latency, int grid_blocks,
+                           hipStream_t s) {
     if (persistent) {
         hipLaunchKernelGGL((k_push_persistent<PREC, FDT>), dim3(grid_blocks), dim3(block), 0, s, a);
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;
-        hipLaunchKernelGGL((k_push<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
+        if (latency)
+            hipLaunchKernelGGL((k_push_lat<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_push<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
     }
     return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t launch_p(const PushArgs &a, int block, bool persistent, int grid_blocks, hipStream_t s) {
+static hipError_t launch_p(const PushArgs &a, int block, bool persistent, bool latency, int grid_blocks,
+                           hipStream_t s) {
     switch (a.f.dtype) {
-        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, grid_blocks, s);
-        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, grid_blocks, s);
-        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, grid_blocks, s);
+        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, latency, grid_blocks, s);
+        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, latency, grid_blocks, s);
+        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, latency, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int grid_blocks,
-                       hipStream_t s) {
+hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, bool latency,
+                       int grid_blocks, hipStream_t s) {
     switch (precision) {
-        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, grid_blocks, s);
-        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, grid_blocks, s);
-        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, grid_blocks, s);
+        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, latency, grid_blocks, s);
+        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, latency, grid_blocks, s);
+        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, latency, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }

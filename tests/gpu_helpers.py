@@ -32,12 +32,14 @@ def say(msg):
 
 
 def run_gpu(wl, field, store_dtype="f64", precision="f64", order="bin", chunk=64, n_steps=None, dt=None,
-            log_depth=0, block=256, persistent=False, tile=1024, coarsen=0, ensembles=None, graph=False):
+            log_depth=0, block=256, persistent=False, tile=1024, coarsen=0, ensembles=None, graph=False,
+            tail_threshold=None):
     import torch
     import paper_2403_06706_amd as gcp
     stream = torch.cuda.Stream() if graph else None
     ctx = gcp.Context(device=0, precision=precision, order=order, chunk_steps=chunk, log_depth=log_depth,
-                      block_size=block, persistent=persistent, tile=tile, bin_coarsen=coarsen, stream=stream)
+                      block_size=block, persistent=persistent, tile=tile, bin_coarsen=coarsen, stream=stream,
+                      tail_threshold=tail_threshold)
     ctx.load_field(wl.grid, field, store_dtype)
     for e in (ensembles or wl.ensembles):
         ctx.inject(e)

@@ -27,6 +27,9 @@ def base():
     dict(order="compact", chunk=100, block=128),
     dict(order="bin", chunk=64, persistent=True, tile=256),
     dict(order="none", chunk=64, persistent=True, tile=1024, block=128),
+    dict(order="bin", chunk=64, tail_threshold=0),             # throughput form and binning every chunk
+    dict(order="bin", chunk=64, tail_threshold=1 << 30),       # tail policy once a count has been read back
+    dict(order="compact", chunk=16, block=64, tail_threshold=1000),
 ])
 def test_trajectories_invariant(base, cfg):
     wl, f, ref, ref_log = base
@@ -48,6 +51,24 @@ def test_graph_replay_matches_eager(base):
             ctx.advance_graph(1.0, 150)
             stream.synchronize()
             torch.zeros(1000, device="cuda").sum().item()   # eager work between replays
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    same_state(st, ref)
+
+
+def test_graph_replays_mixed_with_eager_chunks(base):
+    """Eager advances between replays may leave the state in the other buffer
+    (an odd number of reorders); the next replay must follow it."""
+    wl, f, ref, _ = base
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = gcp.Context(device=0, order="bin", chunk_steps=75, stream=stream)
+    ctx.load_field(wl.grid, f, "f64")
+    ctx.inject(wl.ensembles[0])
+    with torch.cuda.stream(stream):
+        for n, graph in ((150, True),) * 5 + ((75, False),) + ((150, True),) * 5 + ((225, False),):
+            (ctx.advance_graph if graph else ctx.advance)(1.0, n)    # 1800 steps in total
+        stream.synchronize()
     st = gcp.state_to_numpy(ctx.get_state())
     ctx.close()
     same_state(st, ref)
