@@ -62,22 +62,27 @@ __device__ __forceinline__ float dsilu_f(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
-// Workgroup LDS of the evaluation: two staged weight matrices (rows padded to
-// 136 BF16 so that the 16 rows read by a 16-lane group start in distinct bank
-// quads) and the biases.
+// Workgroup LDS of the evaluation (NT threads): two staged weight matrices
+// (rows padded to 136 BF16 so that the 16 rows read by a 16-lane group start in
+// distinct bank quads), the biases and frequencies, and each thread's outputs.
 constexpr int kMlpLdsRowW = kMlpWidth + 8;
 constexpr int kMlpLdsMat = kMlpWidth * kMlpLdsRowW;
+constexpr int kMlpPieces = kMlpWidth * kMlpWidth / 8;       // 16-byte pieces of a 128 x 128 matrix
+constexpr int kMlpOutPieces = kMlpEvalRows * kMlpWidth / 8; // of the 16-row output matrix
+template <int NT>
 struct MlpLds {
     __bf16 w[2][kMlpLdsMat];
     float c[kMlpDepth * kMlpWidth];
     float co[kMlpEvalRows];
     float fa[kMlpFreq], fb[kMlpFreq], fn[kMlpFreq];
+    float y[NT][4 * kMlpOut];     // per thread: y, then dy along r, th, ph
 };
 
 // Biases and frequencies into LDS (all threads of the workgroup; followed by
 // a barrier).
-__device__ __forceinline__ void mlp_lds_init(const MlpArgs &m, MlpLds &L) {
-    for (int i = threadIdx.x; i < kMlpDepth * kMlpWidth; i += blockDim.x) L.c[i] = m.c[i];
+template <int NT>
+__device__ __forceinline__ void mlp_lds_init(const MlpArgs &m, MlpLds<NT> &L) {
+    for (int i = threadIdx.x; i < kMlpDepth * kMlpWidth; i += NT) L.c[i] = m.c[i];
     if (threadIdx.x < kMlpEvalRows) L.co[threadIdx.x] = threadIdx.x < kMlpOut ? m.co[threadIdx.x] : 0.0f;
     if (threadIdx.x < kMlpFreq) {
         L.fa[threadIdx.x] = m.fa[threadIdx.x];
@@ -87,30 +92,32 @@ __device__ __forceinline__ void mlp_lds_init(const MlpArgs &m, MlpLds &L) {
     __syncthreads();
 }
 
-// Matrix mi of the evaluation (0..5 hidden layers, 6 output layer), in 16-byte
-// pieces: 256 threads x 8 pieces cover a 128 x 128 matrix.  Branch-free: for
-// the 16-row output matrix the surplus pieces repeat its last piece and land in
-// rows that are never read.
-__device__ __forceinline__ void mlp_fetch(const MlpArgs &m, int mi, u32x4 v[8]) {
+// Pieces [U0, U0 + U) of this thread's share (piece u * NT + tid) of matrix mi
+// (0..5 hidden layers, 6 output layer).  Branch-free: for the 16-row output
+// matrix the surplus pieces repeat its last piece and land in rows that are
+// never read.
+template <int NT, int U0, int U>
+__device__ __forceinline__ void mlp_fetch(const MlpArgs &m, int mi, u32x4 v[U]) {
     const bool hidden = mi < kMlpDepth;
     const u32x4 *src = reinterpret_cast<const u32x4 *>(hidden ? m.W + (size_t)mi * kMlpWidth * kMlpWidth : m.Wo);
-    const int last = (hidden ? kMlpWidth : kMlpEvalRows) * (kMlpWidth / 8) - 1;
+    const int last = (hidden ? kMlpPieces : kMlpOutPieces) - 1;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = src[min(u * 256 + (int)threadIdx.x, last)];
+    for (int u = 0; u < U; ++u) v[u] = src[min((U0 + u) * NT + (int)threadIdx.x, last)];
 }
 
-__device__ __forceinline__ void mlp_store(const u32x4 v[8], __bf16 *dst) {
+template <int NT, int U0, int U>
+__device__ __forceinline__ void mlp_store(const u32x4 v[U], __bf16 *dst) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int e = u * 256 + (int)threadIdx.x;
+    for (int u = 0; u < U; ++u) {
+        const int e = (U0 + u) * NT + (int)threadIdx.x;
         *reinterpret_cast<u32x4 *>(dst + (e >> 4) * kMlpLdsRowW + (e & 15) * 8) = v[u];
     }
 }
 
-// Evaluate the network and its three tangents for the particles of a
-// 256-thread workgroup (one per thread).  All 256 threads must call it
-// together (it synchronizes the workgroup); the biases must be in L
-// (mlp_lds_init).  Output per thread: y[6] and dy[d][6] = dy / d(r, th, ph)[d].
+// Evaluate the network and its three tangents for the particles of an
+// NT-thread workgroup (one per thread).  All NT threads must call it together
+// (it synchronizes the workgroup); the biases must be in L (mlp_lds_init).
+// Output per thread: y[6] and dy[d][6] = dy / d(r, th, ph)[d].
 //
 // Matrix-core tiling (v_mfma_f32_16x16x32_bf16; each wavefront takes its 64
 // particles in 4 passes of 16): the products are taken transposed, Z^T = W H^T,
@@ -122,30 +129,31 @@ __device__ __forceinline__ void mlp_store(const u32x4 v[8], __bf16 *dst) {
 // lane-local, and with the column permutation of the weights (mlp_perm) its
 // results are already the next layer's B operand; activations never leave the
 // registers.  The weights go through LDS, one matrix at a time, shared by the
-// four wavefronts; the next matrix is fetched from global memory while the
-// current one is in use.  Per pass and hidden layer: 8 unit tiles x 4 k-blocks
-// x 4 column tiles = 128 MFMAs.
-__device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, float ph, MlpLds &L,
+// workgroup's wavefronts; the next matrix is fetched from global memory in two
+// halves while the current one is in use.  Per pass and hidden layer: 8 unit
+// tiles x 4 k-blocks x 4 column tiles = 128 MFMAs, the products of tile t
+// issued before the activation of tile t - 1, which they overlap.
+template <int NT>
+__device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, float ph, MlpLds<NT> &L,
                                           float y[kMlpOut], float dy[3][kMlpOut]) {
-    const int l = threadIdx.x & 63;
+    constexpr int kPer = kMlpPieces / NT;                  // pieces per thread
+    constexpr int kHalf = kPer / 2;
+    static_assert(kPer >= 2 && kPer % 2 == 0, "NT must divide the matrix into an even number of pieces");
+    const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = l >> 4, col = l & 15;
     const float two_pi = 6.283185307179586f;
-    float out[4][kMlpOut];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int o = 0; o < kMlpOut; ++o) out[q][o] = 0.0f;
-    u32x4 pf[8];
-    __syncthreads();                                      // the previous call is done with both buffers
-    mlp_fetch(m, 0, pf);
-    mlp_store(pf, L.w[0]);
+    float *yw = &L.y[wave * 64][0];                          // this wavefront's outputs
+    u32x4 pf[kPer];
+    __syncthreads();                                         // the previous call is done with both buffers
+    mlp_fetch<NT, 0, kPer>(m, 0, pf);
+    mlp_store<NT, 0, kPer>(pf, L.w[0]);
     int cur = 0;
     for (int p = 0; p < 4; ++p) {
-        const int src = 16 * p + col;                       // the particle of this lane's column
+        const int src = 16 * p + col;                        // the particle of this lane's column
         const float pr = __shfl(r, src), pth = __shfl(th, src), pph = __shfl(ph, src);
         const float rt = (pr - m.r_min) * m.inv_rspan, tt = pth * 0.3183098861837907f;
         // layer-1 inputs: features 32s + 8g + i (phases 16s + 4g + i/2), natural order
-        bf16x8 B[4][4];                                     // [k block][value, d/dr, d/dth, d/dph]
+        bf16x8 B[4][4];                                      // [k block][value, d/dr, d/dth, d/dph]
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -167,17 +175,21 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
             }
         }
         for (int mi = 0; mi <= kMlpDepth; ++mi) {
-            __syncthreads();                                // L.w[cur] holds matrix mi
-            mlp_fetch(m, mi < kMlpDepth ? mi + 1 : 0, pf);  // the next one (after the last: unused)
+            __syncthreads();                                 // L.w[cur] holds matrix mi
+            const int next = mi < kMlpDepth ? mi + 1 : 0;    // after the last: unused
+            __bf16 *nbuf = L.w[cur ^ 1];
             const __bf16 *Wl = L.w[cur] + col * kMlpLdsRowW + 8 * g;
             if (mi < kMlpDepth) {
                 bf16x8 Bn[4][4];
                 const float *cl = L.c + mi * kMlpWidth + 4 * g;
-                // software pipeline over the 8 unit tiles: the products of tile t are
-                // issued before the activation of tile t - 1, which overlaps them
                 floatx4 prev[4];
 #pragma unroll
                 for (int t = 0; t <= 8; ++t) {
+                    if (t == 0) mlp_fetch<NT, 0, kHalf>(m, next, pf);
+                    if (t == 4) {
+                        mlp_store<NT, 0, kHalf>(pf, nbuf);
+                        mlp_fetch<NT, kHalf, kHalf>(m, next, pf);
+                    }
                     floatx4 acc[4] = {floatx4{}, floatx4{}, floatx4{}, floatx4{}};
                     if (t < 8) {
 #pragma unroll
@@ -209,11 +221,13 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                     for (int q = 0; q < 4; ++q) prev[q] = acc[q];
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                mlp_store<NT, kHalf, kHalf>(pf, nbuf);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) B[s][q] = Bn[s][q];
             } else {
+                mlp_fetch<NT, 0, kPer>(m, next, pf);
                 // output layer: one 16-row tile (rows >= 6 zero)
                 floatx4 o[4] = {floatx4{}, floatx4{}, floatx4{}, floatx4{}};
 #pragma unroll
@@ -223,28 +237,30 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                     for (int q = 0; q < 4; ++q)
                         o[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[s][q], o[q], 0, 0, 0);
                 }
-                // outputs 0..3 of particle col sit in lane col, outputs 4..5 in lane 16 + col;
-                // the particle's own lane is 16p + col
+                // lane (g, col) holds outputs 4g + jj of particle 16p + col: into its slot in LDS
+                if (g < 2) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) {
-                        const float v0 = __shfl(o[q][jj], col);
-                        const float v1 = __shfl(o[q][jj], 16 + col);
-                        out[q][jj] = g == p ? v0 : out[q][jj];
-                        if (jj < 2) out[q][4 + jj] = g == p ? v1 : out[q][4 + jj];
-                    }
+                        for (int jj = 0; jj < 4; ++jj)
+                            if (4 * g + jj < kMlpOut)
+                                yw[(16 * p + col) * (4 * kMlpOut) + q * kMlpOut + 4 * g + jj] = o[q][jj];
+                }
+                mlp_store<NT, 0, kPer>(pf, nbuf);
             }
-            mlp_store(pf, L.w[cur ^ 1]);
             cur ^= 1;
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float *mine = yw + l * (4 * kMlpOut);
 #pragma unroll
     for (int o = 0; o < kMlpOut; ++o) {
-        y[o] = out[0][o] + L.co[o];
-        dy[0][o] = out[1][o];
-        dy[1][o] = out[2][o];
-        dy[2][o] = out[3][o];
+        y[o] = mine[o] + L.co[o];
+        dy[0][o] = mine[kMlpOut + o];
+        dy[1][o] = mine[2 * kMlpOut + o];
+        dy[2][o] = mine[3 * kMlpOut + o];
     }
 }
 

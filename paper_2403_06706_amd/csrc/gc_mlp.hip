@@ -249,14 +249,17 @@ __global__ void k_mlp_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo,
 // Point evaluation: neural field (64 points per wavefront) and trilinear grid.
 // pts SoA: r[n], th[n], ph[n]; out: [n][12].
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_mlp_eval(MlpArgs m, const double *pts, int n, double *out) {
-    __shared__ MlpLds L;
+constexpr int kEvalThreads = 512;   // 8 wavefronts (2 per SIMD) share the staged weights
+
+__global__ __launch_bounds__(kEvalThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void k_mlp_eval(MlpArgs m, const double *pts, int n, double *out) {
+    __shared__ MlpLds<kEvalThreads> L;
     mlp_lds_init(m, L);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int ii = i < n ? i : n - 1;                 // idle lanes evaluate a valid point
     const double r = pts[ii], th = pts[n + ii], ph = pts[2 * n + ii];
     float y[kMlpOut], dy[3][kMlpOut];
-    mlp_block(m, (float)r, (float)th, (float)ph, L, y, dy);
+    mlp_block<kEvalThreads>(m, (float)r, (float)th, (float)ph, L, y, dy);
     double g[12];
     const bool ok = mlp_assemble<double>(m, r, th, y, dy, g);
     if (i < n)
@@ -361,7 +364,8 @@ hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo,
 
 hipError_t mlp_launch_eval(const MlpArgs &m, const double *pts, int n, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_eval, dim3((n + 255) / 256), dim3(256), 0, s, m, pts, n, out);
+    hipLaunchKernelGGL(k_mlp_eval, dim3((n + kEvalThreads - 1) / kEvalThreads), dim3(kEvalThreads), 0, s, m, pts, n,
+                       out);
     return hipGetLastError();
 }
 
