@@ -190,8 +190,10 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                         mlp_store<NT, 0, kHalf>(pf, nbuf);
                         mlp_fetch<NT, kHalf, kHalf>(m, next, pf);
                     }
+                    // the value tile starts from the bias of its units (16t + 4g + jj)
                     floatx4 acc[4] = {floatx4{}, floatx4{}, floatx4{}, floatx4{}};
                     if (t < 8) {
+                        acc[0] = *reinterpret_cast<const floatx4 *>(cl + 16 * t);
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
                             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(Wl + t * 16 * kMlpLdsRowW + 32 * s);
@@ -203,10 +205,9 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                     if (t > 0) {
                         // lane holds units 16u + 4g + jj (u = t - 1): slots 8g + 4(u&1) + jj of k block u/2
                         const int u = t - 1;
-                        const floatx4 bias = *reinterpret_cast<const floatx4 *>(cl + 16 * u);
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj) {
-                            const float z = prev[0][jj] + bias[jj];
+                            const float z = prev[0][jj];
                             const float sg = sigmoid_f(z);
                             const float h = z * sg;
                             const float ds = sg + h * (1.0f - sg);
