@@ -926,8 +926,8 @@ namespace {
 constexpr int kUserParams = GC_MLP_PARAMS;             // W | c | W_o[6][128] | c_o[6]
 constexpr int kUserOffWo = kMlpOffWo, kUserOffCo = kMlpOffWo + kMlpOut * kMlpWidth;
 static_assert(kUserOffCo + kMlpOut == kUserParams, "GC_MLP_PARAMS does not match the network shape");
-constexpr int kTrainGroups = 64;                      // most row groups of the split-K gradient sums
-constexpr int kRowsPerGroup = 512;
+constexpr int kTrainGroups = 128;                     // most row groups of the split-K weight gradients
+constexpr int kRowsPerGroup = 128;
 constexpr int kLossBlocks = 512;
 
 void to_device_layout(const float *u, std::vector<float> &d) {
@@ -952,7 +952,8 @@ gc_status mlp_workspace(gc_ctx *ctx, int64_t rows) {
     const int64_t cap = std::max<int64_t>(rows, 2 * m.ws_rows);
     const size_t R = (size_t)cap;
     const size_t part = std::max<size_t>((size_t)kTrainGroups * kMlpWidth * kMlpWidth,
-                                         (size_t)(kTrainGroups + 1) * (kMlpOut * kMlpWidth + kMlpOut));
+                                         (size_t)(mlp_col_groups((int)std::min<int64_t>(cap, 1 << 30)) + 1) *
+                                             (kMlpOut * kMlpWidth + kMlpOut));
     const size_t sz[] = {align256(7 * R * kMlpWidth * 2), align256(R * kMlpWidth * 2),
                          align256(6 * R * kMlpWidth * 4), align256(R * kMlpOut * 4), align256(R * kMlpOut * 4),
                          align256(R * kMlpWidth * 4), align256(part * 4), align256(kLossBlocks * 8)};
@@ -1106,13 +1107,12 @@ gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, i
     L.beta = o->beta_pair;
     const int lb = (int)std::min<int64_t>(kLossBlocks, (n_pairs + 255) / 256);
     HIPCHK(mlp_launch_loss(m.args, pts, tgt, m.Y, (int)n_pairs, L, m.dY, m.loss_part, lb, s));
-    // backward; gradient sums split over row groups of about kRowsPerGroup rows
+    // backward; weight-gradient products split over row groups of about kRowsPerGroup rows
     const int groups = std::max(1, std::min(kTrainGroups, rows / kRowsPerGroup));
-    HIPCHK(mlp_launch_out_grad(m.dY, m.H + kMlpDepth * RW, rows, groups, m.part, m.g + kMlpOffWo,
-                               m.g + kMlpOffCo, s));
-    HIPCHK(mlp_launch_out_back(m.dY, m.p + kMlpOffWo, m.Z + (kMlpDepth - 1) * RW, rows, m.dH, s));
+    HIPCHK(mlp_launch_out_grad(m.dY, m.H + kMlpDepth * RW, rows, m.part, m.g + kMlpOffWo, m.g + kMlpOffCo, s));
+    HIPCHK(mlp_launch_out_back(m.dY, m.p + kMlpOffWo, rows, m.dH, s));
     for (int l = kMlpDepth - 1; l >= 0; --l) {
-        HIPCHK(mlp_launch_dz(m.dH, m.Z + l * RW, rows, groups, m.dZ, m.part, m.g + kMlpOffC + l * kMlpWidth, s));
+        HIPCHK(mlp_launch_dz(m.dH, m.Z + l * RW, rows, m.dZ, m.part, m.g + kMlpOffC + l * kMlpWidth, s));
         HIPCHK(mlp_launch_wgrad(m.dZ, m.H + l * RW, rows, groups, m.part, m.g + kMlpOffW + l * WW, s));
         if (l > 0) HIPCHK(mlp_launch_backward_data(m.dZ, m.WT + l * WW, rows, m.dH, s));
     }

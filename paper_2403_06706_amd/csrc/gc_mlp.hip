@@ -165,36 +165,48 @@ __global__ void k_mlp_loss(MlpArgs m, const double *pts, const double *tgt, cons
     if (threadIdx.x == 0) loss_partial[blockIdx.x] = red[0] / npair;
 }
 
-// dZ6 = (dY Wo) * silu'(Z6)  (the output layer has K = 6: plain FP32)
-__global__ void k_mlp_out_back(const float *dY, const float *Wo_master, const float *Z, int rows, float *dH) {
+// dH6 = dY Wo  (the output layer has K = 6: plain FP32; silu' is applied by k_mlp_dz)
+__global__ void k_mlp_out_back(const float *dY, const float *Wo_master, int rows, float *dH) {
     const int k = threadIdx.x, row = blockIdx.x;
     if (row >= rows) return;
     float s = 0.0f;
 #pragma unroll
     for (int c = 0; c < kMlpOut; ++c) s += dY[(size_t)row * kMlpOut + c] * Wo_master[c * kMlpWidth + k];
     dH[(size_t)row * kMlpWidth + k] = s;
-    (void)Z;
 }
 
-// dZ = dH * silu'(Z) -> bf16; per-block column sums for the bias gradient
-__global__ void k_mlp_dz(const float *dH, const float *Z, int rows, int chunk, __bf16 *dZ, float *bias_partial) {
-    const int k = threadIdx.x;
-    const int r_begin = blockIdx.x * chunk, r_end = min(rows, r_begin + chunk);
+// Row-parallel column work: a 256-thread block takes 64 rows, thread
+// (half = tid / 128, k = tid % 128) the rows r0 + half + 2i of column k.
+constexpr int kColRows = 64;
+
+// dZ = dH * silu'(Z) -> bf16, and per-block column sums (bias gradient)
+__global__ __launch_bounds__(256) void k_mlp_dz(const float *dH, const float *Z, int rows, __bf16 *dZ,
+                                                float *bias_partial) {
+    __shared__ float red[kMlpWidth];
+    const int k = threadIdx.x & (kMlpWidth - 1), half = threadIdx.x >> 7;
+    const int r0 = blockIdx.x * kColRows;
     float s = 0.0f;
-    for (int r = r_begin; r < r_end; ++r) {
+    for (int i = half; i < kColRows; i += 2) {
+        const int r = r0 + i;
+        if (r >= rows) break;
         const float v = dH[(size_t)r * kMlpWidth + k] * dsilu_f(Z[(size_t)r * kMlpWidth + k]);
         dZ[(size_t)r * kMlpWidth + k] = (__bf16)v;
         s += v;
     }
-    bias_partial[(size_t)blockIdx.x * kMlpWidth + k] = s;
+    if (half) red[k] = s;
+    __syncthreads();
+    if (!half) bias_partial[(size_t)blockIdx.x * kMlpWidth + k] = s + red[k];
 }
 
 // output layer: dWo[c][k] = sum_r dY[r][c] H6[r][k], dco[c] = sum_r dY[r][c]  (per-block partials)
-__global__ void k_mlp_out_grad(const float *dY, const __bf16 *H6, int rows, int chunk, float *partial) {
-    const int k = threadIdx.x;
-    const int r_begin = blockIdx.x * chunk, r_end = min(rows, r_begin + chunk);
+__global__ __launch_bounds__(256) void k_mlp_out_grad(const float *dY, const __bf16 *H6, int rows, float *partial) {
+    __shared__ float red[kMlpOut * kMlpWidth + kMlpOut];
+    const int k = threadIdx.x & (kMlpWidth - 1), half = threadIdx.x >> 7;
+    const int r0 = blockIdx.x * kColRows;
     float s[kMlpOut] = {0, 0, 0, 0, 0, 0}, sb[kMlpOut] = {0, 0, 0, 0, 0, 0};
-    for (int r = r_begin; r < r_end; ++r) {
+    for (int i = half; i < kColRows; i += 2) {
+        const int r = r0 + i;
+        if (r >= rows) break;
         const float h = (float)H6[(size_t)r * kMlpWidth + k];
 #pragma unroll
         for (int c = 0; c < kMlpOut; ++c) {
@@ -203,10 +215,18 @@ __global__ void k_mlp_out_grad(const float *dY, const __bf16 *H6, int rows, int 
             sb[c] += d;
         }
     }
-    float *P = partial + (size_t)blockIdx.x * (kMlpOut * kMlpWidth + kMlpOut);
+    if (half) {
 #pragma unroll
-    for (int c = 0; c < kMlpOut; ++c) P[c * kMlpWidth + k] = s[c];
-    if (k < kMlpOut) P[kMlpOut * kMlpWidth + k] = sb[k];
+        for (int c = 0; c < kMlpOut; ++c) red[c * kMlpWidth + k] = s[c];
+        if (k < kMlpOut) red[kMlpOut * kMlpWidth + k] = sb[k];
+    }
+    __syncthreads();
+    if (!half) {
+        float *P = partial + (size_t)blockIdx.x * (kMlpOut * kMlpWidth + kMlpOut);
+#pragma unroll
+        for (int c = 0; c < kMlpOut; ++c) P[c * kMlpWidth + k] = s[c] + red[c * kMlpWidth + k];
+        if (k < kMlpOut) P[kMlpOut * kMlpWidth + k] = sb[k] + red[kMlpOut * kMlpWidth + k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -318,26 +338,23 @@ hipError_t mlp_launch_loss(const MlpArgs &m, const double *pts, const double *tg
     return hipGetLastError();
 }
 
-hipError_t mlp_launch_out_back(const float *dY, const float *Wo_master, const float *Z, int rows, float *dH,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_out_back, dim3(rows), dim3(kMlpWidth), 0, s, dY, Wo_master, Z, rows, dH);
+hipError_t mlp_launch_out_back(const float *dY, const float *Wo_master, int rows, float *dH, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_out_back, dim3(rows), dim3(kMlpWidth), 0, s, dY, Wo_master, rows, dH);
     return hipGetLastError();
 }
 
-hipError_t mlp_launch_dz(const float *dH, const float *Z, int rows, int groups, __bf16 *dZ, float *bias_partial,
+hipError_t mlp_launch_dz(const float *dH, const float *Z, int rows, __bf16 *dZ, float *bias_partial,
                          float *bias_out, hipStream_t s) {
-    const int chunk = (rows + groups - 1) / groups;
-    const int g = (rows + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_mlp_dz, dim3(g), dim3(kMlpWidth), 0, s, dH, Z, rows, chunk, dZ, bias_partial);
+    const int g = (rows + kColRows - 1) / kColRows;
+    hipLaunchKernelGGL(k_mlp_dz, dim3(g), dim3(256), 0, s, dH, Z, rows, dZ, bias_partial);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kMlpWidth), 0, s, bias_partial, g, kMlpWidth, bias_out, 0);
     return hipGetLastError();
 }
 
-hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, int groups, float *partial,
-                               float *dWo, float *dco, hipStream_t s) {
-    const int chunk = (rows + groups - 1) / groups;
-    const int g = (rows + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_mlp_out_grad, dim3(g), dim3(kMlpWidth), 0, s, dY, H6, rows, chunk, partial);
+hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, float *partial, float *dWo, float *dco,
+                               hipStream_t s) {
+    const int g = (rows + kColRows - 1) / kColRows;
+    hipLaunchKernelGGL(k_mlp_out_grad, dim3(g), dim3(256), 0, s, dY, H6, rows, partial);
     const int count = kMlpOut * kMlpWidth + kMlpOut;
     // the partial block is [c][k] then [c]: sum into a staging area laid out the same way
     hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, s, partial, g, count,
@@ -347,6 +364,8 @@ hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, int 
                    hipMemcpyDeviceToDevice, s);
     return hipGetLastError();
 }
+
+int mlp_col_groups(int rows) { return (rows + kColRows - 1) / kColRows; }
 
 hipError_t mlp_launch_adam(float *p, float *mo, float *ve, const float *g, int n, float lr, float b1, float b2,
                            float eps, int step, hipStream_t s) {

@@ -21,12 +21,12 @@ hipError_t mlp_launch_wgrad(const __bf16 *D, const __bf16 *H, int rows, int grou
                             hipStream_t s);
 hipError_t mlp_launch_loss(const MlpArgs &m, const double *pts, const double *tgt, const float *Y, int npair,
                            const MlpLoss &L, float *dY, double *loss_partial, int blocks, hipStream_t s);
-hipError_t mlp_launch_out_back(const float *dY, const float *Wo_master, const float *Z, int rows, float *dH,
-                               hipStream_t s);
-hipError_t mlp_launch_dz(const float *dH, const float *Z, int rows, int groups, __bf16 *dZ, float *bias_partial,
+hipError_t mlp_launch_out_back(const float *dY, const float *Wo_master, int rows, float *dH, hipStream_t s);
+hipError_t mlp_launch_dz(const float *dH, const float *Z, int rows, __bf16 *dZ, float *bias_partial,
                          float *bias_out, hipStream_t s);
-hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, int groups, float *partial,
-                               float *dWo, float *dco, hipStream_t s);
+hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, float *partial, float *dWo, float *dco,
+                               hipStream_t s);
+int mlp_col_groups(int rows);   // partial blocks of the row-parallel column sums
 hipError_t mlp_launch_adam(float *p, float *mo, float *ve, const float *g, int n, float lr, float b1, float b2,
                            float eps, int step, hipStream_t s);
 hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, __bf16 *We, __bf16 *Woe,
