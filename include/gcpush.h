@@ -82,9 +82,10 @@ typedef struct {
     int32_t timing;         /* 1: record HIP events around each push launch (see gc_get_counters) */
     int32_t field_source;   /* GC_SOURCE_GRID (trilinear grid) or GC_SOURCE_MLP (neural field, gc_mlp_set) */
     int32_t tail_threshold; /* grid form, eager gc_advance: chunks whose live count (as read back from an
-                               earlier reorder) is below this use the latency form of the push, with
-                               every field load of a gather in flight; 0 disables.  Results are
-                               bitwise identical in both forms. */
+                               earlier reorder) is below this reorder only every 8 chunks and use a
+                               latency form of the push (every field load of a gather in flight;
+                               below a quarter of it, four lanes per particle); 0 disables.
+                               Results are bitwise identical in every form. */
 } gc_options;
 
 enum { GC_SOURCE_GRID = 0, GC_SOURCE_MLP = 1 };

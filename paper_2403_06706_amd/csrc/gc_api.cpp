@@ -229,16 +229,27 @@ uint32_t bits_for(uint32_t max_key) {
 // Tail of a run (eager advance only): once the live count read back from an
 // earlier reorder is below tail_threshold, the machine is far from full and the
 // push is bound by each wavefront's chain of dependent memory round trips.
-// Then the push takes its latency form, and the reorder runs only every
-// kTailReorderEvery chunks (particles cross about two cells per 64 steps, so
-// the cell order decays slowly, while a reorder costs a fixed ~80 us of
-// launches).  Neither choice changes any particle's trajectory.
+// Then the push takes a latency form (all loads of a gather in flight; below a
+// quarter of the threshold, four lanes per particle), and the reorder runs
+// only every kTailReorderEvery chunks (particles cross about two cells per 64
+// steps, so the cell order decays slowly, while a reorder costs a fixed ~80 us
+// of launches).  No choice changes any particle's trajectory.
 constexpr int kTailReorderEvery = 8;
 
+uint32_t seen_count(const gc_ctx *ctx) {
+    if (ctx->opt.tail_threshold <= 0 || ctx->capturing || !ctx->count_host) return 0xFFFFFFFFu;
+    return *ctx->count_host;
+}
+
 bool tail_mode(const gc_ctx *ctx) {
-    if (ctx->opt.tail_threshold <= 0 || ctx->capturing || !ctx->count_host) return false;
-    const uint32_t seen = *ctx->count_host;
+    const uint32_t seen = seen_count(ctx);
     return seen != 0xFFFFFFFFu && seen < (uint32_t)ctx->opt.tail_threshold;
+}
+
+int push_form(const gc_ctx *ctx) {
+    const uint32_t seen = seen_count(ctx);
+    if (seen == 0xFFFFFFFFu || seen >= (uint32_t)ctx->opt.tail_threshold) return 0;
+    return seen < (uint32_t)ctx->opt.tail_threshold / 4 ? 2 : 1;
 }
 
 gc_status reorder(gc_ctx *ctx, bool timed, int order) {
@@ -310,11 +321,11 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
         e1 = take_event(ctx);
         HIPCHK(hipEventRecord(e0, s));
     }
-    const bool latency = tail_mode(ctx);
+    const int form = push_form(ctx);
     if (ctx->opt.field_source == GC_SOURCE_MLP)
         HIPCHK(launch_push_mlp(a, ctx->mlp.args, ctx->opt.precision, s));
     else
-        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, latency, grid_blocks, s));
+        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, form, grid_blocks, s));
     if (timed) {
         HIPCHK(hipEventRecord(e1, s));
         ctx->ev_push.emplace_back(e0, e1);

@@ -95,12 +95,17 @@ template <> struct Pair<GC_F16> {
     }
 };
 
-// kAllPairs: issue the loads of all four node pairs at once (one memory round
-// trip per gather, more registers); otherwise at most two pairs are in
-// registers at a time, which keeps the push within two wavefronts per SIMD.
-// The arithmetic, and so the result, is the same either way.
-template <int FDT, typename R, bool kAllPairs = false>
-__device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
+// Stencil of a trilinear gather: the four node pairs (r, theta corners, each
+// with its two phi nodes) and their weights.
+template <typename R>
+struct GatherPlan {
+    R w[4];              // (r, theta) weight of each node pair
+    R wp;                // phi weight of the second node of a pair
+    uint32_t off[4];     // element offset of each pair in the packed field
+};
+
+template <typename R>
+__device__ __forceinline__ bool gather_plan(const FieldDev &f, R r, R th, R ph, GatherPlan<R> &gp) {
     R x = (r - (R)f.r_min) * (R)f.inv_dr;
     R y = th * (R)f.inv_dth - (R)0.5;
     R z = ph * (R)f.inv_dph;
@@ -111,7 +116,7 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
     R wr = clampr(x - fi, (R)0, (R)1);
     R wt = clampr(y - fj, (R)0, (R)1);
     R zf = floor(z);
-    R wp = z - zf;
+    gp.wp = z - zf;
     R km = zf - nph * floor(zf * (R)f.inv_nph);
     km = km < (R)0 ? km + nph : km;
     km = km >= nph ? km - nph : km;
@@ -120,24 +125,93 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
     const uint32_t row = (uint32_t)(f.nph + 1) * 12u;
     const uint32_t o00 = (i * (uint32_t)f.nth + j) * row + k * 12u;
     const uint32_t dI = (uint32_t)f.nth * row;
-    // sum over the eight corners: (r, theta) weight of the node pair times (1 - w_ph) or w_ph
-    const R w[4] = {((R)1 - wr) * ((R)1 - wt), ((R)1 - wr) * wt, wr * ((R)1 - wt), wr * wt};
-    const uint32_t off[4] = {o00, o00 + row, o00 + dI, o00 + dI + row};
+    gp.w[0] = ((R)1 - wr) * ((R)1 - wt);
+    gp.w[1] = ((R)1 - wr) * wt;
+    gp.w[2] = wr * ((R)1 - wt);
+    gp.w[3] = wr * wt;
+    gp.off[0] = o00;
+    gp.off[1] = o00 + row;
+    gp.off[2] = o00 + dI;
+    gp.off[3] = o00 + dI + row;
+    return true;
+}
+
+// Add node pair p (index q of the stencil) to out: for each component,
+// out = fma(wb, B, fma(wa, A, out)) with wa = w_q (1 - w_ph), wb = w_q w_ph.
+template <int FDT, typename R>
+__device__ __forceinline__ void gather_add(const FieldDev &f, const GatherPlan<R> &gp, int q, const Pair<FDT> &p,
+                                           R out[12]) {
+    const R wa = gp.w[q] * ((R)1 - gp.wp), wb = gp.w[q] * gp.wp;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = fma(wb, (R)p.get(c + 12, f), fma(wa, (R)p.get(c, f), out[c]));
+}
+
+template <typename R>
+__device__ __forceinline__ bool finite12(const R out[12]) {
+    R sum = (R)0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sum += out[c];
+    return isfinite(sum);
+}
+
+// One lane: the four node pairs added in order.
+// kAllPairs: issue the loads of all four node pairs at once (one memory round
+// trip per gather, more registers); otherwise at most two pairs are in
+// registers at a time, which keeps the push within two wavefronts per SIMD.
+// The arithmetic, and so the result, is the same either way.
+template <int FDT, typename R, bool kAllPairs = false>
+__device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
+    GatherPlan<R> gp;
+    if (!gather_plan(f, r, th, ph, gp)) return false;
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = (R)0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         Pair<FDT> p;
-        p.load(f.data, off[q]);
-        const R wa = w[q] * ((R)1 - wp), wb = w[q] * wp;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) out[c] = fma(wb, (R)p.get(c + 12, f), fma(wa, (R)p.get(c, f), out[c]));
+        p.load(f.data, gp.off[q]);
+        gather_add<FDT, R>(f, gp, q, p, out);
         if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
     }
-    R sum = (R)0;
+    return finite12(out);
+}
+
+// Word j of lane J of an aligned group of four lanes, to every lane of the
+// group (DPP quad permutation [J, J, J, J]).
+template <int J>
+__device__ __forceinline__ uint32_t quad_bcast(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, J * 0x55, 0xF, 0xF, false);
+}
+
+template <int FDT, int J>
+__device__ __forceinline__ Pair<FDT> quad_bcast_pair(const Pair<FDT> &mine) {
+    constexpr int kWords = sizeof(Pair<FDT>) / 4;
+    static_assert(sizeof(Pair<FDT>) % 4 == 0, "pair storage must be whole words");
+    uint32_t w[kWords];
+    __builtin_memcpy(w, &mine, sizeof w);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) sum += out[c];
-    return isfinite(sum);
+    for (int i = 0; i < kWords; ++i) w[i] = quad_bcast<J>(w[i]);
+    Pair<FDT> p;
+    __builtin_memcpy(&p, w, sizeof w);
+    return p;
+}
+
+// Four lanes of an aligned quad, one particle: lane gl loads node pair gl, the
+// quad shares the loaded words, and every lane adds the four pairs in the
+// one-lane order, so all four hold the bits of gather().  All four lanes must
+// call it together.
+template <int FDT, typename R>
+__device__ __forceinline__ bool gather_quad(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
+    GatherPlan<R> gp;
+    if (!gather_plan(f, r, th, ph, gp)) return false;
+    Pair<FDT> mine;
+    mine.load(f.data, gp.off[gl]);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = (R)0;
+    gather_add<FDT, R>(f, gp, 0, quad_bcast_pair<FDT, 0>(mine), out);
+    gather_add<FDT, R>(f, gp, 1, quad_bcast_pair<FDT, 1>(mine), out);
+    gather_add<FDT, R>(f, gp, 2, quad_bcast_pair<FDT, 2>(mine), out);
+    gather_add<FDT, R>(f, gp, 3, quad_bcast_pair<FDT, 3>(mine), out);
+    return finite12(out);
 }
 
 // ---------------------------------------------------------------------------

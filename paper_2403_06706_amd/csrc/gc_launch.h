@@ -15,9 +15,10 @@ struct MomDev {
     double r_lo, r_hi, sel_r_lo, sel_r_hi, age_lo, age_hi, age_max, e_lo, e_hi, e_unit, len_unit;
 };
 
-// push (gc_push.hip); latency: the form with all loads of a gather in flight
-hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, bool latency,
-                       int grid_blocks, hipStream_t s);
+// push (gc_push.hip); form: 0 throughput, 1 all pairs of a gather in flight,
+// 2 four lanes per particle (the last two for few active particles)
+hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int form, int grid_blocks,
+                       hipStream_t s);
 
 // gather ceiling (gc_probe.hip): sink[slot] for every slot below *a.n_active
 hipError_t launch_gather_probe(const PushArgs &a, double *sink, hipStream_t s);

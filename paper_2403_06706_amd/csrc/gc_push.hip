@@ -13,8 +13,16 @@
 
 namespace gc {
 
-template <int PREC, int FDT, bool LAT = false>
-__device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot) {
+// Forms of the push (all bitwise identical in their results):
+//   kFormThroughput  one lane per particle, two node pairs of a gather in registers at a time;
+//   kFormAllPairs    one lane per particle, all four pairs of a gather in flight;
+//   kFormQuad        four lanes per particle (an aligned quad): each lane loads one node pair
+//                    of every gather, all four run the rest of the step on identical values,
+//                    lane gl = 0 writes.
+enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
+
+template <int PREC, int FDT, int FORM = kFormThroughput>
+__device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
     constexpr bool kKahan = PrecT<PREC>::kKahan;
@@ -59,7 +67,9 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         bool bad = false;
         for (;;) {
             R g[12];
-            if (!gather<FDT, R, LAT>(a.f, px, pth, pph, g)) { bad = true; break; }
+            const bool ok = FORM == kFormQuad ? gather_quad<FDT, R>(a.f, px, pth, pph, gl, g)
+                                              : gather<FDT, R, FORM == kFormAllPairs>(a.f, px, pth, pph, g);
+            if (!ok) { bad = true; break; }
             if (stage == 0 && (flags & GC_FLAG_PENDING)) {
                 // collision k+1 (Eqs. 9-10): |p| kept, new pitch cosine and free path
                 const R B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -72,7 +82,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
                 s = 0;
                 k += 1;
                 flags = (flags | GC_FLAG_BOOTSTRAP) & ~GC_FLAG_PENDING;
-                if (a.log_depth > 0 && k <= (uint32_t)a.log_depth)
+                if (a.log_depth > 0 && k <= (uint32_t)a.log_depth && gl == 0)
                     a.log[(size_t)st.gid[slot] * a.log_depth + (k - 1)] = step;
             }
             R F[4], vp;
@@ -142,6 +152,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         if (r < r_in || r > r_out || th < th_lo || th > th_hi) { status = GC_EXITED; break; }
         if (e.max_steps > 0 && (int64_t)step >= e.max_steps) { status = GC_FINISHED; break; }
     }
+    if (gl != 0) return 0;
     st.r[slot] = (double)X0; st.th[slot] = (double)X1; st.ph[slot] = (double)X2; st.u[slot] = (double)X3;
     if (kKahan) {
         st.cr[slot] = (double)c0; st.cth[slot] = (double)c1; st.cph[slot] = (double)c2;
@@ -154,37 +165,46 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     return step - step0;
 }
 
-// Grid form: one slot per lane.  Workgroups are dispatched round-robin over
-// the 8 XCDs.  Only the first ceil(n_active / blockDim) workgroups have work
+// Grid form: one slot per G lanes.  Workgroups are dispatched round-robin over
+// the 8 XCDs.  Only the first ceil(G n_active / blockDim) workgroups have work
 // (active particles fill a prefix of the slots after reordering); the remap
 // gives each XCD a contiguous range of that prefix, so that (with cell-sorted
 // slots) its L2 holds the field cells of its own particles, and every XCD gets
 // an equal share however small the active prefix is.
-template <int PREC, int FDT, bool LAT>
+template <int PREC, int FDT, int FORM>
 __device__ __forceinline__ void push_grid(const PushArgs &a) {
+    constexpr uint32_t G = FORM == kFormQuad ? 4 : 1;          // lanes per particle
     const uint32_t n = *a.n_active;
-    const uint32_t nb = (n + blockDim.x - 1) / blockDim.x, b = blockIdx.x;
+    const uint32_t per_block = blockDim.x / G;                // particles per workgroup
+    const uint32_t nb = (n + per_block - 1) / per_block, b = blockIdx.x;
     if (b >= nb) return;
     const uint32_t q = nb >> 3, rem = nb & 7u, xcd = b & 7u, pos = b >> 3;
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
-    const uint32_t slot = lb * blockDim.x + threadIdx.x;
+    const uint32_t slot = lb * per_block + threadIdx.x / G;
     uint32_t taken = 0;
-    if (slot < n) taken = advance_slot<PREC, FDT, LAT>(a, slot);
+    if (slot < n) taken = advance_slot<PREC, FDT, FORM>(a, slot, threadIdx.x % G);
     count_steps(a, taken);
 }
 
 // Throughput form: at most 256 registers per lane (two wavefronts per SIMD).
 template <int PREC, int FDT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
-    push_grid<PREC, FDT, false>(a);
+    push_grid<PREC, FDT, kFormThroughput>(a);
 }
 
-// Latency form, for few active particles (the machine is far from full and
-// each wavefront's step time is its chain of dependent memory round trips):
-// every gather has all its loads in flight at once.
+// Latency forms, for fewer active particles than fill the machine: a
+// wavefront's step time is then its gathers' latency, set by the round trips
+// and by how many distinct cache lines its load instructions touch.  The
+// all-pairs form has each gather in one round trip; the quad form also spreads
+// the particles over four times as many wavefronts (and compute units).
 template <int PREC, int FDT>
-__global__ __launch_bounds__(256) void k_push_lat(PushArgs a) {
-    push_grid<PREC, FDT, true>(a);
+__global__ __launch_bounds__(256) void k_push_allpairs(PushArgs a) {
+    push_grid<PREC, FDT, kFormAllPairs>(a);
+}
+
+template <int PREC, int FDT>
+__global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
+    push_grid<PREC, FDT, kFormQuad>(a);
 }
 
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
@@ -211,15 +231,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 
 template <int PREC, int FDT>
-static hipError_t launch_t(const PushArgs &a, int block, bool persistent, bool latency, int grid_blocks,
-                           hipStream_t s) {
+static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
     if (persistent) {
         hipLaunchKernelGGL((k_push_persistent<PREC, FDT>), dim3(grid_blocks), dim3(block), 0, s, a);
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;
-        if (latency)
-            hipLaunchKernelGGL((k_push_lat<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
+        if (form == kFormQuad)
+            hipLaunchKernelGGL((k_push_quad<PREC, FDT>), dim3(4 * nb), dim3(block), 0, s, a);
+        else if (form == kFormAllPairs)
+            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
         else
             hipLaunchKernelGGL((k_push<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
     }
@@ -227,22 +248,21 @@ static hipError_t launch_t(const PushArgs &a, int block, bool persistent, bool l
 }
 
 template <int PREC>
-static hipError_t launch_p(const PushArgs &a, int block, bool persistent, bool latency, int grid_blocks,
-                           hipStream_t s) {
+static hipError_t launch_p(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
     switch (a.f.dtype) {
-        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, latency, grid_blocks, s);
-        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, latency, grid_blocks, s);
-        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, latency, grid_blocks, s);
+        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, form, grid_blocks, s);
+        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, form, grid_blocks, s);
+        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, form, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, bool latency,
-                       int grid_blocks, hipStream_t s) {
+hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int form, int grid_blocks,
+                       hipStream_t s) {
     switch (precision) {
-        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, latency, grid_blocks, s);
-        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, latency, grid_blocks, s);
-        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, latency, grid_blocks, s);
+        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, form, grid_blocks, s);
+        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, form, grid_blocks, s);
+        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, form, grid_blocks, s);
     }
     return hipErrorInvalidValue;
 }
