@@ -68,6 +68,25 @@ def build_workload(args):
     return wl, np.ascontiguousarray(field)
 
 
+def hbm_copy_rate(ctx, n_bytes=2 << 30):
+    """Achievable HBM bandwidth: gc_copy_probe over n_bytes (read + write bytes
+    per second), timed with HIP events on the library's stream."""
+    import torch
+    src = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ctx.copy_probe(dst, src, n_bytes)          # warm
+    best = 0.0
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        ctx.copy_probe(dst, src, n_bytes)
+        e1.record(ctx.stream)
+        torch.cuda.synchronize()
+        best = max(best, 2 * n_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    return best
+
+
 def gather_ceiling(ctx, wl, store):
     """Gather-only probe (gc_gather_probe) and one push chunk from the same
     state (after the warmup), each timed with HIP events on the library's
@@ -95,6 +114,7 @@ def gather_ceiling(ctx, wl, store):
     ctx.set_state(snap)
     probe, push = out["probe"], out["push"]
     return {"kernel": "gc::k_gather_probe", "state": "after the warmup chunks, 64 steps",
+            "hbm_copy_GBps": hbm_copy_rate(ctx),
             "gather_rate_particle_steps_per_s": probe["rate"],
             "gather_GBps": probe["rate"] * BYTES_PER_STEP[store] / 1e9,
             "push_rate_same_state": push["rate"], "push_frac_of_gather_ceiling": push["rate"] / probe["rate"]}
@@ -408,8 +428,11 @@ def main():
     log(f"[bench] {c['particle_steps']:.3e} particle-steps in {elapsed:.2f} s -> {value:.3e}/s; "
         f"push {c['push_ms']:.0f} ms over {c['n_push']} launches, reorder {c['reorder_ms']:.0f} ms")
 
-    avg_push_s = c["push_ms"] / 1e3 / max(c["n_push"], 1)
-    steps_per_launch = c["particle_steps"] / max(c["n_push"], 1)
+    # roofline of the dominant kernel: the throughput form of the push (k_push);
+    # the latency forms of the tail are reported beside it
+    n0 = max(c["form_launches"][0], 1)
+    avg_push_s = c["form_ms"][0] / 1e3 / n0
+    steps_per_launch = c["form_steps"][0] / n0
     algo_bytes = BYTES_PER_STEP[args.store] * steps_per_launch
     achieved = algo_bytes / avg_push_s / 1e9
     traffic = None
@@ -420,12 +443,18 @@ def main():
                 and tj.get("precision") == args.precision):
             # counters give HBM bytes per active particle-step of the push; scale to this run's launches
             traffic = round(tj["hbm_bytes_per_particle_step"] * steps_per_launch)
+    tail = {}
+    for i, name in ((1, "gc::k_push_allpairs"), (2, "gc::k_push_quad")):
+        if c["form_launches"][i]:
+            tail[name] = {"launches": c["form_launches"][i], "avg_launch_ms": c["form_ms"][i] / c["form_launches"][i],
+                          "particle_steps": c["form_steps"][i],
+                          "rate": c["form_steps"][i] / (c["form_ms"][i] * 1e-3) if c["form_ms"][i] else None}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": "gc::k_push", "avg_launch_ms": round(avg_push_s * 1e3, 4),
-                "algorithmic_bytes_per_launch": round(algo_bytes),
+                "launches": c["form_launches"][0], "algorithmic_bytes_per_launch": round(algo_bytes),
                 "bytes_per_particle_step": BYTES_PER_STEP[args.store],
-                "gather_ceiling": ceiling}
+                "gather_ceiling": ceiling, "tail_forms": tail}
 
     out = {
         "metric": "GC particle-steps/s on 1 MI355X at <=1e-4 rel err vs FP64 oracle",

@@ -240,13 +240,19 @@ gc_status gc_get_log(gc_ctx *ctx, uint32_t *dst);
 /* ----------------------------------------------------------- counters */
 /* Waits for the stream.  push_ms: summed duration of push launches recorded
  * with timing = 1; n_push: their number; particle_steps: steps taken by active
- * particles since the context was created or counters were reset. */
+ * particles since the context was created or counters were reset.  form_*: the
+ * same split by form of the grid push: [0] throughput form (and every other
+ * push: persistent, neural field), [1] all loads of a gather in flight, [2]
+ * four lanes per particle (tail_threshold). */
 typedef struct {
     double push_ms;
     int64_t n_push;
     double reorder_ms;
     int64_t n_reorder;
     uint64_t particle_steps;
+    double form_ms[3];
+    int64_t form_launches[3];
+    uint64_t form_steps[3];
 } gc_counters;
 gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out);
 gc_status gc_reset_counters(gc_ctx *ctx);

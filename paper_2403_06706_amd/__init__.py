@@ -238,7 +238,8 @@ class Context:
         c = _abi.gc_counters()
         self._check(lib.gc_get_counters(self._h, C.byref(c)))
         return {"push_ms": c.push_ms, "n_push": c.n_push, "reorder_ms": c.reorder_ms, "n_reorder": c.n_reorder,
-                "particle_steps": c.particle_steps}
+                "particle_steps": c.particle_steps, "form_ms": list(c.form_ms),
+                "form_launches": list(c.form_launches), "form_steps": list(c.form_steps)}
 
     def reset_counters(self):
         self._check(lib.gc_reset_counters(self._h))

@@ -58,7 +58,8 @@ class gc_state_view(C.Structure):
 
 class gc_counters(C.Structure):
     _fields_ = [("push_ms", C.c_double), ("n_push", C.c_int64), ("reorder_ms", C.c_double),
-                ("n_reorder", C.c_int64), ("particle_steps", C.c_uint64)]
+                ("n_reorder", C.c_int64), ("particle_steps", C.c_uint64), ("form_ms", C.c_double * 3),
+                ("form_launches", C.c_int64 * 3), ("form_steps", C.c_uint64 * 3)]
 
 
 class gc_tune_space(C.Structure):

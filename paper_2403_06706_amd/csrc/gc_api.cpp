@@ -18,6 +18,8 @@
 
 using namespace gc;
 
+constexpr int kPushForms = 3;
+
 struct GraphKey {
     double dt = 0;
     int64_t n_steps = -1;
@@ -67,13 +69,15 @@ struct gc_ctx {
     uint32_t *queue = nullptr;
     uint32_t *n_bound = nullptr;      // live prefix: slots at or past it hold no active particle
     bool bound_dirty = true;          // the bound must be reset to n before the next reorder
-    unsigned long long *steps = nullptr;
+    unsigned long long *steps = nullptr;       // [kPushForms] active particle-steps by push form
     uint32_t *log = nullptr;
     volatile uint32_t *count_host = nullptr;   // live count of the latest completed reorder (pinned)
     bool capturing = false;
     int tail_skip = 0;                         // reorders still to skip in the tail
     // timing
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_push, ev_reorder;
+    struct PushEv { hipEvent_t e0, e1; int form; };
+    std::vector<PushEv> ev_push;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_reorder;
     std::vector<hipEvent_t> ev_pool;   // recorded and read events, ready for reuse
     // graph
     hipGraphExec_t gexec = nullptr;
@@ -307,7 +311,8 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     a.n_slots = (uint32_t)ctx->n;
     a.n_steps = steps;
     a.dt = dt;
-    a.steps_done = ctx->steps;
+    const int form = ctx->opt.field_source == GC_SOURCE_MLP || ctx->opt.persistent ? 0 : push_form(ctx);
+    a.steps_done = ctx->steps + form;
     a.log = ctx->log;
     a.log_depth = ctx->opt.log_depth;
     a.tile = ctx->opt.tile;
@@ -321,14 +326,13 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
         e1 = take_event(ctx);
         HIPCHK(hipEventRecord(e0, s));
     }
-    const int form = push_form(ctx);
     if (ctx->opt.field_source == GC_SOURCE_MLP)
         HIPCHK(launch_push_mlp(a, ctx->mlp.args, ctx->opt.precision, s));
     else
         HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, form, grid_blocks, s));
     if (timed) {
         HIPCHK(hipEventRecord(e1, s));
-        ctx->ev_push.emplace_back(e0, e1);
+        ctx->ev_push.push_back({e0, e1, form});
     }
     return GC_OK;
 }
@@ -416,7 +420,7 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     ctx->n_bound = ctx->n_active + 2;
     ctx->steps = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 64);
     HIPCHK(launch_fill_u32(ctx->n_active, 0u, 3, ctx->stream));
-    HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, ctx->stream));
+    HIPCHK(launch_fill_u64(ctx->steps, 0ull, kPushForms, ctx->stream));
     void *pinned = nullptr;
     HIPCHK(hipHostMalloc(&pinned, 64, hipHostMallocCoherent));
     ctx->count_host = static_cast<volatile uint32_t *>(pinned);
@@ -429,11 +433,14 @@ void gc_destroy(gc_ctx *ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
-    for (auto *v : {&ctx->ev_push, &ctx->ev_reorder})
-        for (auto &p : *v) {
-            (void)hipEventDestroy(p.first);
-            (void)hipEventDestroy(p.second);
-        }
+    for (auto &p : ctx->ev_push) {
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    for (auto &p : ctx->ev_reorder) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
         if (ctx->soa_mem[i]) (void)hipFree(ctx->soa_mem[i]);
@@ -733,9 +740,11 @@ gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out) {
     std::memset(out, 0, sizeof *out);
     for (auto &p : ctx->ev_push) {
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
+        HIPCHK(hipEventElapsedTime(&ms, p.e0, p.e1));
         out->push_ms += ms;
         out->n_push += 1;
+        out->form_ms[p.form] += ms;
+        out->form_launches[p.form] += 1;
     }
     for (auto &p : ctx->ev_reorder) {
         float ms = 0;
@@ -743,9 +752,12 @@ gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out) {
         out->reorder_ms += ms;
         out->n_reorder += 1;
     }
-    unsigned long long steps = 0;
-    HIPCHK(hipMemcpy(&steps, ctx->steps, sizeof steps, hipMemcpyDeviceToHost));
-    out->particle_steps = steps;
+    unsigned long long steps[kPushForms] = {0, 0, 0};
+    HIPCHK(hipMemcpy(steps, ctx->steps, sizeof steps, hipMemcpyDeviceToHost));
+    for (int f = 0; f < kPushForms; ++f) {
+        out->form_steps[f] = steps[f];
+        out->particle_steps += steps[f];
+    }
     return GC_OK;
 }
 
@@ -753,14 +765,17 @@ gc_status gc_reset_counters(gc_ctx *ctx) {
     if (!ctx) return GC_EINVAL;
     HIPCHK(hipSetDevice(ctx->opt.device));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    for (auto *v : {&ctx->ev_push, &ctx->ev_reorder}) {
-        for (auto &p : *v) {
-            ctx->ev_pool.push_back(p.first);
-            ctx->ev_pool.push_back(p.second);
-        }
-        v->clear();
+    for (auto &p : ctx->ev_push) {
+        ctx->ev_pool.push_back(p.e0);
+        ctx->ev_pool.push_back(p.e1);
     }
-    HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, ctx->stream));
+    ctx->ev_push.clear();
+    for (auto &p : ctx->ev_reorder) {
+        ctx->ev_pool.push_back(p.first);
+        ctx->ev_pool.push_back(p.second);
+    }
+    ctx->ev_reorder.clear();
+    HIPCHK(launch_fill_u64(ctx->steps, 0ull, kPushForms, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return GC_OK;
 }
@@ -802,7 +817,7 @@ gc_status time_candidate(gc_ctx *ctx, const Snapshot &sn, const gc_options &o, d
     st = gc_set_state(ctx, &sn.v, sn.n);
     if (st != GC_OK) return st;
     hipStream_t s = ctx->stream;
-    HIPCHK(launch_fill_u64(ctx->steps, 0ull, 1, s));
+    HIPCHK(launch_fill_u64(ctx->steps, 0ull, kPushForms, s));
     hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
     HIPCHK(hipEventRecord(e0, s));
     st = enqueue_advance(ctx, dt, steps, false);
@@ -813,9 +828,10 @@ gc_status time_candidate(gc_ctx *ctx, const Snapshot &sn, const gc_options &o, d
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     ctx->ev_pool.push_back(e0);
     ctx->ev_pool.push_back(e1);
-    unsigned long long done = 0;
-    HIPCHK(hipMemcpy(&done, ctx->steps, sizeof done, hipMemcpyDeviceToHost));
-    *rate = ms > 0 ? (double)done / (ms * 1e-3) : 0.0;
+    unsigned long long done[kPushForms] = {0, 0, 0};
+    HIPCHK(hipMemcpy(done, ctx->steps, sizeof done, hipMemcpyDeviceToHost));
+    const double total = (double)done[0] + (double)done[1] + (double)done[2];
+    *rate = ms > 0 ? total / (ms * 1e-3) : 0.0;
     return GC_OK;
 }
 
@@ -835,8 +851,8 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *sp, gc_tune_result *out)
     gc_status st = take_snapshot(ctx, sn);
     if (st != GC_OK) return st;
     const gc_options entry = ctx->opt;
-    unsigned long long counter_saved = 0;
-    HIPCHK(hipMemcpy(&counter_saved, ctx->steps, sizeof counter_saved, hipMemcpyDeviceToHost));
+    unsigned long long counter_saved[kPushForms] = {0, 0, 0};
+    HIPCHK(hipMemcpy(counter_saved, ctx->steps, sizeof counter_saved, hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof *out);
     gc_options best = entry;
     best.timing = 0;
@@ -885,7 +901,7 @@ gc_status gc_autotune(gc_ctx *ctx, const gc_tune_space *sp, gc_tune_result *out)
     if (st != GC_OK) return st;
     st = gc_set_state(ctx, &sn.v, sn.n);
     if (st != GC_OK) return st;
-    HIPCHK(hipMemcpyAsync(ctx->steps, &counter_saved, sizeof counter_saved, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->steps, counter_saved, sizeof counter_saved, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     out->best = best;
     out->best_rate = best_rate;

@@ -1,6 +1,8 @@
 // gc_kernels.hip -- injection, field packing, moments, state copies, fills.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gc_device.h"
 #include "gc_launch.h"
 
@@ -232,17 +234,28 @@ hipError_t launch_state_in(const SoA &st, const gc_state_view &src, uint32_t n, 
 }
 
 // ---------------------------------------------------------------------------
-// Plain streaming copy (16 B per lane per iteration) for counter calibration.
+// Plain streaming copy for counter calibration and the achievable HBM rate:
+// each thread keeps four independent 16-byte loads in flight per iteration.
 // ---------------------------------------------------------------------------
-__global__ void k_copy_probe(uint4 *dst, const uint4 *src, size_t n16) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+__global__ __launch_bounds__(256) void k_copy_probe(uint4 *dst, const uint4 *src, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 hipError_t launch_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t s) {
     const size_t n16 = n_bytes / 16;
     if (n16 == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_probe, dim3(grid_for(n16, 256)), dim3(256), 0, s, static_cast<uint4 *>(dst),
+    const size_t want = (n16 + 4 * 256 - 1) / (4 * 256);           // four pieces per thread
+    const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), 8192);
+    hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(256), 0, s, static_cast<uint4 *>(dst),
                        static_cast<const uint4 *>(src), n16);
     return hipGetLastError();
 }
