@@ -74,6 +74,8 @@ struct gc_ctx {
     volatile uint32_t *count_host = nullptr;   // live count of the latest completed reorder (pinned)
     bool capturing = false;
     int tail_skip = 0;                         // reorders still to skip in the tail
+    hipEvent_t ahead[4] = {nullptr, nullptr, nullptr, nullptr};   // ends of the last chunks issued
+    int ahead_pos = 0;
     // timing
     struct PushEv { hipEvent_t e0, e1; int form; };
     std::vector<PushEv> ev_push;
@@ -239,6 +241,11 @@ uint32_t bits_for(uint32_t max_key) {
 // steps, so the cell order decays slowly, while a reorder costs a fixed ~80 us
 // of launches).  No choice changes any particle's trajectory.
 constexpr int kTailReorderEvery = 8;
+// The live count read back is only as fresh as the host's lead over the
+// device: with the tail policy on, the host issues a chunk only once the chunk
+// issued kAhead chunks earlier has finished (enough queued work to hide the
+// launches, little enough for the count to follow the run).
+constexpr int kAhead = 3;
 
 uint32_t seen_count(const gc_ctx *ctx) {
     if (ctx->opt.tail_threshold <= 0 || ctx->capturing || !ctx->count_host) return 0xFFFFFFFFu;
@@ -352,6 +359,13 @@ gc_status enqueue_advance(gc_ctx *ctx, double dt, int64_t n_steps, bool timed) {
         if (st != GC_OK) return st;
         st = push(ctx, dt, c, timed);
         if (st != GC_OK) return st;
+        if (ctx->opt.tail_threshold > 0 && !ctx->capturing) {
+            hipEvent_t &ev = ctx->ahead[ctx->ahead_pos];
+            if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            else HIPCHK(hipEventSynchronize(ev));          // the chunk issued kAhead chunks ago
+            HIPCHK(hipEventRecord(ev, ctx->stream));
+            ctx->ahead_pos = (ctx->ahead_pos + 1) % kAhead;
+        }
         left -= c;
     }
     return GC_OK;
@@ -442,6 +456,8 @@ void gc_destroy(gc_ctx *ctx) {
         (void)hipEventDestroy(p.second);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->ahead)
+        if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
         if (ctx->soa_mem[i]) (void)hipFree(ctx->soa_mem[i]);
     if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);

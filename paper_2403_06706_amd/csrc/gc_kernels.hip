@@ -254,7 +254,7 @@ hipError_t launch_copy_probe(void *dst, const void *src, size_t n_bytes, hipStre
     const size_t n16 = n_bytes / 16;
     if (n16 == 0) return hipSuccess;
     const size_t want = (n16 + 4 * 256 - 1) / (4 * 256);           // four pieces per thread
-    const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), 8192);
+    const unsigned grid = (unsigned)std::min<size_t>(std::max<size_t>(want, 1), 32768);
     hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(256), 0, s, static_cast<uint4 *>(dst),
                        static_cast<const uint4 *>(src), n16);
     return hipGetLastError();
