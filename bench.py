@@ -347,7 +347,7 @@ def cpu_baseline_mlp(args, small, f, spec, params):
     from oracle import mlp_oracle as M
     ens = replace(small.ensembles[0], n=96, seed=args.seed)
     tab = O.make_ens_table([ens])
-    p = O.inject(O.Field(small.grid, f), tab, 0, ens, np.arange(ens.n, dtype=np.uint32))
+    p = O.inject(O.Field(small.grid, f), tab, 0, np.arange(ens.n, dtype=np.uint32))
     pd = {k: np.asarray(v, dtype=np.float64) for k, v in params.items()}
     cb = O.Field(small.grid, callback=lambda r, th, ph: M.field(spec, pd, np.array([r]), np.array([th]), np.array([ph]))[0])
     t0 = time.perf_counter()
@@ -366,7 +366,7 @@ def cpu_baseline(args, wl, field):
     n_per = args.cpu_particles // len(wl.ensembles)
     of = O.Field(wl.grid, field.astype(np.float32).astype(np.float64) if args.store == "f32" else field)
     tab = O.make_ens_table(wl.ensembles)
-    p = np.concatenate([O.inject(of, tab, i, e, np.arange(n_per, dtype=np.uint32))
+    p = np.concatenate([O.inject(of, tab, i, np.arange(n_per, dtype=np.uint32))
                         for i, e in enumerate(wl.ensembles)])
     threads = O.max_threads()
     t0 = time.perf_counter()

@@ -11,6 +11,8 @@
  *   bootstrap            backward Euler start at t = 0 and after a collision (Sect. 2.2)
  *   collisions           hard-sphere scattering, Eqs. (9)-(10) (and (12))
  *   or_inject            injection of Sect. 3
+ *   rebirth              continuous injection of Sect. 3: an electron that leaves the
+ *                        shell starts again from its initial state
  * Readings of the paper where it is silent or garbled are marked READING.
  */
 #include "gc_oracle.h"
@@ -59,10 +61,11 @@ void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out
 /* uniform on [0, 1) from the top 53 bits */
 double or_u01(uint64_t x) { return (double)(x >> 11) * (1.0 / 9007199254740992.0); }
 
-/* generator block for (particle id, counter word 1, purpose) under key (seed, ensemble) */
-static void draw(const or_ens *e, uint32_t id, uint64_t w1, uint64_t purpose, double a[4])
+/* generator block for (particle id, counter word 1, purpose, generation) under
+ * key (seed, ensemble) */
+static void draw(const or_ens *e, uint32_t id, uint64_t w1, uint64_t purpose, uint32_t gen, double a[4])
 {
-    uint64_t ctr[4] = { (uint64_t)id, w1, purpose, 0 };
+    uint64_t ctr[4] = { (uint64_t)id, w1, purpose, (uint64_t)gen };
     uint64_t key[2] = { e->seed, (uint64_t)e->ensemble };
     uint64_t o[4];
     or_philox4x64_10(ctr, key, o);
@@ -239,34 +242,68 @@ static double free_path(const or_ens *e, double a)
     return e->lambda > 0.0 ? -e->lambda * log(1.0 - a) : INFINITY;
 }
 
-void or_inject(const or_field *f, const or_ens *e, uint32_t ens_index, const or_inject_params *ip,
-               const uint32_t *ids, int64_t n, or_particle *out)
+/* Initial state of particle id, generation gen (Sect. 3): released at the
+ * injection site with the recipe's energy and pitch.  Site and pitch come from
+ * the block (id, 0, inject, 0), the same for every generation (READING: a reborn
+ * electron restarts on the same line with the same initial velocity, so with
+ * its own initial state); the first free path from the block (id, 0, path, gen). */
+static void init_particle(const or_field *f, const or_ens *e, uint32_t id, uint32_t gen, or_particle *p)
+{
+    const or_inject_params *ip = &e->inj;
+    double a[4];
+    draw(e, id, 0, PURPOSE_INJECT, 0, a);
+    p->ph = ip->lon0 + ip->dlon * (2.0 * a[0] - 1.0);
+    double mup = ip->mu_lo + (ip->mu_hi - ip->mu_lo) * a[1];
+    p->r = ip->r0 + ip->dr0 * (2.0 * a[2] - 1.0);
+    double lat = ip->lat0 + ip->dlat * (2.0 * a[3] - 1.0);
+    p->th = 0.5 * OR_PI - lat;                 /* READING: magnetic latitude = heliographic latitude (aligned dipole) */
+    double gamma = 1.0 + ip->ekin / (e->m * OR_C * OR_C);
+    double pmom = e->m * OR_C * sqrt(gamma * gamma - 1.0);
+    p->u = pmom * mup / e->m;
+    p->flags = OR_BOOTSTRAP;
+    p->status = OR_ACTIVE;
+    double b[4];
+    draw(e, id, 0, PURPOSE_PATH, gen, b);
+    p->ell = free_path(e, b[0]);
+    if (outside(f, e, p->r, p->th)) { p->status = OR_EXITED; return; }
+    double fld[12];
+    if (!or_field_eval(f, p->r, p->th, p->ph, fld)) { p->status = OR_NONFINITE; return; }
+    double B = sqrt(fld[0] * fld[0] + fld[1] * fld[1] + fld[2] * fld[2]);
+    p->mu_B = pmom * pmom * (1.0 - mup * mup) / (2.0 * e->m * B);
+}
+
+void or_inject(const or_field *f, const or_ens *e, uint32_t ens_index, const uint32_t *ids, int64_t n,
+               or_particle *out)
 {
     for (int64_t i = 0; i < n; ++i) {
         or_particle *p = &out[i];
         memset(p, 0, sizeof(*p));
         p->id = ids[i];
         p->ens = ens_index;
-        double a[4];
-        draw(e, p->id, 0, PURPOSE_INJECT, a);
-        p->ph = ip->lon0 + ip->dlon * (2.0 * a[0] - 1.0);
-        double mup = ip->mu_lo + (ip->mu_hi - ip->mu_lo) * a[1];
-        p->r = ip->r0 + ip->dr0 * (2.0 * a[2] - 1.0);
-        double lat = ip->lat0 + ip->dlat * (2.0 * a[3] - 1.0);
-        p->th = 0.5 * OR_PI - lat;                 /* READING: magnetic latitude = heliographic latitude (aligned dipole) */
-        double gamma = 1.0 + ip->ekin / (e->m * OR_C * OR_C);
-        double pmom = e->m * OR_C * sqrt(gamma * gamma - 1.0);
-        p->u = pmom * mup / e->m;
-        p->flags = OR_BOOTSTRAP;
-        p->status = OR_ACTIVE;
-        double b[4];
-        draw(e, p->id, 0, PURPOSE_PATH, b);
-        p->ell = free_path(e, b[0]);
-        if (outside(f, e, p->r, p->th)) { p->status = OR_EXITED; continue; }
-        double fld[12];
-        if (!or_field_eval(f, p->r, p->th, p->ph, fld)) { p->status = OR_NONFINITE; continue; }
-        double B = sqrt(fld[0] * fld[0] + fld[1] * fld[1] + fld[2] * fld[2]);
-        p->mu_B = pmom * pmom * (1.0 - mup * mup) / (2.0 * e->m * B);
+        init_particle(f, e, p->id, 0, p);
+    }
+}
+
+/* Rebirth (Sect. 3): the electron that just left the shell is released again
+ * at once, as generation gen + 1, with age 0 and no collisions; the global step
+ * count goes on.  Its collision-log row starts again empty. */
+static void rebirth(const or_field *f, const or_ens *e, or_particle *p, const or_log *log, int64_t pi)
+{
+    const uint32_t id = p->id, ens = p->ens, step = p->step, gen = p->gen + 1;
+    memset(p, 0, sizeof(*p));
+    p->id = id;
+    p->ens = ens;
+    p->step = step;
+    p->gen = gen;
+    p->birth = step;
+    init_particle(f, e, id, gen, p);
+    if (log && log->depth > 0) {
+        for (int32_t j = 0; j < log->depth; ++j) {
+            size_t idx = (size_t)pi * log->depth + j;
+            log->step[idx] = 0xFFFFFFFFu;
+            log->mu_new[idx] = NAN;
+            log->ell[idx] = NAN;
+        }
     }
 }
 
@@ -276,7 +313,7 @@ static void collide(const or_ens *e, or_particle *p, double B, const or_log *log
 {
     p->k += 1;
     double a[4];
-    draw(e, p->id, p->k, PURPOSE_PATH, a);
+    draw(e, p->id, p->k, PURPOSE_PATH, p->gen, a);
     double m = e->m;
     double p2 = (m * p->u) * (m * p->u) + 2.0 * m * p->mu_B * B;
     double mun;
@@ -339,7 +376,7 @@ static void advance_one(const or_field *f, const or_ens *e, or_particle *p, doub
         if (e->lambda > 0.0) {
             if (e->collision_mode == 1) {
                 double a[4];
-                draw(e, p->id, p->step, PURPOSE_STEPDRAW, a);
+                draw(e, p->id, p->step, PURPOSE_STEPDRAW, p->gen, a);
                 if (a[0] < 1.0 - exp(-ds / e->lambda)) p->flags |= OR_PENDING;
             } else {
                 p->s += ds;
@@ -353,7 +390,11 @@ static void advance_one(const or_field *f, const or_ens *e, or_particle *p, doub
         p->step += 1;
         if (traj) for (int c = 0; c < 4; ++c) traj[(it + 1) * 4 + c] = Xn[c];
         if (!finite4(Xn)) { p->status = OR_NONFINITE; return; }
-        if (outside(f, e, p->r, p->th)) { p->status = OR_EXITED; return; }
+        if (outside(f, e, p->r, p->th)) {
+            if ((int64_t)p->step >= e->rebirth_steps) { p->status = OR_EXITED; return; }
+            rebirth(f, e, p, log, pi);
+            if (p->status != OR_ACTIVE) return;
+        }
         if (e->max_steps > 0 && p->step >= (uint64_t)e->max_steps) { p->status = OR_FINISHED; return; }
     }
 }
@@ -415,6 +456,7 @@ void or_moments(const or_field *f, const or_ens *ens_table, const or_particle *p
         if (q->status != OR_ACTIVE) continue;
         out[6] += fix(q->r / s->len_unit, 4294967296.0);
         if (q->k >= 1) out[7] += 1;
+        if (q->birth < s->min_birth) continue;          /* Sect. 3: only particles injected after a given time */
         double g[12];
         if (!or_field_eval(f, q->r, q->th, q->ph, g)) continue;
         double B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);

@@ -39,23 +39,25 @@ typedef struct {
 } or_field;
 
 typedef struct {
+    double ekin;           /* kinetic energy (J) */
+    double r0, lat0, lon0; /* injection site (m, rad, rad) */
+    double dlon, dr0, dlat;/* half-widths of the uniform spreads */
+    double mu_lo, mu_hi;   /* pitch-angle cosine range */
+} or_inject_params;
+
+typedef struct {
     double q, m;           /* charge (C), rest mass (kg) */
     double lambda;         /* mean free path along B (m); <= 0: no scattering */
     double r_in, r_out;    /* exit shell (m) */
     uint64_t seed;         /* generator key word 0 */
     uint32_t ensemble;     /* generator key word 1 */
     int32_t drift_free;    /* 1: only v_par b kept in dR/dt (paper Sect. 3.2 diagnostic) */
-    int64_t max_steps;     /* > 0: FINISHED after this many steps */
+    int64_t max_steps;     /* > 0: FINISHED after this many steps (counted over all generations) */
     int32_t scatter_law;   /* 0: mu' = 1 - 2a (Eq. 10); 1: mu' = +-sqrt(a) (Eq. 12) */
     int32_t collision_mode;/* 0: exponential free path per collision index; 1: per-step draw (Eq. 9 literally) */
+    int64_t rebirth_steps; /* Sect. 3 continuous injection: an exit at a step count below this is a rebirth */
+    or_inject_params inj;  /* the injection recipe a reborn particle starts from again */
 } or_ens;
-
-typedef struct {
-    double ekin;           /* kinetic energy (J) */
-    double r0, lat0, lon0; /* injection site (m, rad, rad) */
-    double dlon, dr0, dlat;/* half-widths of the uniform spreads */
-    double mu_lo, mu_hi;   /* pitch-angle cosine range */
-} or_inject_params;
 
 typedef struct {
     double r, th, ph, u;   /* guiding-centre position, u = gamma v_par */
@@ -64,13 +66,15 @@ typedef struct {
     double dtp;            /* previous step size (s) */
     double s;              /* path length since the last collision (m) */
     double ell;            /* current free path (m) */
-    double t;              /* time since injection (s) */
+    double t;              /* age: time since the current generation began (s) */
     uint32_t k;            /* collisions so far */
     uint32_t flags;        /* OR_BOOTSTRAP | OR_PENDING */
     uint32_t status;       /* OR_ACTIVE ... */
-    uint32_t step;         /* steps taken */
+    uint32_t step;         /* steps taken since the first injection, over all generations */
     uint32_t id;           /* particle id within its ensemble */
     uint32_t ens;          /* index into the ensemble table */
+    uint32_t gen;          /* generation: rebirths so far (generator counter word 3) */
+    uint32_t birth;        /* step count at which the current generation began */
 } or_particle;
 
 typedef struct {
@@ -91,6 +95,7 @@ typedef struct {
     int32_t n_ebins;   double e_lo, e_hi;      /* energy bins on [e_lo, e_hi) in units of e_unit */
     double e_unit;                             /* J per energy unit (e.g. 1 eV) */
     double len_unit;                           /* m per length unit for the r sum (e.g. 1 AU) */
+    uint32_t min_birth;                        /* binned sums: generation began at step >= min_birth */
 } or_moment_spec;
 
 void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
@@ -105,8 +110,8 @@ void or_pc_predict(const double X[4], const double Fn[4], const double Fp[4],
 void or_pc_correct(const double X[4], const double Fn[4], const double Fs[4], const double Fp[4],
                    double h, double tau, double out[4]);
 
-void or_inject(const or_field *f, const or_ens *e, uint32_t ens_index, const or_inject_params *ip,
-               const uint32_t *ids, int64_t n, or_particle *out);
+void or_inject(const or_field *f, const or_ens *e, uint32_t ens_index, const uint32_t *ids, int64_t n,
+               or_particle *out);
 void or_advance(const or_field *f, const or_ens *ens_table, or_particle *p, int64_t n,
                 double dt, int64_t n_steps, int nthreads, const or_log *log);
 void or_advance_traj(const or_field *f, const or_ens *ens_table, or_particle *p,

@@ -20,8 +20,9 @@ PARTICLE_DTYPE = np.dtype([
     ("r", "f8"), ("th", "f8"), ("ph", "f8"), ("u", "f8"), ("mu_B", "f8"),
     ("fp", "f8", (4,)), ("dtp", "f8"), ("s", "f8"), ("ell", "f8"), ("t", "f8"),
     ("k", "u4"), ("flags", "u4"), ("status", "u4"), ("step", "u4"), ("id", "u4"), ("ens", "u4"),
+    ("gen", "u4"), ("birth", "u4"),
 ], align=True)
-assert PARTICLE_DTYPE.itemsize == 128
+assert PARTICLE_DTYPE.itemsize == 136
 
 
 class _Field(C.Structure):
@@ -31,17 +32,18 @@ class _Field(C.Structure):
                 ("eval", EVAL_FN), ("user", C.c_void_p)]
 
 
-class _Ens(C.Structure):
-    _fields_ = [("q", C.c_double), ("m", C.c_double), ("lam", C.c_double),
-                ("r_in", C.c_double), ("r_out", C.c_double), ("seed", C.c_uint64),
-                ("ensemble", C.c_uint32), ("drift_free", C.c_int32), ("max_steps", C.c_int64),
-                ("scatter_law", C.c_int32), ("collision_mode", C.c_int32)]
-
-
 class _Inject(C.Structure):
     _fields_ = [("ekin", C.c_double), ("r0", C.c_double), ("lat0", C.c_double), ("lon0", C.c_double),
                 ("dlon", C.c_double), ("dr0", C.c_double), ("dlat", C.c_double),
                 ("mu_lo", C.c_double), ("mu_hi", C.c_double)]
+
+
+class _Ens(C.Structure):
+    _fields_ = [("q", C.c_double), ("m", C.c_double), ("lam", C.c_double),
+                ("r_in", C.c_double), ("r_out", C.c_double), ("seed", C.c_uint64),
+                ("ensemble", C.c_uint32), ("drift_free", C.c_int32), ("max_steps", C.c_int64),
+                ("scatter_law", C.c_int32), ("collision_mode", C.c_int32),
+                ("rebirth_steps", C.c_int64), ("inj", _Inject)]
 
 
 class _Log(C.Structure):
@@ -55,7 +57,7 @@ class _MomentSpec(C.Structure):
                 ("age_lo", C.c_double), ("age_hi", C.c_double), ("min_collisions", C.c_int32),
                 ("n_agebins", C.c_int32), ("age_max", C.c_double), ("n_ebins", C.c_int32),
                 ("e_lo", C.c_double), ("e_hi", C.c_double), ("e_unit", C.c_double),
-                ("len_unit", C.c_double)]
+                ("len_unit", C.c_double), ("min_birth", C.c_uint32)]
 
 
 def _load():
@@ -73,7 +75,7 @@ def _load():
     L.or_rhs.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P]
     L.or_pc_predict.argtypes = [P, P, P, C.c_double, C.c_double, P]
     L.or_pc_correct.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
-    L.or_inject.argtypes = [C.POINTER(_Field), C.POINTER(_Ens), C.c_uint32, C.POINTER(_Inject), P, C.c_int64, P]
+    L.or_inject.argtypes = [C.POINTER(_Field), C.POINTER(_Ens), C.c_uint32, P, C.c_int64, P]
     L.or_advance.argtypes = [C.POINTER(_Field), P, P, C.c_int64, C.c_double, C.c_int64, C.c_int, C.POINTER(_Log)]
     L.or_advance_traj.argtypes = [C.POINTER(_Field), P, P, C.c_double, C.c_int64, P]
     L.or_moments_size.argtypes = [C.POINTER(_MomentSpec)]
@@ -178,16 +180,18 @@ def make_ens_table(ensembles, collision_mode: int = 0):
     """ensembles: objects with the attributes of synthetic.workloads.Ensemble."""
     arr = (_Ens * max(1, len(ensembles)))()
     for i, e in enumerate(ensembles):
+        inj = _Inject(e.ekin, e.r0, e.lat0, e.lon0, e.dlon, e.dr0, e.dlat, e.mu_lo, e.mu_hi)
         arr[i] = _Ens(e.q, e.m, e.lambda_par, e.r_in, e.r_out, e.seed, e.ensemble, int(e.drift_free),
-                      int(e.max_steps), int(e.scatter_law), int(collision_mode))
+                      int(e.max_steps), int(e.scatter_law), int(collision_mode),
+                      int(getattr(e, "rebirth_steps", 0)), inj)
     return arr
 
 
-def inject(field: Field, ens_table, ens_index: int, ens, ids: np.ndarray) -> np.ndarray:
+def inject(field: Field, ens_table, ens_index: int, ids: np.ndarray) -> np.ndarray:
+    """Particles ids of ensemble ens_table[ens_index] (its injection recipe is in the table)."""
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     out = np.zeros(len(ids), dtype=PARTICLE_DTYPE)
-    ip = _Inject(ens.ekin, ens.r0, ens.lat0, ens.lon0, ens.dlon, ens.dr0, ens.dlat, ens.mu_lo, ens.mu_hi)
-    lib.or_inject(field.ref, C.byref(ens_table[ens_index]), ens_index, C.byref(ip), _ptr(ids), len(ids), _ptr(out))
+    lib.or_inject(field.ref, C.byref(ens_table[ens_index]), ens_index, _ptr(ids), len(ids), _ptr(out))
     return out
 
 
@@ -235,11 +239,12 @@ class MomentSpec:
     e_hi: float = 1.0
     e_unit: float = 1.602176634e-19
     len_unit: float = 1.495978707e11
+    min_birth: int = 0
 
     def _c(self):
         return _MomentSpec(self.n_rbins, self.r_lo, self.r_hi, self.n_mubins, self.sel_r_lo, self.sel_r_hi,
                            self.age_lo, self.age_hi, self.min_collisions, self.n_agebins, self.age_max,
-                           self.n_ebins, self.e_lo, self.e_hi, self.e_unit, self.len_unit)
+                           self.n_ebins, self.e_lo, self.e_hi, self.e_unit, self.len_unit, self.min_birth)
 
 
 def moments_size(spec: MomentSpec) -> int:

@@ -46,6 +46,7 @@ class Ensemble:
     m: float = M_ELECTRON
     drift_free: bool = False
     scatter_law: int = 0                # 0: mu' = 1 - 2a ; 1: mu' = +-sqrt(a)
+    rebirth_steps: int = 0              # > 0: an exit before this step count is a rebirth
 
 
 @dataclass

@@ -51,7 +51,7 @@ def test_graph_persistent_equals_eager_and_oracle(batched):
     ids = [np.sort(rng.choice(e.n, size=8, replace=False)).astype(np.uint32) for e in wl.ensembles]
     of = O.Field(wl.grid, f)
     tab = O.make_ens_table(wl.ensembles)
-    p = np.concatenate([O.inject(of, tab, i, e, ids[i]) for i, e in enumerate(wl.ensembles)])
+    p = np.concatenate([O.inject(of, tab, i, ids[i]) for i, e in enumerate(wl.ensembles)])
     O.advance(of, tab, p, wl.dt, steps)
     offs = np.cumsum([0] + [e.n for e in wl.ensembles])[:-1]
     gsel = np.concatenate([offs[i] + ids[i] for i in range(len(ids))])

@@ -167,7 +167,7 @@ def test_push_with_network_matches_oracle(net):
     ens = replace(wl.ensembles[0], n=48, lambda_par=0.0, r_in=0.12 * AU, r_out=1.95 * AU)
     of = O.Field(wl.grid, f)
     tab = O.make_ens_table([ens])
-    p = O.inject(of, tab, 0, ens, np.arange(ens.n, dtype=np.uint32))
+    p = O.inject(of, tab, 0, np.arange(ens.n, dtype=np.uint32))
     ctx = gcp.Context(device=0, field_source="mlp")
     ctx.load_field(wl.grid, f, "f64")
     ctx.mlp_set(spec.freq, spec.r_ref, spec.scale, spec.power, params)

@@ -109,7 +109,7 @@ def test_trajectories_through_the_network_stay_with_the_closed_form(trained):
     ctx, wl, f, spec = trained["ctx"], trained["wl"], trained["f"], trained["spec"]
     ens = replace(wl.ensembles[0], n=256, lambda_par=0.0, seed=11, r_in=0.12 * AU)
     tab = O.make_ens_table([ens])
-    p0 = O.inject(O.Field(wl.grid, f), tab, 0, ens, np.arange(ens.n, dtype=np.uint32))
+    p0 = O.inject(O.Field(wl.grid, f), tab, 0, np.arange(ens.n, dtype=np.uint32))
     truth = p0.copy()
     O.advance(O.Field(wl.grid, parker=PARKER), tab, truth, 1.0, 2000)
     params = ctx.mlp_params()

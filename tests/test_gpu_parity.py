@@ -112,7 +112,7 @@ def test_several_ensembles_and_variable_step():
     ctx.close()
     of = O.Field(wl.grid, f)
     tab = O.make_ens_table(ens)
-    p = np.concatenate([O.inject(of, tab, i, e, np.arange(e.n, dtype=np.uint32)) for i, e in enumerate(ens)])
+    p = np.concatenate([O.inject(of, tab, i, np.arange(e.n, dtype=np.uint32)) for i, e in enumerate(ens)])
     for dt, n in ((1.0, 300), (0.5, 200), (2.0, 100)):
         O.advance(of, tab, p, dt, n)
     compare(st, p, M_ELECTRON, TOL64, "ensembles + variable dt")

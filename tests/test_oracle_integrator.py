@@ -62,7 +62,7 @@ def test_corrector_error_constant_at_constant_step():
 def _particle(field, ens, mu=0.5, r0=0.28 * AU, lat=math.radians(24.0), ph=0.1):
     e = replace(ens, r0=r0, lat0=lat, lon0=ph, dlon=0.0, dr0=0.0, dlat=0.0, mu_lo=mu, mu_hi=mu)
     tab = O.make_ens_table([e])
-    p = O.inject(field, tab, 0, e, np.array([7], dtype=np.uint32))
+    p = O.inject(field, tab, 0, np.array([7], dtype=np.uint32))
     return p, tab
 
 

@@ -119,8 +119,8 @@ def test_callback_field_reproduces_builtin_field():
     ens = replace(ens, r0=0.28 * AU, lat0=math.radians(24.0), lon0=0.1)
     tab = O.make_ens_table([ens])
     ids = np.arange(6, dtype=np.uint32)
-    p1 = O.inject(builtin, tab, 0, ens, ids)
-    p2 = O.inject(cb, tab, 0, ens, ids)
+    p1 = O.inject(builtin, tab, 0, ids)
+    p2 = O.inject(cb, tab, 0, ids)
     assert p1.tobytes() == p2.tobytes()
     O.advance(builtin, tab, p1, 1.0, 400)
     O.advance(cb, tab, p2, 1.0, 400)

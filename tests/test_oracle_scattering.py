@@ -21,7 +21,7 @@ def _run(n=2000, lam=0.02 * AU, steps=400, law=0, mode=0, seed=0, depth=64, mu_l
     e = Ensemble(n=n, ensemble=2, seed=seed, r0=1.0 * AU, lat0=0.0, dlon=0.5, lambda_par=lam,
                  r_in=0.11 * AU, r_out=1.85 * AU, scatter_law=law, mu_lo=mu_lo, mu_hi=mu_hi)
     tab = O.make_ens_table([e], collision_mode=mode)
-    p = O.inject(field, tab, 0, e, np.arange(n, dtype=np.uint32))
+    p = O.inject(field, tab, 0, np.arange(n, dtype=np.uint32))
     ell0 = p["ell"].copy()
     u0 = p["u"].copy()
     logs = O.advance(field, tab, p, 1.0, steps, log_depth=depth)
@@ -115,7 +115,7 @@ def test_paper_collision_time_scale():
     e = Ensemble(n=1, ensemble=0, seed=0, r0=1.0 * AU, lat0=0.0, mu_lo=1.0, mu_hi=1.0,
                  lambda_par=0.5 * AU, r_in=0.11 * AU, r_out=1.85 * AU)
     tab = O.make_ens_table([e])
-    p = O.inject(field, tab, 0, e, np.array([0], dtype=np.uint32))
+    p = O.inject(field, tab, 0, np.array([0], dtype=np.uint32))
     gam = 1.0 + 81.0 * KEV / (M_ELECTRON * C_LIGHT ** 2)
     v = p["u"][0] / gam
     assert v / C_LIGHT == pytest.approx(0.5049, abs=2e-4)
