@@ -58,8 +58,8 @@ typedef enum { GC_PREC_F64 = 0, GC_PREC_F32_ACC64 = 1, GC_PREC_F32_KAHAN = 2 } g
 
 /* particle status */
 enum { GC_ACTIVE = 0, GC_EXITED = 1, GC_FINISHED = 2, GC_NONFINITE = 3 };
-/* particle flags */
-enum { GC_FLAG_BOOTSTRAP = 1u, GC_FLAG_PENDING = 2u };
+/* particle flags; bits GC_FLAG_GEN_SHIFT.. hold the generation (rebirths so far) */
+enum { GC_FLAG_BOOTSTRAP = 1u, GC_FLAG_PENDING = 2u, GC_FLAG_GEN_SHIFT = 8 };
 
 /* Particle reordering before each chunk of steps. */
 enum {
@@ -136,6 +136,15 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *desc);
  * and its first free path from counter (id, 0, 0, 0): ell_0 = -lambda ln(1 - a0).
  * u = gamma v mu from ekin; mu_B/m = (p/m)^2 (1 - mu^2) / (2 |B(R0)|).
  * A particle placed outside [r_in, r_out] x [th_0, th_{nth-1}] is EXITED.
+ * Continuous injection (Sect. 3): a particle that leaves the shell at the end of
+ * a step whose step count (counted from its first injection, over all
+ * generations) is below rebirth_steps is reborn at once, in the same step:
+ * generation g + 1 starts from the same initial state (counter (id, 0, 1, 0)
+ * again), with age t = 0, no collisions, a bootstrap start, the state field
+ * birth set to that step count, and draws from counter word 3 = g + 1 (first
+ * free path (id, 0, 0, g + 1), collision k (id, k, 0, g + 1)).  Its collision
+ * log row is cleared.  rebirth_steps <= 0 turns rebirth off; at most 2^24; not
+ * supported with the network field source (GC_EINVAL from gc_advance).
  * Ensemble parameters (q, m, lambda_par, r_in, r_out, max_steps, drift_free,
  * scatter_law, seed) are stored per ensemble index; injecting again into an
  * existing ensemble index replaces them.  lambda_par <= 0 disables scattering;
@@ -143,8 +152,8 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *desc);
  * keeps only v_par b in dR/dt (Sect. 3.2); scatter_law 0: mu' = 1 - 2a (Eq. 10),
  * 1: mu' = +-sqrt(a) (Eq. 12).
  * Errors: GC_ESTATE before gc_load_field; GC_EINVAL for ensemble >= 4096,
- * m <= 0, q == 0, ekin <= 0, r_in >= r_out, mu_lo/mu_hi outside [-1, 1].
- * n == 0 is a no-op. */
+ * m <= 0, q == 0, ekin <= 0, r_in >= r_out, mu_lo/mu_hi outside [-1, 1],
+ * rebirth_steps > 2^24.  n == 0 is a no-op. */
 typedef struct {
     uint32_t ensemble;
     uint32_t first_id;
@@ -160,6 +169,7 @@ typedef struct {
     int64_t max_steps;
     int32_t drift_free;
     int32_t scatter_law;
+    int64_t rebirth_steps;  /* > 0: rebirth of particles that exit before this step count */
 } gc_inject_desc;
 
 gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *desc);
@@ -169,7 +179,8 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *desc);
  * exits, finishes or meets a non-finite value.  Per step (Eqs. 5-6 and 9-10):
  * gather at X^n; apply a pending collision; F^n; bootstrap F^{n-1} if flagged;
  * predictor X*; gather and F*; corrector X^{n+1}; path += (|v_par^n| + |v_par*|) dt / 2,
- * collision pending once the path reaches the free path; exit/finish tests.
+ * collision pending once the path reaches the free path; exit test (with
+ * rebirth when the ensemble asks for it); finish test.
  * tau = dt / (previous dt) on the first step after a change of dt.
  * The work is split in launches of chunk_steps steps, each preceded by the
  * configured reordering.  Errors: GC_ESTATE without field; GC_EINVAL if dt is
@@ -183,7 +194,9 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps);
 /* -------------------------------------------------------------- moments */
 /* Snapshot statistics (Sect. 3: <sin^2 alpha>(r), energy versus age near
  * 1 AU, pitch-cosine distributions).  out: caller-owned DEVICE buffer of
- * gc_moments_size(spec) int64 values, overwritten:
+ * gc_moments_size(spec) int64 values, overwritten (accumulate == 0) or added
+ * to (accumulate != 0: the sum over snapshots of the steady-state statistics
+ * of Sect. 3, one call per snapshot, no host round trip):
  *   [0..3] particles per status, [4] sum of collision counts, [5] sum of steps,
  *   [6] sum over active particles of floor(r/len_unit * 2^32),
  *   [7] active particles with at least one collision,
@@ -193,8 +206,11 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps);
  *     r in [sel_r_lo, sel_r_hi), age in [age_lo, age_hi), k >= min_collisions,
  *   then n_agebins x n_ebins counts of (age on [0, age_max), E on [e_lo, e_hi))
  *     for active particles with r in [sel_r_lo, sel_r_hi).
+ * The three binned sections count only particles whose current generation
+ * began at a step count >= min_birth (Sect. 3 keeps particles injected once
+ * the steady state is reached); [0..7] count every particle.
  * alpha is the pitch angle, E = (gamma - 1) m c^2 with |B| interpolated at the
- * particle, age = time since injection.  Integer sums: the result does not
+ * particle, age = time since (re)injection.  Integer sums: the result does not
  * depend on the particle order.  Errors: GC_EINVAL for out == NULL, negative
  * bin counts, empty ranges, or more than 8192 outputs. */
 typedef struct {
@@ -207,6 +223,8 @@ typedef struct {
     int32_t n_ebins;   double e_lo, e_hi;
     double e_unit;     /* J per energy unit */
     double len_unit;   /* m per length unit */
+    uint32_t min_birth;  /* binned sections: generation began at step count >= min_birth */
+    int32_t accumulate;  /* nonzero: add into out instead of overwriting it */
 } gc_moment_spec;
 
 int64_t gc_moments_size(const gc_moment_spec *spec);
@@ -223,6 +241,7 @@ typedef struct {
     double *dtp, *s, *ell, *t;
     double *cr, *cth, *cph, *cu, *ct;
     uint32_t *k, *flags, *status, *step, *id, *ens;
+    uint32_t *birth;                   /* step count at which the current generation began */
 } gc_state_view;
 
 /* Number of particles injected so far. */

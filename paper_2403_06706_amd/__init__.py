@@ -171,7 +171,7 @@ class Context:
         d = _abi.gc_inject_desc(ens.ensemble, first_id, ens.n if n is None else n, ens.seed, ens.q, ens.m, ens.ekin,
                                 ens.r0, ens.lat0, ens.lon0, ens.dlon, ens.dr0, ens.dlat, ens.mu_lo, ens.mu_hi,
                                 ens.lambda_par, ens.r_in, ens.r_out, int(ens.max_steps), int(ens.drift_free),
-                                int(ens.scatter_law))
+                                int(ens.scatter_law), int(getattr(ens, "rebirth_steps", 0)))
         self._check(lib.gc_inject(self._h, C.byref(d)))
 
     # ------------------------------------------------------------- advance
@@ -183,16 +183,23 @@ class Context:
 
     # ------------------------------------------------------------- moments
     @staticmethod
-    def _spec(spec) -> _abi.gc_moment_spec:
+    def _spec(spec, accumulate: bool = False) -> _abi.gc_moment_spec:
         return _abi.gc_moment_spec(spec.n_rbins, spec.r_lo, spec.r_hi, spec.n_mubins, spec.sel_r_lo, spec.sel_r_hi,
                                    spec.age_lo, spec.age_hi, spec.min_collisions, spec.n_agebins, spec.age_max,
-                                   spec.n_ebins, spec.e_lo, spec.e_hi, spec.e_unit, spec.len_unit)
+                                   spec.n_ebins, spec.e_lo, spec.e_hi, spec.e_unit, spec.len_unit,
+                                   int(getattr(spec, "min_birth", 0)), 1 if accumulate else 0)
 
-    def moments(self, spec):
+    def moments(self, spec, out=None):
+        """Snapshot statistics; with out (an int64 device tensor of the moments
+        size) they are added into out on the device instead (accumulation over
+        snapshots), and out is returned."""
         torch = _torch()
-        s = self._spec(spec)
-        m = lib.gc_moments_size(C.byref(s))
-        out = torch.empty(max(int(m), 1), dtype=torch.int64, device=f"cuda:{self.device}")
+        s = self._spec(spec, accumulate=out is not None)
+        m = int(lib.gc_moments_size(C.byref(s)))
+        if out is None:
+            out = torch.empty(max(m, 1), dtype=torch.int64, device=f"cuda:{self.device}")
+        elif out.dtype != torch.int64 or out.numel() < m or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous int64 tensor of at least {m} values")
         self._inputs_ready()
         self._check(lib.gc_moments(self._h, C.byref(s), C.c_void_p(out.data_ptr())))
         self._outputs_ready(out)

@@ -36,7 +36,7 @@ class gc_inject_desc(C.Structure):
                 ("dlon", C.c_double), ("dr0", C.c_double), ("dlat", C.c_double),
                 ("mu_lo", C.c_double), ("mu_hi", C.c_double), ("lambda_par", C.c_double),
                 ("r_in", C.c_double), ("r_out", C.c_double), ("max_steps", C.c_int64),
-                ("drift_free", C.c_int32), ("scatter_law", C.c_int32)]
+                ("drift_free", C.c_int32), ("scatter_law", C.c_int32), ("rebirth_steps", C.c_int64)]
 
 
 class gc_moment_spec(C.Structure):
@@ -44,12 +44,13 @@ class gc_moment_spec(C.Structure):
                 ("n_mubins", C.c_int32), ("sel_r_lo", C.c_double), ("sel_r_hi", C.c_double),
                 ("age_lo", C.c_double), ("age_hi", C.c_double), ("min_collisions", C.c_int32),
                 ("n_agebins", C.c_int32), ("age_max", C.c_double), ("n_ebins", C.c_int32),
-                ("e_lo", C.c_double), ("e_hi", C.c_double), ("e_unit", C.c_double), ("len_unit", C.c_double)]
+                ("e_lo", C.c_double), ("e_hi", C.c_double), ("e_unit", C.c_double), ("len_unit", C.c_double),
+                ("min_birth", C.c_uint32), ("accumulate", C.c_int32)]
 
 
 STATE_DOUBLES = ("r", "th", "ph", "u", "mu", "fr", "fth", "fph", "fu", "dtp", "s", "ell", "t",
                  "cr", "cth", "cph", "cu", "ct")
-STATE_U32 = ("k", "flags", "status", "step", "id", "ens")
+STATE_U32 = ("k", "flags", "status", "step", "id", "ens", "birth")
 
 
 class gc_state_view(C.Structure):

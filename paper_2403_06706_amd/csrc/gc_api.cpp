@@ -55,10 +55,12 @@ struct gc_ctx {
     bool have_field = false;
     void *field_buf = nullptr;
     FieldDev f{};
+    FieldDev *f_dev = nullptr;        // device copy of f
     // ensembles
     std::vector<EnsDev> ens_host;
     std::vector<char> ens_set;
     EnsDev *ens_dev = nullptr;
+    bool any_rebirth = false;         // some ensemble has rebirth_steps > 0
     // particles (A is current, B is the permutation target)
     uint64_t n = 0, cap = 0;
     void *soa_mem[2] = {nullptr, nullptr};
@@ -131,7 +133,7 @@ void carve(void *mem, uint64_t cap, SoA &s) {
                                      &s.dtp, &s.s, &s.ell, &s.t, &s.cr, &s.cth, &s.cph, &s.cu, &s.ct};
     for (int i = 0; i < kNumDoubleArrays; ++i) *dp[i] = d + (size_t)i * cap;
     uint32_t *u = reinterpret_cast<uint32_t *>(d + (size_t)kNumDoubleArrays * cap);
-    uint32_t **up[kNumU32Arrays] = {&s.k, &s.flags, &s.status, &s.step, &s.id, &s.ens, &s.gid};
+    uint32_t **up[kNumU32Arrays] = {&s.k, &s.flags, &s.status, &s.step, &s.id, &s.ens, &s.gid, &s.birth};
     for (int i = 0; i < kNumU32Arrays; ++i) *up[i] = u + (size_t)i * cap;
 }
 
@@ -179,8 +181,9 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
         for (int i = 0; i < kNumDoubleArrays; ++i)
             HIPCHK(hipMemcpyAsync(*dst_d[i], *src_d[i], ctx->n * 8, hipMemcpyDeviceToDevice, s));
         uint32_t **src_u[kNumU32Arrays] = {&ctx->A.k, &ctx->A.flags, &ctx->A.status, &ctx->A.step,
-                                           &ctx->A.id, &ctx->A.ens, &ctx->A.gid};
-        uint32_t **dst_u[kNumU32Arrays] = {&na.k, &na.flags, &na.status, &na.step, &na.id, &na.ens, &na.gid};
+                                           &ctx->A.id, &ctx->A.ens, &ctx->A.gid, &ctx->A.birth};
+        uint32_t **dst_u[kNumU32Arrays] = {&na.k, &na.flags, &na.status, &na.step, &na.id, &na.ens, &na.gid,
+                                           &na.birth};
         for (int i = 0; i < kNumU32Arrays; ++i)
             HIPCHK(hipMemcpyAsync(*dst_u[i], *src_u[i], ctx->n * 4, hipMemcpyDeviceToDevice, s));
         if (log && ctx->log)
@@ -313,7 +316,9 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     PushArgs a{};
     a.st = ctx->A;
     a.f = ctx->f;
+    a.fdev = ctx->f_dev;
     a.ens = ctx->ens_dev;
+    a.rebirth = ctx->any_rebirth ? 1 : 0;
     a.n_active = ctx->n_active;
     a.n_slots = (uint32_t)ctx->n;
     a.n_steps = steps;
@@ -378,6 +383,8 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
     if (n_steps < 0) return fail(ctx, GC_EINVAL, "n_steps must be >= 0");
     if (ctx->opt.field_source == GC_SOURCE_MLP && !ctx->mlp.set)
         return fail(ctx, GC_ESTATE, "field_source is the neural field but gc_mlp_set was not called");
+    if (ctx->opt.field_source == GC_SOURCE_MLP && ctx->any_rebirth)
+        return fail(ctx, GC_EINVAL, "rebirth is not supported with the neural field source");
     return GC_OK;
 }
 
@@ -427,6 +434,7 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     ctx->ens_host.assign(kMaxEnsembles, EnsDev{});
     ctx->ens_set.assign(kMaxEnsembles, 0);
     HIPCHK(hipMalloc(&ctx->ens_dev, sizeof(EnsDev) * kMaxEnsembles));
+    HIPCHK(hipMalloc(&ctx->f_dev, sizeof(FieldDev)));
     void *small = nullptr;
     HIPCHK(hipMalloc(&small, 256));
     ctx->n_active = static_cast<uint32_t *>(small);
@@ -466,6 +474,7 @@ void gc_destroy(gc_ctx *ctx) {
     if (ctx->mlp.mem) (void)hipFree(ctx->mlp.mem);
     if (ctx->mlp.ws) (void)hipFree(ctx->mlp.ws);
     if (ctx->ens_dev) (void)hipFree(ctx->ens_dev);
+    if (ctx->f_dev) (void)hipFree(ctx->f_dev);
     if (ctx->n_active) (void)hipFree(ctx->n_active);
     if (ctx->count_host) (void)hipHostFree(const_cast<uint32_t *>(ctx->count_host));
     delete ctx;
@@ -564,6 +573,8 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     f.th_lo = 0.5 * pi / d->nth;
     f.th_hi = pi - 0.5 * pi / d->nth;
     for (int c = 0; c < 12; ++c) f.scale[c] = scale[c];
+    HIPCHK(hipMemcpyAsync(ctx->f_dev, &ctx->f, sizeof(FieldDev), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
     ctx->have_field = true;
     if (ctx->gexec) {
         (void)hipGraphExecDestroy(ctx->gexec);
@@ -582,6 +593,8 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
     if (!(d->mu_lo >= -1.0 && d->mu_lo <= 1.0 && d->mu_hi >= -1.0 && d->mu_hi <= 1.0))
         return fail(ctx, GC_EINVAL, "mu_lo and mu_hi must be in [-1, 1]");
     if (d->scatter_law != 0 && d->scatter_law != 1) return fail(ctx, GC_EINVAL, "scatter_law must be 0 or 1");
+    if (d->rebirth_steps > (int64_t)kMaxRebirthSteps)
+        return fail(ctx, GC_EINVAL, "rebirth_steps must be <= %lld", (long long)kMaxRebirthSteps);
     if (d->n == 0) return GC_OK;
     if ((uint64_t)d->first_id + d->n > 0x100000000ull) return fail(ctx, GC_EINVAL, "ids exceed 32 bits");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -599,12 +612,24 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
     e.ensemble = d->ensemble;
     e.drift_free = d->drift_free ? 1 : 0;
     e.scatter_law = d->scatter_law;
+    e.ekin = d->ekin;
+    e.r0 = d->r0;
+    e.lat0 = d->lat0;
+    e.lon0 = d->lon0;
+    e.dlon = d->dlon;
+    e.dr0 = d->dr0;
+    e.dlat = d->dlat;
+    e.mu_lo = d->mu_lo;
+    e.mu_hi = d->mu_hi;
+    e.rebirth_steps = d->rebirth_steps;
     ctx->ens_host[d->ensemble] = e;
     ctx->ens_set[d->ensemble] = 1;
+    ctx->any_rebirth = false;
+    for (int i = 0; i < kMaxEnsembles; ++i)
+        if (ctx->ens_set[i] && ctx->ens_host[i].rebirth_steps > 0) ctx->any_rebirth = true;
     HIPCHK(hipMemcpyAsync(ctx->ens_dev + d->ensemble, &ctx->ens_host[d->ensemble], sizeof(EnsDev),
                           hipMemcpyHostToDevice, ctx->stream));
-    InjectParams ip{d->ekin, d->r0, d->lat0, d->lon0, d->dlon, d->dr0, d->dlat, d->mu_lo, d->mu_hi};
-    HIPCHK(launch_inject(ctx->A, ctx->f, e, ip, (uint32_t)ctx->n, (uint32_t)d->n, d->first_id, d->ensemble,
+    HIPCHK(launch_inject(ctx->A, ctx->f, e, (uint32_t)ctx->n, (uint32_t)d->n, d->first_id, d->ensemble,
                          ctx->stream));
     ctx->n += d->n;
     ctx->bound_dirty = true;
@@ -700,6 +725,8 @@ gc_status gc_moments(gc_ctx *ctx, const gc_moment_spec *s, int64_t *out) {
     m.e_hi = s->e_hi;
     m.e_unit = s->e_unit;
     m.len_unit = s->len_unit;
+    m.min_birth = s->min_birth;
+    m.accumulate = s->accumulate != 0;
     HIPCHK(launch_moments(ctx->A, ctx->f, ctx->ens_dev, (uint32_t)ctx->n, m,
                           reinterpret_cast<unsigned long long *>(out), ctx->stream));
     return GC_OK;
@@ -723,7 +750,7 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
     if (!ctx->have_field) return fail(ctx, GC_ESTATE, "gc_set_state before gc_load_field");
     const void *ptrs[] = {src->r, src->th, src->ph, src->u, src->mu, src->fr, src->fth, src->fph, src->fu,
                           src->dtp, src->s, src->ell, src->t, src->cr, src->cth, src->cph, src->cu, src->ct,
-                          src->k, src->flags, src->status, src->step, src->id, src->ens};
+                          src->k, src->flags, src->status, src->step, src->id, src->ens, src->birth};
     for (const void *p : ptrs)
         if (!p) return fail(ctx, GC_EINVAL, "every member of the state view must be set");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -812,7 +839,7 @@ struct Snapshot {
 
 gc_status take_snapshot(gc_ctx *ctx, Snapshot &sn) {
     sn.n = ctx->n;
-    const size_t bytes = (size_t)sn.n * (kNumDoubleArrays * 8 + 6 * 4) + 64;
+    const size_t bytes = (size_t)sn.n * (kNumDoubleArrays * 8 + 7 * 4) + 64;
     if (hipMalloc(&sn.mem, bytes) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate tuning snapshot");
     double *d = static_cast<double *>(sn.mem);
     double **dp[kNumDoubleArrays] = {&sn.v.r, &sn.v.th, &sn.v.ph, &sn.v.u, &sn.v.mu, &sn.v.fr, &sn.v.fth, &sn.v.fph,
@@ -820,8 +847,8 @@ gc_status take_snapshot(gc_ctx *ctx, Snapshot &sn) {
                                      &sn.v.cu, &sn.v.ct};
     for (int i = 0; i < kNumDoubleArrays; ++i) *dp[i] = d + (size_t)i * sn.n;
     uint32_t *u = reinterpret_cast<uint32_t *>(d + (size_t)kNumDoubleArrays * sn.n);
-    uint32_t **up[6] = {&sn.v.k, &sn.v.flags, &sn.v.status, &sn.v.step, &sn.v.id, &sn.v.ens};
-    for (int i = 0; i < 6; ++i) *up[i] = u + (size_t)i * sn.n;
+    uint32_t **up[7] = {&sn.v.k, &sn.v.flags, &sn.v.status, &sn.v.step, &sn.v.id, &sn.v.ens, &sn.v.birth};
+    for (int i = 0; i < 7; ++i) *up[i] = u + (size_t)i * sn.n;
     return gc_get_state(ctx, &sn.v);
 }
 

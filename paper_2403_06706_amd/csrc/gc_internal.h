@@ -9,6 +9,7 @@ namespace gc {
 
 constexpr int kMaxEnsembles = 4096;
 constexpr int kMaxMoments = 8192;
+constexpr int64_t kMaxRebirthSteps = 1 << 24;   // generations fit the 24 flag bits above GC_FLAG_GEN_SHIFT
 constexpr int kNumComp = 12;
 
 // Per-ensemble parameters, indexed by the particle's ensemble field.
@@ -24,6 +25,9 @@ struct EnsDev {
     int32_t drift_free;
     int32_t scatter_law;
     int32_t pad;
+    // injection site and spreads (Sect. 3), read again when a particle is reborn
+    double ekin, r0, lat0, lon0, dlon, dr0, dlat, mu_lo, mu_hi;
+    int64_t rebirth_steps;  // an exit at a step count below this is followed by a rebirth
 };
 
 // Packed field on the device: [nr][nth][nph+1][12], the extra phi node repeats
@@ -43,14 +47,15 @@ struct SoA {
     double *fr, *fth, *fph, *fu;
     double *dtp, *s, *ell, *t;
     double *cr, *cth, *cph, *cu, *ct;
-    uint32_t *k, *flags, *status, *step, *id, *ens, *gid;
+    uint32_t *k, *flags, *status, *step, *id, *ens, *gid, *birth;
 };
 constexpr int kNumDoubleArrays = 18;
-constexpr int kNumU32Arrays = 7;
+constexpr int kNumU32Arrays = 8;
 
 struct PushArgs {
     SoA st;
     FieldDev f;
+    const FieldDev *fdev;          // device copy of f (for the out-of-line rebirth)
     const EnsDev *ens;
     const uint32_t *n_active;      // device count of slots to visit
     uint32_t n_slots;              // grid coverage
@@ -61,6 +66,7 @@ struct PushArgs {
     int32_t log_depth;
     int32_t tile;                  // persistent mode: particles per work item
     uint32_t *queue;               // persistent mode: next tile counter
+    int32_t rebirth;               // some ensemble has rebirth_steps > 0
 };
 
 }  // namespace gc

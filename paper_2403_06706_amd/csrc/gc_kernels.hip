@@ -5,6 +5,7 @@
 
 #include "gc_device.h"
 #include "gc_launch.h"
+#include "gc_step.h"
 
 namespace gc {
 
@@ -38,46 +39,27 @@ hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int 
 // Injection (Sect. 3): one particle per lane, FP64.
 // ---------------------------------------------------------------------------
 template <int FDT>
-__global__ void k_inject(SoA st, FieldDev f, EnsDev e, InjectParams ip, uint32_t n0, uint32_t n,
-                         uint32_t first_id, uint32_t eidx) {
+__global__ void k_inject(SoA st, FieldDev f, EnsDev e, uint32_t n0, uint32_t n, uint32_t first_id, uint32_t eidx) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t slot = n0 + i, pid = first_id + i;
-    const U64x4 a = philox4x64_10(pid, 0, kPurposeInject, 0, e.seed, e.ensemble);
-    const double ph = ip.lon0 + ip.dlon * (2.0 * u01(a.v[0]) - 1.0);
-    const double mup = ip.mu_lo + (ip.mu_hi - ip.mu_lo) * u01(a.v[1]);
-    const double r = ip.r0 + ip.dr0 * (2.0 * u01(a.v[2]) - 1.0);
-    const double lat = ip.lat0 + ip.dlat * (2.0 * u01(a.v[3]) - 1.0);
-    const double th = 0.5 * kPi - lat;
-    const double gamma = 1.0 + ip.ekin / (e.m * kC * kC);
-    const double pm = kC * sqrt(gamma * gamma - 1.0);        // |p| / m
-    const U64x4 b = philox4x64_10(pid, 0, kPurposePath, 0, e.seed, e.ensemble);
-    const double ell = e.lambda > 0.0 ? -e.lambda * log(1.0 - u01(b.v[0])) : __builtin_inf();
-    uint32_t status = GC_ACTIVE;
-    double mu = 0.0;
-    if (r < e.r_in || r > e.r_out || th < f.th_lo || th > f.th_hi) {
-        status = GC_EXITED;
-    } else {
-        double g[12];
-        if (!gather<FDT, double>(f, r, th, ph, g)) status = GC_NONFINITE;
-        else mu = pm * pm * (1.0 - mup * mup) / (2.0 * sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]));
-    }
-    st.r[slot] = r; st.th[slot] = th; st.ph[slot] = ph; st.u[slot] = pm * mup; st.mu[slot] = mu;
+    const BirthState b = birth_state<FDT>(f, e, pid, 0);
+    st.r[slot] = b.r; st.th[slot] = b.th; st.ph[slot] = b.ph; st.u[slot] = b.u; st.mu[slot] = b.mu;
     st.fr[slot] = 0.0; st.fth[slot] = 0.0; st.fph[slot] = 0.0; st.fu[slot] = 0.0;
-    st.dtp[slot] = 0.0; st.s[slot] = 0.0; st.ell[slot] = ell; st.t[slot] = 0.0;
+    st.dtp[slot] = 0.0; st.s[slot] = 0.0; st.ell[slot] = b.ell; st.t[slot] = 0.0;
     st.cr[slot] = 0.0; st.cth[slot] = 0.0; st.cph[slot] = 0.0; st.cu[slot] = 0.0; st.ct[slot] = 0.0;
-    st.k[slot] = 0; st.flags[slot] = GC_FLAG_BOOTSTRAP; st.status[slot] = status; st.step[slot] = 0;
-    st.id[slot] = pid; st.ens[slot] = eidx; st.gid[slot] = slot;
+    st.k[slot] = 0; st.flags[slot] = GC_FLAG_BOOTSTRAP; st.status[slot] = b.status; st.step[slot] = 0;
+    st.id[slot] = pid; st.ens[slot] = eidx; st.gid[slot] = slot; st.birth[slot] = 0;
 }
 
-hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, const InjectParams &ip,
-                         uint32_t n0, uint32_t n, uint32_t first_id, uint32_t eidx, hipStream_t s) {
+hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, uint32_t n0, uint32_t n,
+                         uint32_t first_id, uint32_t eidx, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const dim3 grid((n + 255) / 256), block(256);
     switch (f.dtype) {
-        case GC_F64: hipLaunchKernelGGL(k_inject<GC_F64>, grid, block, 0, s, st, f, e, ip, n0, n, first_id, eidx); break;
-        case GC_F32: hipLaunchKernelGGL(k_inject<GC_F32>, grid, block, 0, s, st, f, e, ip, n0, n, first_id, eidx); break;
-        default:     hipLaunchKernelGGL(k_inject<GC_F16>, grid, block, 0, s, st, f, e, ip, n0, n, first_id, eidx); break;
+        case GC_F64: hipLaunchKernelGGL(k_inject<GC_F64>, grid, block, 0, s, st, f, e, n0, n, first_id, eidx); break;
+        case GC_F32: hipLaunchKernelGGL(k_inject<GC_F32>, grid, block, 0, s, st, f, e, n0, n, first_id, eidx); break;
+        default:     hipLaunchKernelGGL(k_inject<GC_F16>, grid, block, 0, s, st, f, e, n0, n, first_id, eidx); break;
     }
     return hipGetLastError();
 }
@@ -115,6 +97,7 @@ __global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, Mom
         const uint32_t k = st.k[i];
         acc[6] += fixp(r / m.len_unit, 4294967296.0);
         if (k >= 1) acc[7] += 1;
+        if (st.birth[i] < m.min_birth) continue;
         double g[12];
         if (!gather<FDT, double>(f, r, th, ph, g)) continue;
         const double B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
@@ -183,7 +166,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s) {
 
 hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
                           unsigned long long *out, hipStream_t s) {
-    hipError_t e = launch_fill_u64(out, 0ull, (size_t)m.total, s);
+    hipError_t e = m.accumulate ? hipSuccess : launch_fill_u64(out, 0ull, (size_t)m.total, s);
     if (e != hipSuccess || n == 0) return e;
     const dim3 grid(grid_for(n, 256) > 1024 ? 1024 : grid_for(n, 256)), block(256);
     const size_t lds = (size_t)m.total * sizeof(unsigned long long);
@@ -200,7 +183,7 @@ hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, u
 // ---------------------------------------------------------------------------
 #define GC_FOR_DOUBLES(X) X(r) X(th) X(ph) X(u) X(mu) X(fr) X(fth) X(fph) X(fu) X(dtp) X(s) X(ell) X(t) \
                           X(cr) X(cth) X(cph) X(cu) X(ct)
-#define GC_FOR_U32(X) X(k) X(flags) X(status) X(step) X(id) X(ens)
+#define GC_FOR_U32(X) X(k) X(flags) X(status) X(step) X(id) X(ens) X(birth)
 
 __global__ void k_state_out(SoA st, gc_state_view dst, uint32_t n) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;

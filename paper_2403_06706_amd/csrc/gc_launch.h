@@ -6,12 +6,10 @@
 
 namespace gc {
 
-struct InjectParams {
-    double ekin, r0, lat0, lon0, dlon, dr0, dlat, mu_lo, mu_hi;
-};
-
 struct MomDev {
     int32_t n_rbins, n_mubins, n_agebins, n_ebins, min_collisions, total;
+    uint32_t min_birth;
+    int32_t accumulate;
     double r_lo, r_hi, sel_r_lo, sel_r_hi, age_lo, age_hi, age_max, e_lo, e_hi, e_unit, len_unit;
 };
 
@@ -24,8 +22,8 @@ hipError_t launch_push(const PushArgs &a, int precision, int block, bool persist
 hipError_t launch_gather_probe(const PushArgs &a, double *sink, hipStream_t s);
 
 // injection, moments, state copies, fills (gc_kernels.hip)
-hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, const InjectParams &ip,
-                         uint32_t n0, uint32_t n, uint32_t first_id, uint32_t eidx, hipStream_t s);
+hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, uint32_t n0, uint32_t n,
+                         uint32_t first_id, uint32_t eidx, hipStream_t s);
 hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
                           unsigned long long *out, hipStream_t s);
 hipError_t launch_state_out(const SoA &st, const gc_state_view &dst, uint32_t n, hipStream_t s);

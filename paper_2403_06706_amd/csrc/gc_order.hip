@@ -262,7 +262,7 @@ __global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, const uint32_t
     const uint32_t j = perm[i];
 #define P_(name) dst.name[i] = src.name[j];
     P_(r) P_(th) P_(ph) P_(u) P_(mu) P_(fr) P_(fth) P_(fph) P_(fu) P_(dtp) P_(s) P_(ell) P_(t)
-    P_(k) P_(flags) P_(status) P_(step) P_(id) P_(ens) P_(gid)
+    P_(k) P_(flags) P_(status) P_(step) P_(id) P_(ens) P_(gid) P_(birth)
     if (kWithComp) { P_(cr) P_(cth) P_(cph) P_(cu) P_(ct) }
 #undef P_
 }
@@ -285,7 +285,7 @@ __global__ void k_copy_range(SoA src, SoA dst, const uint32_t *lo, const uint32_
     if (i >= *hi) return;
 #define T_(name) dst.name[i] = src.name[i];
     T_(r) T_(th) T_(ph) T_(u) T_(mu) T_(fr) T_(fth) T_(fph) T_(fu) T_(dtp) T_(s) T_(ell) T_(t)
-    T_(k) T_(flags) T_(status) T_(step) T_(id) T_(ens) T_(gid)
+    T_(k) T_(flags) T_(status) T_(step) T_(id) T_(ens) T_(gid) T_(birth)
     if (with_comp) { T_(cr) T_(cth) T_(cph) T_(cu) T_(ct) }
 #undef T_
 }

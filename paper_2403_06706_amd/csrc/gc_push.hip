@@ -21,7 +21,9 @@ namespace gc {
 //                    lane gl = 0 writes.
 enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 
-template <int PREC, int FDT, int FORM = kFormThroughput>
+// RB: some ensemble asks for rebirth.  A separate instantiation, because the
+// out-of-line rebirth raises the register count of the FP32 forms.
+template <int PREC, int FDT, bool RB, int FORM = kFormThroughput>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
@@ -31,7 +33,10 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     if (status != GC_ACTIVE) return 0;
     uint32_t flags = st.flags[slot], k = st.k[slot], step = st.step[slot];
     const uint32_t step0 = step;
-    const EnsDev e = a.ens[min(st.ens[slot], (uint32_t)(kMaxEnsembles - 1))];
+    const uint32_t eidx = min(st.ens[slot], (uint32_t)(kMaxEnsembles - 1));
+    const EnsDev e = a.ens[eidx];
+    uint32_t birth = 0;
+    bool reborn = false;
     const uint32_t pid = st.id[slot];
     A X0 = (A)st.r[slot], X1 = (A)st.th[slot], X2 = (A)st.ph[slot], X3 = (A)st.u[slot];
     A T = (A)st.t[slot];
@@ -58,7 +63,8 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         // gather at X^n gives |B| there.
         R mun = 0, ell_new = 0;
         if (flags & GC_FLAG_PENDING) {
-            const CollisionDraw d = draw_collision(pid, k + 1, e.seed, e.ensemble, e.scatter_law, e.lambda);
+            const CollisionDraw d = draw_collision(pid, k + 1, flags >> GC_FLAG_GEN_SHIFT, e.seed, e.ensemble,
+                                                   e.scatter_law, e.lambda);
             mun = (R)d.mun;
             ell_new = (R)d.ell;
         }
@@ -149,7 +155,26 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         step += 1;
         if (!(isfinite(n0) && isfinite(n1) && isfinite(n2) && isfinite(n3))) { status = GC_NONFINITE; break; }
         const double r = (double)X0, th = (double)X1;
-        if (r < r_in || r > r_out || th < th_lo || th > th_hi) { status = GC_EXITED; break; }
+        if (r < r_in || r > r_out || th < th_lo || th > th_hi) {
+            if (!RB || (int64_t)step >= e.rebirth_steps) { status = GC_EXITED; break; }
+            // rebirth (continuous injection, Sect. 3): the next generation starts
+            // from the injection state with its own generator stream
+            const uint32_t gen = (flags >> GC_FLAG_GEN_SHIFT) + 1;
+            const BirthState b = rebirth_state<FDT>(a.fdev, a.ens + eidx, pid, gen);
+            X0 = (A)b.r; X1 = (A)b.th; X2 = (A)b.ph; X3 = (A)b.u;
+            c0 = 0; c1 = 0; c2 = 0; c3 = 0; cT = 0; T = 0;
+            fp0 = 0; fp1 = 0; fp2 = 0; fp3 = 0;
+            mu = (R)b.mu; dtp = 0; s = 0; ell = (R)b.ell;
+            k = 0;
+            flags = GC_FLAG_BOOTSTRAP | (gen << GC_FLAG_GEN_SHIFT);
+            birth = step;
+            reborn = true;
+            if (a.log_depth > 0 && gl == 0) {
+                uint32_t *row = a.log + (size_t)st.gid[slot] * a.log_depth;
+                for (int j = 0; j < a.log_depth; ++j) row[j] = 0xFFFFFFFFu;
+            }
+            if (b.status != GC_ACTIVE) { status = b.status; break; }
+        }
         if (e.max_steps > 0 && (int64_t)step >= e.max_steps) { status = GC_FINISHED; break; }
     }
     if (gl != 0) return 0;
@@ -162,6 +187,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     st.fr[slot] = (double)fp0; st.fth[slot] = (double)fp1; st.fph[slot] = (double)fp2; st.fu[slot] = (double)fp3;
     st.mu[slot] = (double)mu; st.dtp[slot] = (double)dtp; st.s[slot] = (double)s; st.ell[slot] = (double)ell;
     st.k[slot] = k; st.flags[slot] = flags; st.status[slot] = status; st.step[slot] = step;
+    if (reborn) st.birth[slot] = birth;
     return step - step0;
 }
 
@@ -171,7 +197,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
 // gives each XCD a contiguous range of that prefix, so that (with cell-sorted
 // slots) its L2 holds the field cells of its own particles, and every XCD gets
 // an equal share however small the active prefix is.
-template <int PREC, int FDT, int FORM>
+template <int PREC, int FDT, bool RB, int FORM>
 __device__ __forceinline__ void push_grid(const PushArgs &a) {
     constexpr uint32_t G = FORM == kFormQuad ? 4 : 1;          // lanes per particle
     const uint32_t n = *a.n_active;
@@ -182,14 +208,14 @@ __device__ __forceinline__ void push_grid(const PushArgs &a) {
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
     const uint32_t slot = lb * per_block + threadIdx.x / G;
     uint32_t taken = 0;
-    if (slot < n) taken = advance_slot<PREC, FDT, FORM>(a, slot, threadIdx.x % G);
+    if (slot < n) taken = advance_slot<PREC, FDT, RB, FORM>(a, slot, threadIdx.x % G);
     count_steps(a, taken);
 }
 
 // Throughput form: at most 256 registers per lane (two wavefronts per SIMD).
-template <int PREC, int FDT>
+template <int PREC, int FDT, bool RB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
-    push_grid<PREC, FDT, kFormThroughput>(a);
+    push_grid<PREC, FDT, RB, kFormThroughput>(a);
 }
 
 // Latency forms, for fewer active particles than fill the machine: a
@@ -197,19 +223,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // and by how many distinct cache lines its load instructions touch.  The
 // all-pairs form has each gather in one round trip; the quad form also spreads
 // the particles over four times as many wavefronts (and compute units).
-template <int PREC, int FDT>
+template <int PREC, int FDT, bool RB>
 __global__ __launch_bounds__(256) void k_push_allpairs(PushArgs a) {
-    push_grid<PREC, FDT, kFormAllPairs>(a);
+    push_grid<PREC, FDT, RB, kFormAllPairs>(a);
 }
 
-template <int PREC, int FDT>
+template <int PREC, int FDT, bool RB>
 __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
-    push_grid<PREC, FDT, kFormQuad>(a);
+    push_grid<PREC, FDT, RB, kFormQuad>(a);
 }
 
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
 // atomic counter until the tiles run out (every workgroup reaches the exit).
-template <int PREC, int FDT>
+template <int PREC, int FDT, bool RB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
@@ -224,27 +250,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (t >= ntiles) break;
         const uint32_t end = min(n, (t + 1) * tile);
         for (uint32_t slot = t * tile + threadIdx.x; slot < end; slot += blockDim.x)
-            taken += advance_slot<PREC, FDT>(a, slot);
+            taken += advance_slot<PREC, FDT, RB>(a, slot);
     }
     count_steps(a, taken);
 }
 
 
-template <int PREC, int FDT>
-static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
+template <int PREC, int FDT, bool RB>
+static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
     if (persistent) {
-        hipLaunchKernelGGL((k_push_persistent<PREC, FDT>), dim3(grid_blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_push_persistent<PREC, FDT, RB>), dim3(grid_blocks), dim3(block), 0, s, a);
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;
         if (form == kFormQuad)
-            hipLaunchKernelGGL((k_push_quad<PREC, FDT>), dim3(4 * nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push_quad<PREC, FDT, RB>), dim3(4 * nb), dim3(block), 0, s, a);
         else if (form == kFormAllPairs)
-            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, RB>), dim3(nb), dim3(block), 0, s, a);
         else
-            hipLaunchKernelGGL((k_push<PREC, FDT>), dim3(nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push<PREC, FDT, RB>), dim3(nb), dim3(block), 0, s, a);
     }
     return hipGetLastError();
+}
+
+template <int PREC, int FDT>
+static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
+    return a.rebirth ? launch_r<PREC, FDT, true>(a, block, persistent, form, grid_blocks, s)
+                     : launch_r<PREC, FDT, false>(a, block, persistent, form, grid_blocks, s);
 }
 
 template <int PREC>

@@ -66,7 +66,8 @@ void k_push_mlp(PushArgs a, MlpArgs m) {
     R Fn[4] = {0, 0, 0, 0}, vpn = 0, tau = 1;
     R mun = 0, ell_new = 0;
     if (active && (flags & GC_FLAG_PENDING)) {
-        const CollisionDraw d = draw_collision(pid, k + 1, e.seed, e.ensemble, e.scatter_law, e.lambda);
+        const CollisionDraw d = draw_collision(pid, k + 1, flags >> GC_FLAG_GEN_SHIFT, e.seed, e.ensemble,
+                                               e.scatter_law, e.lambda);
         mun = (R)d.mun;
         ell_new = (R)d.ell;
     }
@@ -126,7 +127,8 @@ void k_push_mlp(PushArgs a, MlpArgs m) {
             mun = 0;
             ell_new = 0;
             if (flags & GC_FLAG_PENDING) {
-                const CollisionDraw d = draw_collision(pid, k + 1, e.seed, e.ensemble, e.scatter_law, e.lambda);
+                const CollisionDraw d = draw_collision(pid, k + 1, flags >> GC_FLAG_GEN_SHIFT, e.seed, e.ensemble,
+                                               e.scatter_law, e.lambda);
                 mun = (R)d.mun;
                 ell_new = (R)d.ell;
             }

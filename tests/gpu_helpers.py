@@ -63,7 +63,7 @@ def run_oracle(wl, field, n_steps=None, dt=None, ensembles=None, ids=None, log_d
     parts = []
     for i, e in enumerate(ens):
         sel = np.arange(e.n, dtype=np.uint32) if ids is None else np.asarray(ids[i], dtype=np.uint32)
-        parts.append(O.inject(of, tab, i, e, sel))
+        parts.append(O.inject(of, tab, i, sel))
     p = np.concatenate(parts) if parts else np.zeros(0, dtype=O.PARTICLE_DTYPE)
     n = wl.n_steps if n_steps is None else n_steps
     logs = O.advance(of, tab, p, wl.dt if dt is None else dt, n, threads, log_depth=log_depth)
@@ -109,8 +109,41 @@ def oracle_to_state(p, m):
     for k in ("cr", "cth", "cph", "cu", "ct"):
         d[k] = np.zeros(len(p))
     out = {k: torch.tensor(np.ascontiguousarray(v, dtype=np.float64)) for k, v in d.items()}
-    for k in ("k", "flags", "status", "step", "id", "ens"):
-        out[k] = torch.tensor(np.ascontiguousarray(p[k]).view(np.int32))
+    u32 = {k: p[k] for k in ("k", "status", "step", "id", "ens", "birth")}
+    u32["flags"] = p["flags"] | (p["gen"] << np.uint32(GEN_SHIFT))
+    for k, v in u32.items():
+        out[k] = torch.tensor(np.ascontiguousarray(v, dtype=np.uint32).view(np.int32))
+    return out
+
+
+GEN_SHIFT = 8     # device flags: generation in the bits from here up
+
+
+def generation(st):
+    return st["flags"].astype(np.uint32) >> np.uint32(GEN_SHIFT)
+
+
+def device_bmag(wl, field, store_dtype, r, th, ph):
+    """|B| at points by the device's own trilinear sampling of the loaded grid
+    (derived quantities of device results come from the device side)."""
+    import torch
+    import paper_2403_06706_amd as gcp
+    if len(r) == 0:
+        return np.zeros(0)
+    ctx = gcp.Context(device=0)
+    ctx.load_field(wl.grid, field, store_dtype)
+    pts = torch.tensor(np.stack([r, th, ph]), dtype=torch.float64, device="cuda:0").contiguous()
+    g = ctx.field_sample(pts).cpu().numpy()
+    ctx.close()
+    return np.linalg.norm(g[:, 0:3], axis=1)
+
+
+def oracle_bmag(of, r, th, ph):
+    out = np.full(len(r), np.nan)
+    for i in range(len(r)):
+        g, ok = O.field_eval(of, r[i], th[i], ph[i])
+        if ok:
+            out[i] = np.linalg.norm(g[0:3])
     return out
 
 

@@ -1,48 +1,24 @@
 """Moments kernel against the oracle's moments of the same particle state.
-Counts and histograms must match exactly; each fixed-point sum may differ by
-at most one unit per particle (floor of a product computed in a different
-rounding order)."""
+The state is made by the oracle (injection and 3600 steps) and loaded into the
+device with gc_set_state.  Counts and histograms must match exactly; each
+fixed-point sum may differ by at most one unit per particle (floor of a product
+computed in a different rounding order)."""
 import numpy as np
 import pytest
 
 import oracle as O
 import paper_2403_06706_amd as gcp
-from gpu_helpers import field_of, small, say
+from gpu_helpers import field_of, oracle_to_state, run_oracle, small, say, stored
 from synthetic import AU, E_CHARGE
 
 pytestmark = pytest.mark.gpu
 
-
-def _to_oracle(st, ens_m):
-    p = np.zeros(len(st["r"]), dtype=O.PARTICLE_DTYPE)
-    for k in ("r", "th", "ph", "u", "dtp", "s", "ell", "t"):
-        p[k] = st[k]
-    p["mu_B"] = st["mu"] * ens_m
-    p["fp"] = np.stack([st["fr"], st["fth"], st["fph"], st["fu"]], axis=1)
-    for k in ("k", "flags", "status", "step", "id", "ens"):
-        p[k] = st[k]
-    return p
+SPEC = dict(n_rbins=38, r_lo=0.1 * AU, r_hi=2.0 * AU, n_mubins=20, sel_r_lo=0.9 * AU, sel_r_hi=1.1 * AU,
+            age_lo=0.0, age_hi=1e9, min_collisions=1, n_agebins=6, age_max=3600.0, n_ebins=40, e_lo=79e3,
+            e_hi=83e3, e_unit=E_CHARGE, len_unit=AU)
 
 
-@pytest.mark.parametrize("store", ["f64", "f32"])
-def test_moments_match_oracle(store):
-    wl = small(n=5000, hours=1.0)
-    f = field_of(wl)
-    if store == "f32":
-        f = f.astype(np.float32).astype(np.float64)
-    ctx = gcp.Context(device=0)
-    ctx.load_field(wl.grid, f, store)
-    ctx.inject(wl.ensembles[0])
-    ctx.advance(1.0, 3600)
-    spec = O.MomentSpec(n_rbins=38, r_lo=0.1 * AU, r_hi=2.0 * AU, n_mubins=20, sel_r_lo=0.9 * AU,
-                        sel_r_hi=1.1 * AU, age_lo=0.0, age_hi=1e9, min_collisions=1, n_agebins=6, age_max=3600.0,
-                        n_ebins=40, e_lo=79e3, e_hi=83e3, e_unit=E_CHARGE, len_unit=AU)
-    got = ctx.moments(spec).cpu().numpy()
-    st = gcp.state_to_numpy(ctx.get_state())
-    ctx.close()
-    p = _to_oracle(st, wl.ensembles[0].m)
-    want = O.moments(O.Field(wl.grid, f), O.make_ens_table(wl.ensembles), p, spec)
-    say(f"  moments counts {want[:8]}")
+def _check(got, want, spec):
     assert got.shape == want.shape
     nr = spec.n_rbins
     fixed = np.zeros(len(want), dtype=bool)
@@ -52,4 +28,21 @@ def test_moments_match_oracle(store):
     assert np.array_equal(got[~fixed], want[~fixed])
     active = int(want[0])
     assert np.all(np.abs(got[fixed] - want[fixed]) <= active)
-    assert want[8 + 3 * nr:].sum() > 100          # the histograms are populated
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_moments_match_oracle(store):
+    wl = small(n=5000, hours=1.0)
+    f = stored(field_of(wl), store)
+    p, _, of, tab = run_oracle(wl, f, n_steps=3600, dt=1.0)
+    spec = O.MomentSpec(**SPEC)
+    want = O.moments(of, tab, p, spec)
+    ctx = gcp.Context(device=0)
+    ctx.load_field(wl.grid, f, store)
+    ctx.inject(wl.ensembles[0])             # registers the ensemble parameters
+    ctx.set_state(oracle_to_state(p, wl.ensembles[0].m))
+    got = ctx.moments(spec).cpu().numpy()
+    ctx.close()
+    say(f"  moments counts {want[:8]}")
+    _check(got, want, spec)
+    assert want[8 + 3 * spec.n_rbins:].sum() > 100          # the histograms are populated
