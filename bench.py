@@ -159,6 +159,110 @@ def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False,
     return elapsed, c, final, m, ceiling
 
 
+def steady_spec(min_birth: int):
+    from synthetic import AU, E_CHARGE
+
+    class Spec:   # Sect. 3 steady-state statistics near 1 AU, electrons born after the steady state
+        n_rbins, r_lo, r_hi = 38, 0.1 * AU, 2.0 * AU
+        n_mubins, sel_r_lo, sel_r_hi = 36, 0.9 * AU, 1.1 * AU
+        age_lo, age_hi, min_collisions = 0.0, 1e12, 0
+        n_agebins, age_max = 60, 30 * 3600.0
+        n_ebins, e_lo, e_hi = 64, 70e3, 82e3
+        e_unit, len_unit = E_CHARGE, AU
+    Spec.min_birth = min_birth
+    return Spec
+
+
+def run_steady(args, n=None, hours=None, field=None, with_cpu=True):
+    """The steady-state run of Sect. 3 as one job: 10^3 electrons reborn at
+    once whenever they leave the shell, 150 h of 0.54 s steps, <r>(t) after
+    every 100 steps, and from 8.3 h on snapshots every 100 steps accumulated
+    on the device, the binned sections keeping electrons born after 8.3 h."""
+    import numpy as np
+    import torch
+    import paper_2403_06706_amd as gcp
+    from synthetic import workloads, AU
+    wl = workloads.config_steady(seed=args.seed, n=n or args.steady_particles,
+                                 hours=hours or args.steady_hours, store_dtype=args.store)
+    if field is None:
+        field = np.ascontiguousarray(wl.build_field(wl.grid, device="cuda"))
+    every = wl.bin_interval
+    n_snap = wl.n_steps // every
+    t_steady = 8.3 * 3600.0
+    first = int(np.ceil(t_steady / wl.dt / every))          # first accumulated snapshot
+    min_birth = int(np.ceil(t_steady / wl.dt))
+    spec = steady_spec(min_birth)
+
+    class Mean:   # <r> only: the eight scalar sums
+        n_rbins = n_mubins = n_agebins = n_ebins = min_collisions = 0
+        r_lo, r_hi, sel_r_lo, sel_r_hi, age_lo, age_hi, age_max = 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 1.0
+        e_lo, e_hi, e_unit, len_unit = 0.0, 1.0, 1.0, AU
+    ctx = gcp.Context(device=0, precision=args.precision, order="bin", chunk_steps=every, timing=True)
+    ctx.load_field(wl.grid, field, args.store)
+    ctx.inject(wl.ensembles[0])
+    acc = torch.zeros(ctx.moments_size(spec), dtype=torch.int64, device="cuda")
+    series = torch.zeros((n_snap, 8), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(n_snap):
+        ctx.advance(wl.dt, every)
+        ctx.moments(Mean, out=series[j])
+        if j + 1 >= first:
+            ctx.moments(spec, out=acc, accumulate=True)
+        if (j + 1) % 2000 == 0:
+            log(f"[bench] steady: snapshot {j + 1}/{n_snap}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c = ctx.counters()
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    ser = series.cpu().numpy()
+    a = acc.cpu().numpy()
+    r_mean = ser[:, 6] / 2.0 ** 32 / np.maximum(ser[:, 0], 1)          # AU
+    t_h = (np.arange(n_snap) + 1) * every * wl.dt / 3600.0
+    late = r_mean[len(r_mean) // 2:].mean()
+    win = max(1, int(round(3600.0 / (every * wl.dt))))                   # one hour of snapshots
+    smooth = np.convolve(r_mean, np.ones(win) / win, mode="valid")
+    near = np.nonzero(np.abs(smooth - late) <= 0.02 * late)[0]
+    nb = spec.n_rbins
+    n_part = wl.ensembles[0].n
+    gen = st["flags"].astype(np.uint32) >> np.uint32(8)
+    out = {"workload": wl.name, "particles": n_part, "steps": wl.n_steps, "dt_s": wl.dt,
+           "simulated_hours": wl.n_steps * wl.dt / 3600.0, "wall_s": round(elapsed, 3),
+           "value": c["particle_steps"] / elapsed, "unit": "particle-steps/s",
+           "snapshots_accumulated": int(n_snap - first + 1), "samples_accumulated": int(a[0]),
+           "samples_per_electron_snapshot": a[0] / (n_part * (n_snap - first + 1)),
+           "selected_binned_samples": int(a[8:8 + 3 * nb:3].sum()),
+           "rebirths": int(gen.sum()), "rebirths_per_electron": float(gen.mean()),
+           "r_mean_AU": {f"{h:g}h": round(float(r_mean[min(n_snap - 1, int(round(h * 3600 / wl.dt / every)) - 1)]), 4)
+                         for h in (1, 2, 4, 8.3, 20, 50, 100, 150) if h * 3600 / wl.dt / every <= n_snap},
+           "steady_after_h": round(float(t_h[near[0]]), 2) if len(near) else None,
+           "forms": {"launches": c["form_launches"], "ms": [round(x, 1) for x in c["form_ms"]],
+                     "particle_steps": c["form_steps"]}}
+    log(f"[bench] steady: {out['value']:.3e} particle-steps/s, {elapsed:.1f} s for {out['simulated_hours']:.0f} h; "
+        f"{out['rebirths_per_electron']:.1f} rebirths per electron; steady after {out['steady_after_h']} h")
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline_steady(args, wl, field)
+    return out
+
+
+def cpu_baseline_steady(args, wl, field):
+    """The oracle on the same steady-state job, over a bounded share of its steps."""
+    import numpy as np
+    import oracle as O
+    of = O.Field(wl.grid, field.astype(np.float32).astype(np.float64) if args.store == "f32" else field)
+    tab = O.make_ens_table(wl.ensembles)
+    p = O.inject(of, tab, 0, np.arange(wl.ensembles[0].n, dtype=np.uint32))
+    steps = min(wl.n_steps, args.steady_cpu_steps)
+    t0 = time.perf_counter()
+    O.advance(of, tab, p, wl.dt, steps)
+    el = time.perf_counter() - t0
+    done = int(p["step"].astype(np.int64).sum())
+    return {"value": done / el, "unit": "particle-steps/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{wl.ensembles[0].n} electrons x first {steps} steps of the run",
+            "job_estimate_s": round(wl.n_steps / steps * el, 1)}
+
+
 def run_batched(args):
     """64 ensembles of uneven size (4M electrons), ragged stop times, advanced by
     the persistent push in hipGraph replays of 128 steps, launch parameters
@@ -399,7 +503,11 @@ def main():
     ap.add_argument("--cpu-particles", type=int, default=98304)
     ap.add_argument("--cpu-steps", type=int, default=14400)
     ap.add_argument("--probe-copy", action="store_true", help="run a 256 MiB copy kernel first (counter calibration)")
-    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "mlp"])
+    ap.add_argument("--workload", default="paper", choices=["paper", "batched", "mlp", "steady"])
+    ap.add_argument("--steady-particles", type=int, default=1000)
+    ap.add_argument("--steady-hours", type=float, default=150.0)
+    ap.add_argument("--steady-cpu-steps", type=int, default=20000)
+    ap.add_argument("--no-steady", action="store_true", help="skip the steady-state summary of the default run")
     ap.add_argument("--mlp-particles", type=int, default=10 << 20)
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (batched workload)")
     args = ap.parse_args()
@@ -416,6 +524,9 @@ def main():
         return
     if args.workload == "mlp":
         print(json.dumps(run_mlp(args)), flush=True)
+        return
+    if args.workload == "steady":
+        print(json.dumps(run_steady(args)), flush=True)
         return
     if args.steps is None:
         args.steps = 1350
@@ -494,6 +605,11 @@ def main():
                                "field_error_vs_grid_rms": nf["config"]["field_error_vs_grid_rms"],
                                "trajectory_difference_vs_grid": nf["trajectory_difference_vs_grid"],
                                "note": "full measurement: bench.py --workload mlp"}
+
+    if not args.no_steady and not args.probe_copy:
+        log("[bench] steady-state summary ...")
+        out["steady_state"] = run_steady(args, field=field, with_cpu=False)
+        out["steady_state"]["note"] = "with the oracle beside it: bench.py --workload steady"
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")

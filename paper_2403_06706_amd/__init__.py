@@ -189,12 +189,18 @@ class Context:
                                    spec.n_ebins, spec.e_lo, spec.e_hi, spec.e_unit, spec.len_unit,
                                    int(getattr(spec, "min_birth", 0)), 1 if accumulate else 0)
 
-    def moments(self, spec, out=None):
-        """Snapshot statistics; with out (an int64 device tensor of the moments
-        size) they are added into out on the device instead (accumulation over
-        snapshots), and out is returned."""
+    def moments_size(self, spec) -> int:
+        return int(lib.gc_moments_size(C.byref(self._spec(spec))))
+
+    def moments(self, spec, out=None, accumulate: bool = False):
+        """Snapshot statistics into a new int64 device tensor, or into out (a
+        contiguous int64 device tensor of at least the moments size), replacing
+        its contents or, with accumulate, adding to them on the device (the sum
+        over snapshots).  Returns the moments view of the output."""
         torch = _torch()
-        s = self._spec(spec, accumulate=out is not None)
+        if accumulate and out is None:
+            raise ValueError("accumulate needs out")
+        s = self._spec(spec, accumulate=accumulate)
         m = int(lib.gc_moments_size(C.byref(s)))
         if out is None:
             out = torch.empty(max(m, 1), dtype=torch.int64, device=f"cuda:{self.device}")

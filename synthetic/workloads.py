@@ -99,6 +99,24 @@ def config_paper_scale(seed: int = 0, n: int = 1 << 20, hours: float = 24.0, fie
                     ens, 1.0, int(round(hours * HOUR)), store_dtype, 64)
 
 
+def config_steady(seed: int = 0, n: int = 1000, hours: float = 150.0, dt: float = 0.54, field_seed: int = 1,
+                  lambda_au: float = 0.5, store_dtype: str = "f32") -> Workload:
+    """Steady-state run of Sect. 3: 10^3 electrons of 81 keV released with pitch
+    angle 0 at 0.28 AU and 24 deg latitude, all on one field line, lambda = 0.5 AU,
+    dt = 0.54 s, reborn at once whenever they leave the shell, for 150 h.  The
+    field is the paper-scale one (Parker spiral plus 16 Fourier modes on
+    256x128x256 over [0.1, 2] AU); its radial extent puts the outer exit shell
+    just inside 2 AU, the paper's value for its lambda = 0.1 AU run."""
+    grid = SphericalGrid(256, 128, 256, 0.1 * AU, 2.0 * AU)
+    n_steps = int(round(hours * HOUR / dt))
+    ens = Ensemble(n=n, ensemble=0, seed=seed, r0=0.28 * AU, lat0=math.radians(24.0), lon0=0.0, dlon=0.0,
+                   mu_lo=1.0, mu_hi=1.0, lambda_par=lambda_au * AU, r_in=0.28 * AU, r_out=r_out_default(grid),
+                   rebirth_steps=n_steps)
+    return Workload(f"steady-{n}e-{hours:g}h", grid,
+                    lambda g, device=None: fields.perturbed_parker(g, field_seed, device=device),
+                    [ens], dt, n_steps, store_dtype, 100)
+
+
 def config_batched(seed: int = 0, n_ens: int = 64, total: int = 4 << 20, field_seed: int = 1,
                    dt: float = 1.0, store_dtype: str = "f32", grid: SphericalGrid = None,
                    hours_lo: float = 6.0, hours_hi: float = 48.0) -> Workload:

@@ -87,7 +87,7 @@ def test_accumulated_snapshots_match_oracle():
     acc = torch.zeros(O.moments_size(spec), dtype=torch.int64, device="cuda:0")
     for _ in range(S):
         ctx.advance(wl.dt, every)
-        ctx.moments(spec, out=acc)
+        ctx.moments(spec, out=acc, accumulate=True)
     got = acc.cpu().numpy()
     ctx.close()
     n = wl.ensembles[0].n
