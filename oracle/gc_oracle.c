@@ -9,7 +9,8 @@
  *   or_rhs               GC equations, Eqs. (1)-(3), with the definitions that follow them
  *   or_pc_predict/correct third-order predictor-corrector, Eqs. (5)-(6)
  *   bootstrap            backward Euler start at t = 0 and after a collision (Sect. 2.2)
- *   collisions           hard-sphere scattering, Eqs. (9)-(10) (and (12))
+ *   collisions           hard-sphere scattering, Eqs. (9)-(10) (and (12)), in the inertial
+ *                        frame (Sect. 3) or in the frame of the wind (Sect. 3.3)
  *   or_inject            injection of Sect. 3
  *   rebirth              continuous injection of Sect. 3: an electron that leaves the
  *                        shell starts again from its initial state
@@ -307,20 +308,64 @@ static void rebirth(const or_field *f, const or_ens *e, or_particle *p, const or
     }
 }
 
-/* hard-sphere collision number k (Eqs. 9-10): |p| kept (inertial frame, Sect. 3),
- * new pitch cosine, new free path; the position is unchanged. */
-static void collide(const or_ens *e, or_particle *p, double B, const or_log *log, int64_t pi)
+/* Component of the wind velocity along b.  READING (Sect. 3.3): the wind is
+ * radial with speed v_wind, as in the stand-in fields; its component across B
+ * is the E x B drift the guiding centre already moves with, so the frame of
+ * the scattering centres differs from the drift frame by V_par = v_wind b_r. */
+static double wind_par(const or_ens *e, const double fld[12])
 {
+    double B = sqrt(fld[0] * fld[0] + fld[1] * fld[1] + fld[2] * fld[2]);
+    return e->v_wind * fld[0] / B;
+}
+
+/* Path covered along b in one step, against the scattering centres (READING of
+ * Eq. 9: the trapezoid of the speed along b at X^n and X*).  Inertial frame:
+ * |v_par|.  Wind frame: the centres move with V_par along b, and a boost along
+ * b turns dx - V_par dt into Gamma (v_par - V_par) dt. */
+static double path_step(const or_ens *e, double vpn, const double gn[12], double vps, const double gs[12], double dt)
+{
+    if (e->v_wind > 0.0) {
+        double Vn = wind_par(e, gn), Vs = wind_par(e, gs);
+        double Gn = 1.0 / sqrt(1.0 - Vn * Vn / (OR_C * OR_C));
+        double Gs = 1.0 / sqrt(1.0 - Vs * Vs / (OR_C * OR_C));
+        return 0.5 * (Gn * fabs(vpn - Vn) + Gs * fabs(vps - Vs)) * dt;
+    }
+    return 0.5 * (fabs(vpn) + fabs(vps)) * dt;
+}
+
+/* hard-sphere collision number k (Eqs. 9-10): new pitch cosine drawn in the
+ * frame of the scattering centres, |p| kept there, new free path; the position
+ * is unchanged.  Inertial centres (Sect. 3): |p| kept.  Wind-frame centres
+ * (Sect. 3.3): the momentum (p_par, p_perp) and energy are boosted along b by
+ * V_par (a Lorentz boost: p_perp unchanged), the collision keeps |p~| and sets
+ * p~_par = mu' |p~|, and the boost back gives the new p_par and p_perp. */
+static void collide(const or_ens *e, or_particle *p, const double fld[12], const or_log *log, int64_t pi)
+{
+    double B = sqrt(fld[0] * fld[0] + fld[1] * fld[1] + fld[2] * fld[2]);
     p->k += 1;
     double a[4];
     draw(e, p->id, p->k, PURPOSE_PATH, p->gen, a);
     double m = e->m;
-    double p2 = (m * p->u) * (m * p->u) + 2.0 * m * p->mu_B * B;
     double mun;
     if (e->scatter_law == 1) mun = (a[2] < 0.5 ? -1.0 : 1.0) * sqrt(a[1]);   /* Eq. 12 */
     else mun = 1.0 - 2.0 * a[1];                                              /* Eq. 10 */
-    p->u = mun * sqrt(p2) / m;
-    p->mu_B = p2 * (1.0 - mun * mun) / (2.0 * m * B);
+    double ppar = m * p->u;
+    double pperp2 = 2.0 * m * p->mu_B * B;
+    if (e->v_wind > 0.0) {
+        double V = wind_par(e, fld);
+        double G = 1.0 / sqrt(1.0 - V * V / (OR_C * OR_C));
+        double En = sqrt(m * m * OR_C * OR_C * OR_C * OR_C + (ppar * ppar + pperp2) * OR_C * OR_C);
+        double pw = G * (ppar - V * En / (OR_C * OR_C));          /* p~_par */
+        double Ew = G * (En - V * ppar);                          /* E~ */
+        double P2 = pw * pw + pperp2;                             /* |p~|^2, kept */
+        double pw_new = mun * sqrt(P2);
+        p->u = G * (pw_new + V * Ew / (OR_C * OR_C)) / m;
+        p->mu_B = P2 * (1.0 - mun * mun) / (2.0 * m * B);
+    } else {
+        double p2 = ppar * ppar + pperp2;
+        p->u = mun * sqrt(p2) / m;
+        p->mu_B = p2 * (1.0 - mun * mun) / (2.0 * m * B);
+    }
     p->ell = free_path(e, a[0]);
     p->s = 0.0;
     p->flags = (p->flags | OR_BOOTSTRAP) & ~OR_PENDING;
@@ -346,8 +391,7 @@ static void advance_one(const or_field *f, const or_ens *e, or_particle *p, doub
         double g[12];
         if (!or_field_eval(f, X[0], X[1], X[2], g)) { p->status = OR_NONFINITE; return; }
         if (p->flags & OR_PENDING) {
-            double B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-            collide(e, p, B, log, pi);
+            collide(e, p, g, log, pi);
             X[3] = p->u;
         }
         double Fn[4], vpn, gam;
@@ -371,8 +415,7 @@ static void advance_one(const or_field *f, const or_ens *e, or_particle *p, doub
         or_rhs(Xs, p->mu_B, e->q, e->m, e->drift_free, gs, Fs, &vps, NULL);
         double Xn[4];
         or_pc_correct(X, Fn, Fs, Fp, dt, tau, Xn);
-        /* READING of Eq. 9: the path covered in the step is the trapezoid of |v_par| at X^n and X*. */
-        double ds = 0.5 * (fabs(vpn) + fabs(vps)) * dt;
+        double ds = path_step(e, vpn, g, vps, gs, dt);
         if (e->lambda > 0.0) {
             if (e->collision_mode == 1) {
                 double a[4];

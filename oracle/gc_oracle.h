@@ -57,6 +57,7 @@ typedef struct {
     int32_t collision_mode;/* 0: exponential free path per collision index; 1: per-step draw (Eq. 9 literally) */
     int64_t rebirth_steps; /* Sect. 3 continuous injection: an exit at a step count below this is a rebirth */
     or_inject_params inj;  /* the injection recipe a reborn particle starts from again */
+    double v_wind;         /* > 0: the scattering centres move with a radial wind of this speed (m/s), Sect. 3.3 */
 } or_ens;
 
 typedef struct {

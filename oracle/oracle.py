@@ -43,7 +43,7 @@ class _Ens(C.Structure):
                 ("r_in", C.c_double), ("r_out", C.c_double), ("seed", C.c_uint64),
                 ("ensemble", C.c_uint32), ("drift_free", C.c_int32), ("max_steps", C.c_int64),
                 ("scatter_law", C.c_int32), ("collision_mode", C.c_int32),
-                ("rebirth_steps", C.c_int64), ("inj", _Inject)]
+                ("rebirth_steps", C.c_int64), ("inj", _Inject), ("v_wind", C.c_double)]
 
 
 class _Log(C.Structure):
@@ -183,7 +183,7 @@ def make_ens_table(ensembles, collision_mode: int = 0):
         inj = _Inject(e.ekin, e.r0, e.lat0, e.lon0, e.dlon, e.dr0, e.dlat, e.mu_lo, e.mu_hi)
         arr[i] = _Ens(e.q, e.m, e.lambda_par, e.r_in, e.r_out, e.seed, e.ensemble, int(e.drift_free),
                       int(e.max_steps), int(e.scatter_law), int(collision_mode),
-                      int(getattr(e, "rebirth_steps", 0)), inj)
+                      int(getattr(e, "rebirth_steps", 0)), inj, float(getattr(e, "v_wind", 0.0)))
     return arr
 
 

@@ -47,6 +47,7 @@ class Ensemble:
     drift_free: bool = False
     scatter_law: int = 0                # 0: mu' = 1 - 2a ; 1: mu' = +-sqrt(a)
     rebirth_steps: int = 0              # > 0: an exit before this step count is a rebirth
+    v_wind: float = 0.0                 # > 0: scattering centres move with a radial wind of this speed (m/s)
 
 
 @dataclass
