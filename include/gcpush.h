@@ -145,6 +145,14 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *desc);
  * free path (id, 0, 0, g + 1), collision k (id, k, 0, g + 1)).  Its collision
  * log row is cleared.  rebirth_steps <= 0 turns rebirth off; at most 2^24; not
  * supported with the network field source (GC_EINVAL from gc_advance).
+ * Scattering in the wind frame (Sect. 3.3, adiabatic cooling): with v_wind > 0
+ * the scattering centres move with a radial wind of that speed.  Its component
+ * across B is the E x B drift of the guiding centre; along b it is
+ * V = v_wind b_r.  A collision boosts (p_par, energy) along b by V (Lorentz;
+ * p_perp unchanged), keeps |p~| there, sets p~_par = mu' |p~| and boosts back;
+ * the path of Eq. 9 is measured against the centres, Gamma |v_par - V| dt.
+ * v_wind = 0 keeps the inertial frame (|p| kept).  Not supported with the
+ * network field source (GC_EINVAL from gc_advance).
  * Ensemble parameters (q, m, lambda_par, r_in, r_out, max_steps, drift_free,
  * scatter_law, seed) are stored per ensemble index; injecting again into an
  * existing ensemble index replaces them.  lambda_par <= 0 disables scattering;
@@ -153,7 +161,7 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *desc);
  * 1: mu' = +-sqrt(a) (Eq. 12).
  * Errors: GC_ESTATE before gc_load_field; GC_EINVAL for ensemble >= 4096,
  * m <= 0, q == 0, ekin <= 0, r_in >= r_out, mu_lo/mu_hi outside [-1, 1],
- * rebirth_steps > 2^24.  n == 0 is a no-op. */
+ * rebirth_steps > 2^24, v_wind outside [0, 0.1 c).  n == 0 is a no-op. */
 typedef struct {
     uint32_t ensemble;
     uint32_t first_id;
@@ -170,6 +178,7 @@ typedef struct {
     int32_t drift_free;
     int32_t scatter_law;
     int64_t rebirth_steps;  /* > 0: rebirth of particles that exit before this step count */
+    double v_wind;          /* m/s; > 0: scattering centres move with a radial wind (Sect. 3.3) */
 } gc_inject_desc;
 
 gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *desc);

@@ -171,7 +171,8 @@ class Context:
         d = _abi.gc_inject_desc(ens.ensemble, first_id, ens.n if n is None else n, ens.seed, ens.q, ens.m, ens.ekin,
                                 ens.r0, ens.lat0, ens.lon0, ens.dlon, ens.dr0, ens.dlat, ens.mu_lo, ens.mu_hi,
                                 ens.lambda_par, ens.r_in, ens.r_out, int(ens.max_steps), int(ens.drift_free),
-                                int(ens.scatter_law), int(getattr(ens, "rebirth_steps", 0)))
+                                int(ens.scatter_law), int(getattr(ens, "rebirth_steps", 0)),
+                                float(getattr(ens, "v_wind", 0.0)))
         self._check(lib.gc_inject(self._h, C.byref(d)))
 
     # ------------------------------------------------------------- advance

@@ -36,7 +36,8 @@ class gc_inject_desc(C.Structure):
                 ("dlon", C.c_double), ("dr0", C.c_double), ("dlat", C.c_double),
                 ("mu_lo", C.c_double), ("mu_hi", C.c_double), ("lambda_par", C.c_double),
                 ("r_in", C.c_double), ("r_out", C.c_double), ("max_steps", C.c_int64),
-                ("drift_free", C.c_int32), ("scatter_law", C.c_int32), ("rebirth_steps", C.c_int64)]
+                ("drift_free", C.c_int32), ("scatter_law", C.c_int32), ("rebirth_steps", C.c_int64),
+                ("v_wind", C.c_double)]
 
 
 class gc_moment_spec(C.Structure):

@@ -61,6 +61,7 @@ struct gc_ctx {
     std::vector<char> ens_set;
     EnsDev *ens_dev = nullptr;
     bool any_rebirth = false;         // some ensemble has rebirth_steps > 0
+    bool any_wind = false;            // some ensemble scatters in the wind frame
     // particles (A is current, B is the permutation target)
     uint64_t n = 0, cap = 0;
     void *soa_mem[2] = {nullptr, nullptr};
@@ -318,7 +319,7 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     a.f = ctx->f;
     a.fdev = ctx->f_dev;
     a.ens = ctx->ens_dev;
-    a.rebirth = ctx->any_rebirth ? 1 : 0;
+    a.ext = ctx->any_rebirth || ctx->any_wind ? 1 : 0;
     a.n_active = ctx->n_active;
     a.n_slots = (uint32_t)ctx->n;
     a.n_steps = steps;
@@ -385,6 +386,8 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
         return fail(ctx, GC_ESTATE, "field_source is the neural field but gc_mlp_set was not called");
     if (ctx->opt.field_source == GC_SOURCE_MLP && ctx->any_rebirth)
         return fail(ctx, GC_EINVAL, "rebirth is not supported with the neural field source");
+    if (ctx->opt.field_source == GC_SOURCE_MLP && ctx->any_wind)
+        return fail(ctx, GC_EINVAL, "wind-frame scattering is not supported with the neural field source");
     return GC_OK;
 }
 
@@ -595,6 +598,8 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
     if (d->scatter_law != 0 && d->scatter_law != 1) return fail(ctx, GC_EINVAL, "scatter_law must be 0 or 1");
     if (d->rebirth_steps > (int64_t)kMaxRebirthSteps)
         return fail(ctx, GC_EINVAL, "rebirth_steps must be <= %lld", (long long)kMaxRebirthSteps);
+    if (!(d->v_wind >= 0.0 && d->v_wind < 0.1 * 299792458.0))
+        return fail(ctx, GC_EINVAL, "v_wind must be in [0, 0.1 c)");
     if (d->n == 0) return GC_OK;
     if ((uint64_t)d->first_id + d->n > 0x100000000ull) return fail(ctx, GC_EINVAL, "ids exceed 32 bits");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -622,11 +627,16 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
     e.mu_lo = d->mu_lo;
     e.mu_hi = d->mu_hi;
     e.rebirth_steps = d->rebirth_steps;
+    e.v_wind = d->v_wind;
     ctx->ens_host[d->ensemble] = e;
     ctx->ens_set[d->ensemble] = 1;
     ctx->any_rebirth = false;
-    for (int i = 0; i < kMaxEnsembles; ++i)
-        if (ctx->ens_set[i] && ctx->ens_host[i].rebirth_steps > 0) ctx->any_rebirth = true;
+    ctx->any_wind = false;
+    for (int i = 0; i < kMaxEnsembles; ++i) {
+        if (!ctx->ens_set[i]) continue;
+        if (ctx->ens_host[i].rebirth_steps > 0) ctx->any_rebirth = true;
+        if (ctx->ens_host[i].v_wind > 0.0) ctx->any_wind = true;
+    }
     HIPCHK(hipMemcpyAsync(ctx->ens_dev + d->ensemble, &ctx->ens_host[d->ensemble], sizeof(EnsDev),
                           hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(launch_inject(ctx->A, ctx->f, e, (uint32_t)ctx->n, (uint32_t)d->n, d->first_id, d->ensemble,

@@ -28,6 +28,7 @@ struct EnsDev {
     // injection site and spreads (Sect. 3), read again when a particle is reborn
     double ekin, r0, lat0, lon0, dlon, dr0, dlat, mu_lo, mu_hi;
     int64_t rebirth_steps;  // an exit at a step count below this is followed by a rebirth
+    double v_wind;          // > 0: scattering centres move with a radial wind of this speed (m/s)
 };
 
 // Packed field on the device: [nr][nth][nph+1][12], the extra phi node repeats
@@ -66,7 +67,7 @@ struct PushArgs {
     int32_t log_depth;
     int32_t tile;                  // persistent mode: particles per work item
     uint32_t *queue;               // persistent mode: next tile counter
-    int32_t rebirth;               // some ensemble has rebirth_steps > 0
+    int32_t ext;                   // some ensemble asks for rebirth or wind-frame scattering
 };
 
 }  // namespace gc

@@ -21,9 +21,10 @@ namespace gc {
 //                    lane gl = 0 writes.
 enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 
-// RB: some ensemble asks for rebirth.  A separate instantiation, because the
-// out-of-line rebirth raises the register count of the FP32 forms.
-template <int PREC, int FDT, bool RB, int FORM = kFormThroughput>
+// EXT: some ensemble asks for rebirth or for scattering in the wind frame
+// (Sect. 3 and 3.3).  A separate instantiation, because the out-of-line
+// rebirth raises the register count of the FP32 forms.
+template <int PREC, int FDT, bool EXT, int FORM = kFormThroughput>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
@@ -49,6 +50,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     const R qm = (R)e.qm, iqm = (R)e.iqm;
     const bool drift_free = e.drift_free != 0;
     const bool scatter = e.lambda > 0.0;
+    const R vw = EXT ? (R)e.v_wind : (R)0;          // > 0: scattering centres move with the wind
     const R h = (R)a.dt;
     const double r_in = e.r_in, r_out = e.r_out, th_lo = a.f.th_lo, th_hi = a.f.th_hi;
 
@@ -79,8 +81,11 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             if (stage == 0 && (flags & GC_FLAG_PENDING)) {
                 // collision k+1 (Eqs. 9-10): |p| kept, new pitch cosine and free path
                 const R B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-                const R p2 = pu * pu + (R)2 * mu * B;            // (p/m)^2
-                X3 = (A)(mun * sqrt(p2));
+                R p2 = pu * pu + (R)2 * mu * B;                  // (p/m)^2, kept in the inertial frame
+                R un;
+                if (EXT && vw > (R)0) wind_collision<R>(pu, mu, B, g[0], vw, mun, un, p2);
+                else un = mun * sqrt(p2);
+                X3 = (A)un;
                 c3 = 0;
                 pu = (R)X3;
                 mu = p2 * ((R)1 - mun * mun) / ((R)2 * B);
@@ -95,12 +100,12 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             gc_rhs<R>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp);
             if (stage == 2) {
                 Fs[0] = F[0]; Fs[1] = F[1]; Fs[2] = F[2]; Fs[3] = F[3];
-                vps = vp;
+                vps = EXT ? path_speed<R>(vp, g, vw) : vp;
                 break;
             }
             if (stage == 0) {
                 Fn[0] = F[0]; Fn[1] = F[1]; Fn[2] = F[2]; Fn[3] = F[3];
-                vpn = vp;
+                vpn = EXT ? path_speed<R>(vp, g, vw) : vp;
                 if (flags & GC_FLAG_BOOTSTRAP) {
                     // backward Euler start (Sect. 2.2)
                     px = (R)X0 - h * F[0]; pth = (R)X1 - h * F[1]; pph = (R)X2 - h * F[2]; pu = (R)X3 - h * F[3];
@@ -156,7 +161,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         if (!(isfinite(n0) && isfinite(n1) && isfinite(n2) && isfinite(n3))) { status = GC_NONFINITE; break; }
         const double r = (double)X0, th = (double)X1;
         if (r < r_in || r > r_out || th < th_lo || th > th_hi) {
-            if (!RB || (int64_t)step >= e.rebirth_steps) { status = GC_EXITED; break; }
+            if (!EXT || (int64_t)step >= e.rebirth_steps) { status = GC_EXITED; break; }
             // rebirth (continuous injection, Sect. 3): the next generation starts
             // from the injection state with its own generator stream
             const uint32_t gen = (flags >> GC_FLAG_GEN_SHIFT) + 1;
@@ -197,7 +202,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
 // gives each XCD a contiguous range of that prefix, so that (with cell-sorted
 // slots) its L2 holds the field cells of its own particles, and every XCD gets
 // an equal share however small the active prefix is.
-template <int PREC, int FDT, bool RB, int FORM>
+template <int PREC, int FDT, bool EXT, int FORM>
 __device__ __forceinline__ void push_grid(const PushArgs &a) {
     constexpr uint32_t G = FORM == kFormQuad ? 4 : 1;          // lanes per particle
     const uint32_t n = *a.n_active;
@@ -208,14 +213,14 @@ __device__ __forceinline__ void push_grid(const PushArgs &a) {
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
     const uint32_t slot = lb * per_block + threadIdx.x / G;
     uint32_t taken = 0;
-    if (slot < n) taken = advance_slot<PREC, FDT, RB, FORM>(a, slot, threadIdx.x % G);
+    if (slot < n) taken = advance_slot<PREC, FDT, EXT, FORM>(a, slot, threadIdx.x % G);
     count_steps(a, taken);
 }
 
 // Throughput form: at most 256 registers per lane (two wavefronts per SIMD).
-template <int PREC, int FDT, bool RB>
+template <int PREC, int FDT, bool EXT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
-    push_grid<PREC, FDT, RB, kFormThroughput>(a);
+    push_grid<PREC, FDT, EXT, kFormThroughput>(a);
 }
 
 // Latency forms, for fewer active particles than fill the machine: a
@@ -223,19 +228,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // and by how many distinct cache lines its load instructions touch.  The
 // all-pairs form has each gather in one round trip; the quad form also spreads
 // the particles over four times as many wavefronts (and compute units).
-template <int PREC, int FDT, bool RB>
+template <int PREC, int FDT, bool EXT>
 __global__ __launch_bounds__(256) void k_push_allpairs(PushArgs a) {
-    push_grid<PREC, FDT, RB, kFormAllPairs>(a);
+    push_grid<PREC, FDT, EXT, kFormAllPairs>(a);
 }
 
-template <int PREC, int FDT, bool RB>
+template <int PREC, int FDT, bool EXT>
 __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
-    push_grid<PREC, FDT, RB, kFormQuad>(a);
+    push_grid<PREC, FDT, EXT, kFormQuad>(a);
 }
 
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
 // atomic counter until the tiles run out (every workgroup reaches the exit).
-template <int PREC, int FDT, bool RB>
+template <int PREC, int FDT, bool EXT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
@@ -250,32 +255,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (t >= ntiles) break;
         const uint32_t end = min(n, (t + 1) * tile);
         for (uint32_t slot = t * tile + threadIdx.x; slot < end; slot += blockDim.x)
-            taken += advance_slot<PREC, FDT, RB>(a, slot);
+            taken += advance_slot<PREC, FDT, EXT>(a, slot);
     }
     count_steps(a, taken);
 }
 
 
-template <int PREC, int FDT, bool RB>
+template <int PREC, int FDT, bool EXT>
 static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
     if (persistent) {
-        hipLaunchKernelGGL((k_push_persistent<PREC, FDT, RB>), dim3(grid_blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_push_persistent<PREC, FDT, EXT>), dim3(grid_blocks), dim3(block), 0, s, a);
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;
         if (form == kFormQuad)
-            hipLaunchKernelGGL((k_push_quad<PREC, FDT, RB>), dim3(4 * nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push_quad<PREC, FDT, EXT>), dim3(4 * nb), dim3(block), 0, s, a);
         else if (form == kFormAllPairs)
-            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, RB>), dim3(nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, EXT>), dim3(nb), dim3(block), 0, s, a);
         else
-            hipLaunchKernelGGL((k_push<PREC, FDT, RB>), dim3(nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push<PREC, FDT, EXT>), dim3(nb), dim3(block), 0, s, a);
     }
     return hipGetLastError();
 }
 
 template <int PREC, int FDT>
 static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
-    return a.rebirth ? launch_r<PREC, FDT, true>(a, block, persistent, form, grid_blocks, s)
+    return a.ext ? launch_r<PREC, FDT, true>(a, block, persistent, form, grid_blocks, s)
                      : launch_r<PREC, FDT, false>(a, block, persistent, form, grid_blocks, s);
 }
 

@@ -39,6 +39,36 @@ __device__ __noinline__ CollisionDraw draw_collision(uint32_t pid, uint32_t k1, 
     return d;
 }
 
+// Collision in the frame of the scattering centres when they move with a
+// radial wind of speed vw (Sect. 3.3).  The wind's component across B is the
+// E x B drift the guiding centre already moves with; along b it is
+// V = vw b_r.  A Lorentz boost along b by V takes (p_par, energy) to the wind
+// frame (p_perp unchanged); the collision keeps |p~| and sets
+// p~_par = mun |p~|; the boost back gives the new u = p_par / m.  In: u, mu =
+// mu_B / m, |B|, B_r, mun.  Out: u_new and (|p~| / m)^2, from which the
+// caller takes mu_B / m = |p~|^2 (1 - mun^2) / (2 |B|).
+template <typename R>
+__device__ __forceinline__ void wind_collision(R u, R mu, R B, R Br, R vw, R mun, R &u_new, R &P2) {
+    const R V = vw * Br / B;
+    const R G = rsqrt_nr((R)1 - V * V * (R)kInvC2);
+    const R pp2 = (R)2 * mu * B;                       // (p_perp / m)^2
+    const R gam = sqrt((R)1 + (u * u + pp2) * (R)kInvC2);
+    const R uw = G * (u - V * gam);                    // wind frame: p_par / m
+    const R gw = G * (gam - V * u * (R)kInvC2);        // wind frame: gamma
+    P2 = uw * uw + pp2;
+    u_new = G * (mun * sqrt(P2) + V * gw);
+}
+
+// Speed along b against the scattering centres, for the path of Eq. 9:
+// |v_par| for centres at rest, Gamma |v_par - V| for centres moving with the
+// wind (V = vw b_r; a boost along b turns dx - V dt into Gamma (v_par - V) dt).
+template <typename R>
+__device__ __forceinline__ R path_speed(R vp, const R g[12], R vw) {
+    if (!(vw > (R)0)) return fabs(vp);
+    const R V = vw * g[0] * rsqrt_nr(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    return rsqrt_nr((R)1 - V * V * (R)kInvC2) * fabs(vp - V);
+}
+
 // Initial state of particle pid (Sect. 3 injection), FP64: site, spreads and
 // pitch cosine from block (pid, 0, inject, 0), the same for every generation;
 // the first free path of generation gen from block (pid, 0, path, gen);
