@@ -166,8 +166,8 @@ def steady_spec(min_birth: int):
         n_rbins, r_lo, r_hi = 38, 0.1 * AU, 2.0 * AU
         n_mubins, sel_r_lo, sel_r_hi = 36, 0.9 * AU, 1.1 * AU
         age_lo, age_hi, min_collisions = 0.0, 1e12, 0
-        n_agebins, age_max = 60, 30 * 3600.0
-        n_ebins, e_lo, e_hi = 64, 70e3, 82e3
+        n_agebins, age_max = 96, 12 * 3600.0          # 7.5 min age bins
+        n_ebins, e_lo, e_hi = 80, 62e3, 82e3          # 0.25 keV energy bins
         e_unit, len_unit = E_CHARGE, AU
     Spec.min_birth = min_birth
     return Spec
@@ -184,6 +184,11 @@ def run_steady(args, n=None, hours=None, field=None, with_cpu=True):
     from synthetic import workloads, AU
     wl = workloads.config_steady(seed=args.seed, n=n or args.steady_particles,
                                  hours=hours or args.steady_hours, store_dtype=args.store)
+    if getattr(args, "steady_wind", False):
+        # Fig. 11 setting: centres moving with a 418 km/s wind, only v_par b kept
+        from dataclasses import replace
+        wl.ensembles = [replace(wl.ensembles[0], v_wind=418e3, drift_free=True)]
+        wl.name += "-windframe"
     if field is None:
         field = np.ascontiguousarray(wl.build_field(wl.grid, device="cuda"))
     every = wl.bin_interval
@@ -237,12 +242,38 @@ def run_steady(args, n=None, hours=None, field=None, with_cpu=True):
            "r_mean_AU": {f"{h:g}h": round(float(r_mean[min(n_snap - 1, int(round(h * 3600 / wl.dt / every)) - 1)]), 4)
                          for h in (1, 2, 4, 8.3, 20, 50, 100, 150) if h * 3600 / wl.dt / every <= n_snap},
            "steady_after_h": round(float(t_h[near[0]]), 2) if len(near) else None,
+           "energy_vs_age_near_1AU": energy_vs_age(a, spec),
            "forms": {"launches": c["form_launches"], "ms": [round(x, 1) for x in c["form_ms"]],
                      "particle_steps": c["form_steps"]}}
     log(f"[bench] steady: {out['value']:.3e} particle-steps/s, {elapsed:.1f} s for {out['simulated_hours']:.0f} h; "
         f"{out['rebirths_per_electron']:.1f} rebirths per electron; steady after {out['steady_after_h']} h")
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline_steady(args, wl, field)
+    return out
+
+
+def energy_vs_age(a, spec):
+    """Mean kinetic energy (keV) of the accumulated electrons near 1 AU per age
+    bin, and the loss rate (keV/h) at a few ages (central differences over
+    +-2 bins), from the energy-vs-age histogram of the accumulated moments."""
+    import numpy as np
+    nb = spec.n_rbins
+    h = a[8 + 3 * nb + spec.n_mubins:].reshape(spec.n_agebins, spec.n_ebins).astype(np.float64)
+    e_mid = (spec.e_lo + (np.arange(spec.n_ebins) + 0.5) * (spec.e_hi - spec.e_lo) / spec.n_ebins) / 1e3
+    cnt = h.sum(1)
+    mean = np.where(cnt > 0, (h * e_mid).sum(1) / np.maximum(cnt, 1), np.nan)
+    da = spec.age_max / spec.n_agebins / 3600.0
+    age_mid = (np.arange(spec.n_agebins) + 0.5) * da
+    def num(x):
+        return None if not np.isfinite(x) else round(float(x), 3)
+    out = {"samples": int(cnt.sum()),
+           "mean_keV": {f"{t:g}h": num(mean[int(t / da)]) for t in (0.3, 0.5, 1, 2, 4, 8)}}
+    rates = {}
+    for t in (0.3, 1, 4):            # least-squares slope over the populated bins within +-2 of the age
+        i = int(t / da)
+        sel = [j for j in range(max(i - 2, 0), min(i + 3, spec.n_agebins)) if cnt[j] > 0]
+        rates[f"{t:g}h"] = num(np.polyfit(age_mid[sel], mean[sel], 1)[0]) if len(sel) >= 2 else None
+    out["loss_rate_keV_per_h"] = rates
     return out
 
 
@@ -508,6 +539,8 @@ def main():
     ap.add_argument("--steady-hours", type=float, default=150.0)
     ap.add_argument("--steady-cpu-steps", type=int, default=20000)
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state summary of the default run")
+    ap.add_argument("--steady-wind", action="store_true",
+                    help="steady-state job with scattering in the wind frame and only v_par b (Fig. 11 setting)")
     ap.add_argument("--mlp-particles", type=int, default=10 << 20)
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (batched workload)")
     args = ap.parse_args()
