@@ -6,7 +6,7 @@ and marshals numpy arrays; all arithmetic happens in the C code.
 """
 from .oracle import (  # noqa: F401
     PARTICLE_DTYPE, ACTIVE, EXITED, FINISHED, NONFINITE, BOOTSTRAP, PENDING,
-    Field, philox, u01, field_eval, parker_closed_form, rhs, pc_predict, pc_correct,
+    Field, philox, u01, field_eval, field_eval_extra, parker_closed_form, rhs, pc_predict, pc_correct,
     make_ens_table, inject, advance, advance_traj, moments, moments_size, MomentSpec, max_threads,
     lib,
 )

@@ -6,7 +6,8 @@
  *
  * Each function follows one passage of the paper:
  *   or_field_eval        trilinear interpolation of the gridded field (Sect. 2.2)
- *   or_rhs               GC equations, Eqs. (1)-(3), with the definitions that follow them
+ *   or_rhs               GC equations, Eqs. (1)-(3), with the definitions that follow them;
+ *                        the terms with derivatives of b and v_E when the field carries them
  *   or_pc_predict/correct third-order predictor-corrector, Eqs. (5)-(6)
  *   bootstrap            backward Euler start at t = 0 and after a collision (Sect. 2.2)
  *   collisions           hard-sphere scattering, Eqs. (9)-(10) (and (12)), in the inertial
@@ -102,6 +103,39 @@ void or_parker_closed_form(double a0, double omega, double v, double r, double t
 static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 /* returns 1 if every input and output is finite */
+/* trilinear interpolation of an [nr][nth][nph][nc] node array */
+static void grid_interp(const or_field *f, const double *data, int nc, double r, double th, double ph, double *out)
+{
+    const int nr = f->nr, nth = f->nth, nph = f->nph;
+    const double dr = (f->r_max - f->r_min) / (nr - 1);
+    const double dth = OR_PI / nth;
+    const double dph = 2.0 * OR_PI / nph;
+    /* index-space coordinates: r nodes from r_min, theta nodes cell-centred, phi periodic */
+    double x = (r - f->r_min) / dr;
+    double y = th / dth - 0.5;
+    double z = ph / dph;
+    double fi = clampd(floor(x), 0.0, (double)(nr - 2));
+    double fj = clampd(floor(y), 0.0, (double)(nth - 2));
+    int i = (int)fi, j = (int)fj;
+    double wr = clampd(x - fi, 0.0, 1.0);
+    double wt = clampd(y - fj, 0.0, 1.0);
+    double zf = floor(z);
+    double wp = z - zf;
+    double km = fmod(zf, (double)nph);
+    if (km < 0) km += nph;
+    int k0 = (int)km;
+    int k1 = (k0 + 1) % nph;
+    for (int c = 0; c < nc; ++c) out[c] = 0.0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int cc = 0; cc < 2; ++cc) {
+                double w = (a ? wr : 1.0 - wr) * (b ? wt : 1.0 - wt) * (cc ? wp : 1.0 - wp);
+                size_t node = ((size_t)(i + a) * nth + (size_t)(j + b)) * nph + (size_t)(cc ? k1 : k0);
+                const double *v = data + node * nc;
+                for (int c = 0; c < nc; ++c) out[c] += w * v[c];
+            }
+}
+
 int or_field_eval(const or_field *f, double r, double th, double ph, double out[12])
 {
     if (!(isfinite(r) && isfinite(th) && isfinite(ph))) return 0;
@@ -110,36 +144,20 @@ int or_field_eval(const or_field *f, double r, double th, double ph, double out[
     } else if (f->kind == OR_FIELD_CALLBACK) {
         if (!f->eval || !f->eval(f->user, r, th, ph, out)) return 0;
     } else {
-        const int nr = f->nr, nth = f->nth, nph = f->nph;
-        const double dr = (f->r_max - f->r_min) / (nr - 1);
-        const double dth = OR_PI / nth;
-        const double dph = 2.0 * OR_PI / nph;
-        /* index-space coordinates: r nodes from r_min, theta nodes cell-centred, phi periodic */
-        double x = (r - f->r_min) / dr;
-        double y = th / dth - 0.5;
-        double z = ph / dph;
-        double fi = clampd(floor(x), 0.0, (double)(nr - 2));
-        double fj = clampd(floor(y), 0.0, (double)(nth - 2));
-        int i = (int)fi, j = (int)fj;
-        double wr = clampd(x - fi, 0.0, 1.0);
-        double wt = clampd(y - fj, 0.0, 1.0);
-        double zf = floor(z);
-        double wp = z - zf;
-        double km = fmod(zf, (double)nph);
-        if (km < 0) km += nph;
-        int k0 = (int)km;
-        int k1 = (k0 + 1) % nph;
-        for (int c = 0; c < 12; ++c) out[c] = 0.0;
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int cc = 0; cc < 2; ++cc) {
-                    double w = (a ? wr : 1.0 - wr) * (b ? wt : 1.0 - wt) * (cc ? wp : 1.0 - wp);
-                    size_t node = ((size_t)(i + a) * nth + (size_t)(j + b)) * nph + (size_t)(cc ? k1 : k0);
-                    const double *v = f->data + node * 12;
-                    for (int c = 0; c < 12; ++c) out[c] += w * v[c];
-                }
+        grid_interp(f, f->data, 12, r, th, ph, out);
     }
     for (int c = 0; c < 12; ++c) if (!isfinite(out[c])) return 0;
+    return 1;
+}
+
+/* The three vectors of the full Eqs. 1-2, (v_E.grad)b, (b.grad)v_E and
+ * (v_E.grad)v_E, interpolated like the field; 0 when the field has none. */
+int or_field_eval_extra(const or_field *f, double r, double th, double ph, double out[9])
+{
+    if (f->kind != OR_FIELD_GRID || !f->extra) return 0;
+    if (!(isfinite(r) && isfinite(th) && isfinite(ph))) return 0;
+    grid_interp(f, f->extra, 9, r, th, ph, out);
+    for (int c = 0; c < 9; ++c) if (!isfinite(out[c])) return 0;
     return 1;
 }
 
@@ -173,7 +191,7 @@ static double dot(const double a[3], const double b[3]) { return a[0] * b[0] + a
  * Position rates: (V_r, V_th / r, V_ph / (r sin th)).
  */
 void or_rhs(const double X[4], double mu_B, double q, double m, int drift_free,
-            const double fld[12], double F[4], double *vpar_out, double *gamma_out)
+            const double fld[12], const double *xfld, double F[4], double *vpar_out, double *gamma_out)
 {
     const double r = X[0], th = X[1], u = X[3];
     const double *Bv = fld, *E = fld + 3, *G = fld + 6, *K = fld + 9;
@@ -195,10 +213,17 @@ void or_rhs(const double X[4], double mu_B, double q, double m, int drift_free,
             a[c] = mu_B / (gamma * gamma * m) * G[c]
                  + q * vpar * Epar / (gamma * m * OR_C * OR_C) * vE[c]
                  + vpar * vpar * K[c];
+        udot = (q / m) * Epar - mu_B / (gamma * m) * dot(b, G) + gamma * vpar * dot(vE, K);
+        if (xfld) {
+            /* the full Eqs. 1-2: v_par((v_E.grad)b + (b.grad)v_E) + (v_E.grad)v_E in the
+             * bracket of dR/dt, gamma v_E.(v_E.grad)b in d(gamma v_par)/dt */
+            const double *A = xfld, *Cv = xfld + 3, *D = xfld + 6;
+            for (int c = 0; c < 3; ++c) a[c] += vpar * (A[c] + Cv[c]) + D[c];
+            udot += gamma * dot(vE, A);
+        }
         cross(b, a, bxa);
         double pref = gamma * m / (q * B);
         for (int c = 0; c < 3; ++c) V[c] = vpar * b[c] + vE[c] + pref * bxa[c];
-        udot = (q / m) * Epar - mu_B / (gamma * m) * dot(b, G) + gamma * vpar * dot(vE, K);
     }
     F[0] = V[0];
     F[1] = V[1] / r;
@@ -385,6 +410,7 @@ static int finite4(const double X[4])
 static void advance_one(const or_field *f, const or_ens *e, or_particle *p, double dt, int64_t n_steps,
                         const or_log *log, int64_t pi, double *traj)
 {
+    const int full = f->kind == OR_FIELD_GRID && f->extra != NULL;   /* full Eqs. 1-2 */
     for (int64_t it = 0; it < n_steps; ++it) {
         if (p->status != OR_ACTIVE) return;
         double X[4] = { p->r, p->th, p->ph, p->u };
@@ -394,15 +420,19 @@ static void advance_one(const or_field *f, const or_ens *e, or_particle *p, doub
             collide(e, p, g, log, pi);
             X[3] = p->u;
         }
-        double Fn[4], vpn, gam;
-        or_rhs(X, p->mu_B, e->q, e->m, e->drift_free, g, Fn, &vpn, &gam);
+        double Fn[4], vpn, gam, xg[9];
+        const double *xn = full ? (or_field_eval_extra(f, X[0], X[1], X[2], xg) ? xg : NULL) : NULL;
+        if (full && !xn) { p->status = OR_NONFINITE; return; }
+        or_rhs(X, p->mu_B, e->q, e->m, e->drift_free, g, xn, Fn, &vpn, &gam);
         double Fp[4], tau;
         if (p->flags & OR_BOOTSTRAP) {
             /* X^{n-1} = X^n - dt F^n, F^{n-1} = F(X^{n-1}) (Sect. 2.2) */
             double Xm[4], gm[12];
             for (int c = 0; c < 4; ++c) Xm[c] = X[c] - dt * Fn[c];
             if (!or_field_eval(f, Xm[0], Xm[1], Xm[2], gm)) { p->status = OR_NONFINITE; return; }
-            or_rhs(Xm, p->mu_B, e->q, e->m, e->drift_free, gm, Fp, NULL, NULL);
+            double xm[9];
+            if (full && !or_field_eval_extra(f, Xm[0], Xm[1], Xm[2], xm)) { p->status = OR_NONFINITE; return; }
+            or_rhs(Xm, p->mu_B, e->q, e->m, e->drift_free, gm, full ? xm : NULL, Fp, NULL, NULL);
             tau = 1.0;
             p->flags &= ~OR_BOOTSTRAP;
         } else {
@@ -412,7 +442,9 @@ static void advance_one(const or_field *f, const or_ens *e, or_particle *p, doub
         double Xs[4], gs[12], Fs[4], vps;
         or_pc_predict(X, Fn, Fp, dt, tau, Xs);
         if (!or_field_eval(f, Xs[0], Xs[1], Xs[2], gs)) { p->status = OR_NONFINITE; return; }
-        or_rhs(Xs, p->mu_B, e->q, e->m, e->drift_free, gs, Fs, &vps, NULL);
+        double xs[9];
+        if (full && !or_field_eval_extra(f, Xs[0], Xs[1], Xs[2], xs)) { p->status = OR_NONFINITE; return; }
+        or_rhs(Xs, p->mu_B, e->q, e->m, e->drift_free, gs, full ? xs : NULL, Fs, &vps, NULL);
         double Xn[4];
         or_pc_correct(X, Fn, Fs, Fp, dt, tau, Xn);
         double ds = path_step(e, vpn, g, vps, gs, dt);

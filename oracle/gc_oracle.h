@@ -36,6 +36,10 @@ typedef struct {
      * single-threaded: pass nthreads = 1 to the advance calls. */
     int (*eval)(void *user, double r, double th, double ph, double out[12]);
     void *user;
+    /* grid fields only: NULL, or [nr][nth][nph][9] node values of (v_E.grad)b,
+     * (b.grad)v_E and (v_E.grad)v_E (local basis); with them the full Eqs. 1-2 are
+     * integrated, without them the reduced form */
+    const double *extra;
 } or_field;
 
 typedef struct {
@@ -105,7 +109,8 @@ double or_u01(uint64_t x);
 int  or_field_eval(const or_field *f, double r, double th, double ph, double out[12]);
 void or_parker_closed_form(double a0, double omega, double v_wind, double r, double th, double out[12]);
 void or_rhs(const double X[4], double mu_B, double q, double m, int drift_free,
-            const double fld[12], double F[4], double *vpar, double *gamma);
+            const double fld[12], const double *xfld, double F[4], double *vpar, double *gamma);
+int  or_field_eval_extra(const or_field *f, double r, double th, double ph, double out[9]);
 void or_pc_predict(const double X[4], const double Fn[4], const double Fp[4],
                    double h, double tau, double out[4]);
 void or_pc_correct(const double X[4], const double Fn[4], const double Fs[4], const double Fp[4],

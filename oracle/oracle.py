@@ -29,7 +29,7 @@ class _Field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nr", C.c_int32), ("nth", C.c_int32), ("nph", C.c_int32),
                 ("r_min", C.c_double), ("r_max", C.c_double), ("data", C.c_void_p),
                 ("a0", C.c_double), ("omega", C.c_double), ("v_wind", C.c_double),
-                ("eval", EVAL_FN), ("user", C.c_void_p)]
+                ("eval", EVAL_FN), ("user", C.c_void_p), ("extra", C.c_void_p)]
 
 
 class _Inject(C.Structure):
@@ -72,7 +72,9 @@ def _load():
     L.or_field_eval.argtypes = [C.POINTER(_Field), C.c_double, C.c_double, C.c_double, P]
     L.or_field_eval.restype = C.c_int
     L.or_parker_closed_form.argtypes = [C.c_double] * 5 + [P]
-    L.or_rhs.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P]
+    L.or_rhs.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_int, P, P, P, P, P]
+    L.or_field_eval_extra.argtypes = [C.POINTER(_Field), C.c_double, C.c_double, C.c_double, P]
+    L.or_field_eval_extra.restype = C.c_int
     L.or_pc_predict.argtypes = [P, P, P, C.c_double, C.c_double, P]
     L.or_pc_correct.argtypes = [P, P, P, P, C.c_double, C.c_double, P]
     L.or_inject.argtypes = [C.POINTER(_Field), C.POINTER(_Ens), C.c_uint32, P, C.c_int64, P]
@@ -98,9 +100,13 @@ class Field:
     spiral, or a callback fn(r, th, ph) -> 12 components (or None where
     undefined); advance calls with a callback field must use nthreads=1."""
 
-    def __init__(self, grid, data: Optional[np.ndarray] = None, parker: Optional[dict] = None, callback=None):
+    def __init__(self, grid, data: Optional[np.ndarray] = None, parker: Optional[dict] = None, callback=None,
+                 extra: Optional[np.ndarray] = None):
+        """extra (grid fields only): [nr][nth][nph][9] node values of (v_E.grad)b,
+        (b.grad)v_E and (v_E.grad)v_E; with it the full Eqs. 1-2 are integrated."""
         self.grid = grid
         self.callback = callback
+        self.extra = None
         if callback is not None:
             def _eval(_user, r, th, ph, out):
                 g = callback(r, th, ph)
@@ -118,6 +124,10 @@ class Field:
             assert self.data.shape == (grid.nr, grid.nth, grid.nph, 12)
             self._s = _Field(FIELD_GRID, grid.nr, grid.nth, grid.nph, grid.r_min, grid.r_max,
                              self.data.ctypes.data, 0.0, 0.0, 0.0)
+            if extra is not None:
+                self.extra = np.ascontiguousarray(extra, dtype=np.float64)
+                assert self.extra.shape == (grid.nr, grid.nth, grid.nph, 9)
+                self._s.extra = self.extra.ctypes.data
         else:
             self.data = None
             self._s = _Field(FIELD_PARKER, grid.nr, grid.nth, grid.nph, grid.r_min, grid.r_max,
@@ -152,13 +162,24 @@ def parker_closed_form(a0, omega, v, r, th) -> np.ndarray:
     return o
 
 
-def rhs(X, mu_B, q, m, fld, drift_free=False):
+def field_eval_extra(field: Field, r: float, th: float, ph: float):
+    o = np.zeros(9)
+    ok = lib.or_field_eval_extra(field.ref, r, th, ph, _ptr(o))
+    return o, bool(ok)
+
+
+def rhs(X, mu_B, q, m, fld, drift_free=False, extra=None):
+    """GC right-hand side; extra (9 values) adds the terms of the full Eqs. 1-2."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     fld = np.ascontiguousarray(fld, dtype=np.float64)
+    xp = None
+    if extra is not None:
+        extra = np.ascontiguousarray(extra, dtype=np.float64)
+        xp = _ptr(extra)
     F = np.zeros(4)
     vp = C.c_double()
     g = C.c_double()
-    lib.or_rhs(_ptr(X), mu_B, q, m, int(drift_free), _ptr(fld), _ptr(F), C.addressof(vp), C.addressof(g))
+    lib.or_rhs(_ptr(X), mu_B, q, m, int(drift_free), _ptr(fld), xp, _ptr(F), C.addressof(vp), C.addressof(g))
     return F, vp.value, g.value
 
 

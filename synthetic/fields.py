@@ -21,6 +21,13 @@ automatic differentiation (torch.autograd.forward_ad), and
   (b.grad)b = (J b - b (b . J b)) / |B|,
 before all vectors are projected on the local basis (r^, th^, ph^) at the node.
 Everything is float64.  The builder runs on any torch device.
+
+For the full guiding-centre equations (the terms of Eqs. 1-2 with derivatives
+of b and v_E) a second node array holds, in the same local basis,
+  A = (v_E.grad) b,   C = (b.grad) v_E,   D = (v_E.grad) v_E,
+with v_E = E x B / B^2, each a directional derivative taken by forward-mode
+automatic differentiation along v_E or b at the node (``*_extra`` builders,
+[nr][nth][nph][9]).
 """
 from __future__ import annotations
 
@@ -32,7 +39,7 @@ import torch
 import torch.autograd.forward_ad as fwAD
 
 from .constants import AU, OMEGA_SUN, V_WIND, B0_1AU
-from .grid import SphericalGrid, N_COMP
+from .grid import SphericalGrid, N_COMP, N_EXTRA
 
 
 # ----------------------------------------------------------------------------
@@ -148,17 +155,55 @@ def _local_from_cartesian(bfun: Callable, r, th, ph, v_wind: float):
     return torch.stack(out, dim=1)                 # [n][12]
 
 
-def _build(grid: SphericalGrid, bfun: Callable, v_wind: float, device=None, slab: int = 0) -> np.ndarray:
+def _cross(a, b):
+    return torch.stack([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]])
+
+
+def _extra_from_cartesian(bfun: Callable, r, th, ph, v_wind: float):
+    """A = (v_E.grad) b, C = (b.grad) v_E, D = (v_E.grad) v_E at the nodes, [n][9]."""
+    st, ct = torch.sin(th), torch.cos(th)
+    sp, cp = torch.sin(ph), torch.cos(ph)
+    pos = torch.stack([r * st * cp, r * st * sp, r * ct])
+
+    def b_and_vE(q):
+        B = torch.stack(bfun(q[0], q[1], q[2]))
+        rhat = q / torch.sqrt((q * q).sum(0))
+        E = -v_wind * _cross(rhat, B)
+        B2 = (B * B).sum(0)
+        return B / torch.sqrt(B2), _cross(E, B) / B2
+
+    b0, vE0 = b_and_vE(pos)
+    with fwAD.dual_level():
+        b1, vE1 = b_and_vE(fwAD.make_dual(pos, vE0))
+        A = torch.stack([fwAD.unpack_dual(c).tangent for c in b1])
+        D = torch.stack([fwAD.unpack_dual(c).tangent for c in vE1])
+    with fwAD.dual_level():
+        _, vE2 = b_and_vE(fwAD.make_dual(pos, b0))
+        C = torch.stack([fwAD.unpack_dual(c).tangent for c in vE2])
+    rhat = torch.stack([st * cp, st * sp, ct])
+    thhat = torch.stack([ct * cp, ct * sp, -st])
+    phhat = torch.stack([-sp, cp, torch.zeros_like(sp)])
+    out = []
+    for vec in (A, C, D):
+        out.append((vec * rhat).sum(0))
+        out.append((vec * thhat).sum(0))
+        out.append((vec * phhat).sum(0))
+    return torch.stack(out, dim=1)                 # [n][9]
+
+
+def _build(grid: SphericalGrid, bfun: Callable, v_wind: float, device=None, slab: int = 0,
+           extra: bool = False) -> np.ndarray:
     device = torch.device("cpu") if device is None else torch.device(device)
     if slab <= 0:   # r-slices per batch: ~4M nodes on a GPU, ~0.25M on the host
         per = grid.nth * grid.nph
         slab = max(1, (4_000_000 if device.type == "cuda" else 250_000) // per)
-    out = np.empty(grid.shape(), dtype=np.float64)
+    nc = N_EXTRA if extra else N_COMP
+    out = np.empty(grid.shape()[:3] + (nc,), dtype=np.float64)
     for i0 in range(0, grid.nr, slab):
         i1 = min(grid.nr, i0 + slab)
         r, th, ph = _node_coords(grid, i0, i1, device)
-        vals = _local_from_cartesian(bfun, r, th, ph, v_wind)
-        out[i0:i1] = vals.reshape(i1 - i0, grid.nth, grid.nph, N_COMP).cpu().numpy()
+        vals = (_extra_from_cartesian if extra else _local_from_cartesian)(bfun, r, th, ph, v_wind)
+        out[i0:i1] = vals.reshape(i1 - i0, grid.nth, grid.nph, nc).cpu().numpy()
     return out
 
 
@@ -172,6 +217,18 @@ def perturbed_parker(grid: SphericalGrid, seed: int = 1, eps: float = 0.1,
     """Parker spiral plus seeded Fourier perturbation, float64 [nr][nth][nph][12]."""
     modes = draw_modes(seed, n_modes)
     return _build(grid, perturbed_parker_B(modes, eps), V_WIND, device)
+
+
+def parker_extra(grid: SphericalGrid, device=None) -> np.ndarray:
+    """(v_E.grad) b, (b.grad) v_E, (v_E.grad) v_E of the Parker spiral, [nr][nth][nph][9]."""
+    return _build(grid, parker_B, V_WIND, device, extra=True)
+
+
+def perturbed_parker_extra(grid: SphericalGrid, seed: int = 1, eps: float = 0.1,
+                           n_modes: int = 16, device=None) -> np.ndarray:
+    """The same terms for the perturbed spiral, [nr][nth][nph][9]."""
+    modes = draw_modes(seed, n_modes)
+    return _build(grid, perturbed_parker_B(modes, eps), V_WIND, device, extra=True)
 
 
 # Affine test field: value = a + b * (r - r_ref) / AU + c * (th - pi/2), per component.

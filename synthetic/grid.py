@@ -20,6 +20,10 @@ import numpy as np
 N_COMP = 12
 COMP_NAMES = ("Br", "Bth", "Bph", "Er", "Eth", "Eph",
               "Gr", "Gth", "Gph", "Kr", "Kth", "Kph")
+# optional second node array for the full guiding-centre equations, [nr][nth][nph][9]:
+# A = (v_E.grad) b, C = (b.grad) v_E, D = (v_E.grad) v_E (v_E = E x B / B^2), local basis
+N_EXTRA = 9
+EXTRA_NAMES = ("Ar", "Ath", "Aph", "Cr", "Cth", "Cph", "Dr", "Dth", "Dph")
 
 
 @dataclass(frozen=True)
