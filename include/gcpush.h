@@ -113,6 +113,15 @@ gc_status gc_get_options(const gc_ctx *ctx, gc_options *opt);
  * The library copies and repacks the data in store_dtype (GC_F16 stores each
  * component divided by a per-component power-of-two scale); the caller's buffer
  * may be freed when the call returns.  The call waits for the upload.
+ * extra: NULL (the reduced Eqs. 1-2, dropping the terms with derivatives of b
+ *   and v_E), or a HOST pointer to [nr][nth][nph][9] values of src_dtype:
+ *   (v_E.grad)b | (b.grad)v_E | (v_E.grad)v_E, local basis, v_E = E x B / B^2;
+ *   with it every push integrates the full Eqs. 1-2: v_par((v_E.grad)b +
+ *   (b.grad)v_E) + (v_E.grad)v_E is added to the bracket of dR/dt and
+ *   gamma v_E.(v_E.grad)b to d(gamma v_par)/dt (not in the drift-free form).
+ *   Stored like the field (same layout, 3 zero components); the push then
+ *   makes a second gather at each evaluation and uses no quad form.  Not
+ *   supported with the network field source (GC_EINVAL from gc_advance).
  * Errors: GC_EINVAL if nr < 2, nth < 2, nph < 2, r_min <= 0, r_max <= r_min,
  * data == NULL or a dtype is unknown.  Loading a new field keeps the particles. */
 typedef struct {
@@ -122,6 +131,7 @@ typedef struct {
     const void *data;       /* host */
     int32_t store_dtype;    /* GC_F64, GC_F32 or GC_F16 */
     int32_t pad;
+    const void *extra;      /* host or NULL: the full-equation terms, see above */
 } gc_field_desc;
 
 gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *desc);

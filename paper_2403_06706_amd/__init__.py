@@ -157,12 +157,20 @@ class Context:
         return n.value
 
     # --------------------------------------------------------------- field
-    def load_field(self, grid, data: np.ndarray, store_dtype: str = "f64"):
+    def load_field(self, grid, data: np.ndarray, store_dtype: str = "f64", extra: Optional[np.ndarray] = None):
+        """data [nr][nth][nph][12]; extra (optional, same dtype) [nr][nth][nph][9]:
+        the node values that switch the push to the full Eqs. 1-2."""
         arr = np.ascontiguousarray(data)
         if arr.dtype not in (np.float64, np.float32):
             raise TypeError("field data must be float64 or float32")
+        xp = None
+        if extra is not None:
+            xarr = np.ascontiguousarray(extra, dtype=arr.dtype)
+            if xarr.shape != (grid.nr, grid.nth, grid.nph, 9):
+                raise ValueError("extra must be [nr][nth][nph][9]")
+            xp = xarr.ctypes.data
         d = _abi.gc_field_desc(grid.nr, grid.nth, grid.nph, GC_F64 if arr.dtype == np.float64 else GC_F32,
-                               grid.r_min, grid.r_max, arr.ctypes.data, _DTYPES[store_dtype], 0)
+                               grid.r_min, grid.r_max, arr.ctypes.data, _DTYPES[store_dtype], 0, xp)
         self._check(lib.gc_load_field(self._h, C.byref(d)))
 
     # ----------------------------------------------------------- injection

@@ -26,7 +26,7 @@ class gc_options(C.Structure):
 class gc_field_desc(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nth", C.c_int32), ("nph", C.c_int32), ("src_dtype", C.c_int32),
                 ("r_min", C.c_double), ("r_max", C.c_double), ("data", C.c_void_p),
-                ("store_dtype", C.c_int32), ("pad", C.c_int32)]
+                ("store_dtype", C.c_int32), ("pad", C.c_int32), ("extra", C.c_void_p)]
 
 
 class gc_inject_desc(C.Structure):

@@ -56,6 +56,8 @@ struct gc_ctx {
     void *field_buf = nullptr;
     FieldDev f{};
     FieldDev *f_dev = nullptr;        // device copy of f
+    FieldDev fx{};                    // the extra node array of the full Eqs. 1-2 (data NULL if none)
+    void *extra_buf = nullptr;
     // ensembles
     std::vector<EnsDev> ens_host;
     std::vector<char> ens_set;
@@ -319,12 +321,14 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     a.f = ctx->f;
     a.fdev = ctx->f_dev;
     a.ens = ctx->ens_dev;
-    a.ext = ctx->any_rebirth || ctx->any_wind ? 1 : 0;
+    a.fx = ctx->fx;
+    a.mode = ctx->fx.data ? 2 : (ctx->any_rebirth || ctx->any_wind ? 1 : 0);
     a.n_active = ctx->n_active;
     a.n_slots = (uint32_t)ctx->n;
     a.n_steps = steps;
     a.dt = dt;
-    const int form = ctx->opt.field_source == GC_SOURCE_MLP || ctx->opt.persistent ? 0 : push_form(ctx);
+    int form = ctx->opt.field_source == GC_SOURCE_MLP || ctx->opt.persistent ? 0 : push_form(ctx);
+    if (form == 2 && ctx->fx.data) form = 1;      // the full equations have no quad form
     a.steps_done = ctx->steps + form;
     a.log = ctx->log;
     a.log_depth = ctx->opt.log_depth;
@@ -388,6 +392,55 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
         return fail(ctx, GC_EINVAL, "rebirth is not supported with the neural field source");
     if (ctx->opt.field_source == GC_SOURCE_MLP && ctx->any_wind)
         return fail(ctx, GC_EINVAL, "wind-frame scattering is not supported with the neural field source");
+    if (ctx->opt.field_source == GC_SOURCE_MLP && ctx->fx.data)
+        return fail(ctx, GC_EINVAL, "the full GC terms are not supported with the neural field source");
+    return GC_OK;
+}
+
+// Stage a host [nodes][nc] node array (nc = 12, or 9 padded to 12 with zeros)
+// as float64 on the device and pack it into [nr][nth][nph+1][12] of the store
+// type; scale receives the FP16 per-component scales.  Waits.
+gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int nc, void **out, float scale[12]) {
+    hipStream_t s = ctx->stream;
+    const size_t nodes = (size_t)d->nr * d->nth * d->nph;
+    const size_t packed = (size_t)d->nr * d->nth * (d->nph + 1) * 12;
+    std::vector<double> conv;
+    const double *src = static_cast<const double *>(host);
+    if (d->src_dtype == GC_F32 || nc != 12) {
+        conv.assign(nodes * 12, 0.0);
+        for (size_t i = 0; i < nodes; ++i)
+            for (int c = 0; c < nc; ++c)
+                conv[i * 12 + c] = d->src_dtype == GC_F32 ? (double)static_cast<const float *>(host)[i * nc + c]
+                                                          : static_cast<const double *>(host)[i * nc + c];
+        src = conv.data();
+    }
+    float inv_scale[12];
+    for (int c = 0; c < 12; ++c) scale[c] = inv_scale[c] = 1.0f;
+    if (d->store_dtype == GC_F16) {
+        double mx[12] = {0};
+        for (size_t i = 0; i < nodes; ++i)
+            for (int c = 0; c < 12; ++c) mx[c] = std::max(mx[c], std::fabs(src[i * 12 + c]));
+        for (int c = 0; c < 12; ++c) {
+            if (!(mx[c] > 0.0) || !std::isfinite(mx[c])) continue;
+            const int e = (int)std::ceil(std::log2(mx[c])) - 14;   // max maps into (8192, 16384]
+            scale[c] = std::ldexp(1.0f, e);
+            inv_scale[c] = std::ldexp(1.0f, -e);
+        }
+    }
+    const size_t esz = d->store_dtype == GC_F64 ? 8 : (d->store_dtype == GC_F32 ? 4 : 2);
+    void *stage = nullptr, *buf = nullptr;
+    if (hipMalloc(&stage, nodes * 12 * 8 + 64) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot stage field");
+    if (hipMalloc(&buf, packed * esz) != hipSuccess) {
+        (void)hipFree(stage);
+        return fail(ctx, GC_ENOMEM, "cannot allocate field");
+    }
+    float *dscale = reinterpret_cast<float *>(static_cast<char *>(stage) + nodes * 12 * 8);
+    HIPCHK(hipMemcpyAsync(stage, src, nodes * 12 * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s));
+    HIPCHK(hipStreamSynchronize(s));
+    (void)hipFree(stage);
+    *out = buf;
     return GC_OK;
 }
 
@@ -474,6 +527,7 @@ void gc_destroy(gc_ctx *ctx) {
     if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);
     if (ctx->log) (void)hipFree(ctx->log);
     if (ctx->field_buf) (void)hipFree(ctx->field_buf);
+    if (ctx->extra_buf) (void)hipFree(ctx->extra_buf);
     if (ctx->mlp.mem) (void)hipFree(ctx->mlp.mem);
     if (ctx->mlp.ws) (void)hipFree(ctx->mlp.ws);
     if (ctx->ens_dev) (void)hipFree(ctx->ens_dev);
@@ -519,48 +573,25 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     if (!d->data) return fail(ctx, GC_EINVAL, "data is NULL");
     if (d->src_dtype != GC_F64 && d->src_dtype != GC_F32) return fail(ctx, GC_EINVAL, "src_dtype must be F64 or F32");
     if (d->store_dtype < GC_F64 || d->store_dtype > GC_F16) return fail(ctx, GC_EINVAL, "unknown store_dtype");
-    const size_t nodes = (size_t)d->nr * d->nth * d->nph;
     const size_t packed = (size_t)d->nr * d->nth * (d->nph + 1) * 12;
     if (packed >= 0xFFFFFFF0ull) return fail(ctx, GC_EINVAL, "grid too large for 32-bit offsets");
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = ctx->stream;
-    // stage as float64 on the device, then pack
-    std::vector<double> conv;
-    const double *src = static_cast<const double *>(d->data);
-    if (d->src_dtype == GC_F32) {
-        conv.resize(nodes * 12);
-        const float *fp = static_cast<const float *>(d->data);
-        for (size_t i = 0; i < nodes * 12; ++i) conv[i] = fp[i];
-        src = conv.data();
-    }
-    float scale[12], inv_scale[12];
-    for (int c = 0; c < 12; ++c) scale[c] = inv_scale[c] = 1.0f;
-    if (d->store_dtype == GC_F16) {
-        double mx[12] = {0};
-        for (size_t i = 0; i < nodes; ++i)
-            for (int c = 0; c < 12; ++c) mx[c] = std::max(mx[c], std::fabs(src[i * 12 + c]));
-        for (int c = 0; c < 12; ++c) {
-            if (!(mx[c] > 0.0) || !std::isfinite(mx[c])) continue;
-            const int e = (int)std::ceil(std::log2(mx[c])) - 14;   // max maps into (8192, 16384]
-            scale[c] = std::ldexp(1.0f, e);
-            inv_scale[c] = std::ldexp(1.0f, -e);
+    float scale[12], xscale[12];
+    void *buf = nullptr, *xbuf = nullptr;
+    gc_status st = pack_nodes(ctx, d, d->data, 12, &buf, scale);
+    if (st != GC_OK) return st;
+    if (d->extra) {
+        st = pack_nodes(ctx, d, d->extra, 9, &xbuf, xscale);
+        if (st != GC_OK) {
+            (void)hipFree(buf);
+            return st;
         }
     }
-    const size_t esz = d->store_dtype == GC_F64 ? 8 : (d->store_dtype == GC_F32 ? 4 : 2);
-    void *stage = nullptr, *buf = nullptr;
-    if (hipMalloc(&stage, nodes * 12 * 8 + 64) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot stage field");
-    if (hipMalloc(&buf, packed * esz) != hipSuccess) {
-        (void)hipFree(stage);
-        return fail(ctx, GC_ENOMEM, "cannot allocate field");
-    }
-    float *dscale = reinterpret_cast<float *>(static_cast<char *>(stage) + nodes * 12 * 8);
-    HIPCHK(hipMemcpyAsync(stage, src, nodes * 12 * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s));
-    HIPCHK(hipStreamSynchronize(s));
-    (void)hipFree(stage);
     if (ctx->field_buf) (void)hipFree(ctx->field_buf);
+    if (ctx->extra_buf) (void)hipFree(ctx->extra_buf);
     ctx->field_buf = buf;
+    ctx->extra_buf = xbuf;
     FieldDev &f = ctx->f;
     f.data = buf;
     f.nr = d->nr;
@@ -576,6 +607,10 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     f.th_lo = 0.5 * pi / d->nth;
     f.th_hi = pi - 0.5 * pi / d->nth;
     for (int c = 0; c < 12; ++c) f.scale[c] = scale[c];
+    ctx->fx = f;                      // same geometry, the extra node array (or none)
+    ctx->fx.data = xbuf;
+    if (xbuf)
+        for (int c = 0; c < 12; ++c) ctx->fx.scale[c] = xscale[c];
     HIPCHK(hipMemcpyAsync(ctx->f_dev, &ctx->f, sizeof(FieldDev), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     ctx->have_field = true;

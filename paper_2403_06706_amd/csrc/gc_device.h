@@ -283,10 +283,13 @@ __device__ __forceinline__ R sin_0_pi(R x) {
 //   du/dt = (q/m) E_par - (mu/gamma) b.grad B + gamma v_par v_E.(b.grad)b
 // drift-free form (only v_par b kept): dR/dt = v_par b, du/dt without the v_E term.
 // Output: coordinate rates (dr/dt, dth/dt, dph/dt, du/dt) and v_par.
+// kFull: the full Eqs. 1-2, x = (v_E.grad)b, (b.grad)v_E, (v_E.grad)v_E at the
+// point: v_par (x0..2 + x3..5) + x6..8 joins the bracket of dR/dt and
+// gamma v_E.x0..2 joins du/dt.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, bool kFull = false>
 __device__ __forceinline__ void gc_rhs(R r, R th, R u, R mu, R qm, R iqm, bool drift_free,
-                                       const R g[12], R F[4], R &vpar) {
+                                       const R g[12], R F[4], R &vpar, const R *x = nullptr) {
     const R Bx = g[0], By = g[1], Bz = g[2];
     const R Ex = g[3], Ey = g[4], Ez = g[5];
     const R Gx = g[6], Gy = g[7], Gz = g[8];
@@ -312,14 +315,20 @@ __device__ __forceinline__ void gc_rhs(R r, R th, R u, R mu, R qm, R iqm, bool d
         const R cG = mu * ig * ig;
         const R cE = qm * vpar * Epar * ig * (R)kInvC2;
         const R cK = vpar * vpar;
-        const R ax = cG * Gx + cE * vEx + cK * Kx;
-        const R ay = cG * Gy + cE * vEy + cK * Ky;
-        const R az = cG * Gz + cE * vEz + cK * Kz;
+        R ax = cG * Gx + cE * vEx + cK * Kx;
+        R ay = cG * Gy + cE * vEy + cK * Ky;
+        R az = cG * Gz + cE * vEz + cK * Kz;
+        if (kFull) {
+            ax += vpar * (x[0] + x[3]) + x[6];
+            ay += vpar * (x[1] + x[4]) + x[7];
+            az += vpar * (x[2] + x[5]) + x[8];
+        }
         const R pref = gamma * iqm * iB;
         Vx = vpar * bx + vEx + pref * (by * az - bz * ay);
         Vy = vpar * by + vEy + pref * (bz * ax - bx * az);
         Vz = vpar * bz + vEz + pref * (bx * ay - by * ax);
         udot = qm * Epar - mu * ig * bG + gamma * vpar * (vEx * Kx + vEy * Ky + vEz * Kz);
+        if (kFull) udot += gamma * (vEx * x[0] + vEy * x[1] + vEz * x[2]);
     }
     const R ir = rcp_nr(r);
     F[0] = Vx;

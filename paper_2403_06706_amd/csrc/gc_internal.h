@@ -56,6 +56,7 @@ constexpr int kNumU32Arrays = 8;
 struct PushArgs {
     SoA st;
     FieldDev f;
+    FieldDev fx;                   // full Eqs. 1-2: the extra node array (mode 2)
     const FieldDev *fdev;          // device copy of f (for the out-of-line rebirth)
     const EnsDev *ens;
     const uint32_t *n_active;      // device count of slots to visit
@@ -67,7 +68,7 @@ struct PushArgs {
     int32_t log_depth;
     int32_t tile;                  // persistent mode: particles per work item
     uint32_t *queue;               // persistent mode: next tile counter
-    int32_t ext;                   // some ensemble asks for rebirth or wind-frame scattering
+    int32_t mode;                  // 0 plain, 1 rebirth or wind-frame scattering, 2 also the full Eqs. 1-2
 };
 
 }  // namespace gc

@@ -21,11 +21,15 @@ namespace gc {
 //                    lane gl = 0 writes.
 enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 
-// EXT: some ensemble asks for rebirth or for scattering in the wind frame
-// (Sect. 3 and 3.3).  A separate instantiation, because the out-of-line
-// rebirth raises the register count of the FP32 forms.
-template <int PREC, int FDT, bool EXT, int FORM = kFormThroughput>
+// MODE 0: the reduced equations, no rebirth, centres at rest.  MODE 1: also
+// rebirth and scattering in the wind frame (Sect. 3 and 3.3); a separate
+// instantiation because the out-of-line rebirth raises the register count of
+// the FP32 forms.  MODE 2: also the full Eqs. 1-2 (a second gather of the
+// extra node array at each evaluation; no quad form).
+template <int PREC, int FDT, int MODE, int FORM = kFormThroughput>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
+    constexpr bool EXT = MODE >= 1;
+    constexpr bool FULL = MODE == 2;
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
     constexpr bool kKahan = PrecT<PREC>::kKahan;
@@ -97,7 +101,13 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
                     a.log[(size_t)st.gid[slot] * a.log_depth + (k - 1)] = step;
             }
             R F[4], vp;
-            gc_rhs<R>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp);
+            if (FULL) {
+                R x[12];
+                if (!gather<FDT, R, FORM == kFormAllPairs>(a.fx, px, pth, pph, x)) { bad = true; break; }
+                gc_rhs<R, true>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp, x);
+            } else {
+                gc_rhs<R>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp);
+            }
             if (stage == 2) {
                 Fs[0] = F[0]; Fs[1] = F[1]; Fs[2] = F[2]; Fs[3] = F[3];
                 vps = EXT ? path_speed<R>(vp, g, vw) : vp;
@@ -202,7 +212,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
 // gives each XCD a contiguous range of that prefix, so that (with cell-sorted
 // slots) its L2 holds the field cells of its own particles, and every XCD gets
 // an equal share however small the active prefix is.
-template <int PREC, int FDT, bool EXT, int FORM>
+template <int PREC, int FDT, int MODE, int FORM>
 __device__ __forceinline__ void push_grid(const PushArgs &a) {
     constexpr uint32_t G = FORM == kFormQuad ? 4 : 1;          // lanes per particle
     const uint32_t n = *a.n_active;
@@ -213,14 +223,14 @@ __device__ __forceinline__ void push_grid(const PushArgs &a) {
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
     const uint32_t slot = lb * per_block + threadIdx.x / G;
     uint32_t taken = 0;
-    if (slot < n) taken = advance_slot<PREC, FDT, EXT, FORM>(a, slot, threadIdx.x % G);
+    if (slot < n) taken = advance_slot<PREC, FDT, MODE, FORM>(a, slot, threadIdx.x % G);
     count_steps(a, taken);
 }
 
 // Throughput form: at most 256 registers per lane (two wavefronts per SIMD).
-template <int PREC, int FDT, bool EXT>
+template <int PREC, int FDT, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
-    push_grid<PREC, FDT, EXT, kFormThroughput>(a);
+    push_grid<PREC, FDT, MODE, kFormThroughput>(a);
 }
 
 // Latency forms, for fewer active particles than fill the machine: a
@@ -228,19 +238,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // and by how many distinct cache lines its load instructions touch.  The
 // all-pairs form has each gather in one round trip; the quad form also spreads
 // the particles over four times as many wavefronts (and compute units).
-template <int PREC, int FDT, bool EXT>
+template <int PREC, int FDT, int MODE>
 __global__ __launch_bounds__(256) void k_push_allpairs(PushArgs a) {
-    push_grid<PREC, FDT, EXT, kFormAllPairs>(a);
+    push_grid<PREC, FDT, MODE, kFormAllPairs>(a);
 }
 
-template <int PREC, int FDT, bool EXT>
+template <int PREC, int FDT, int MODE>
 __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
-    push_grid<PREC, FDT, EXT, kFormQuad>(a);
+    push_grid<PREC, FDT, MODE, kFormQuad>(a);
 }
 
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
 // atomic counter until the tiles run out (every workgroup reaches the exit).
-template <int PREC, int FDT, bool EXT>
+template <int PREC, int FDT, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
@@ -255,33 +265,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (t >= ntiles) break;
         const uint32_t end = min(n, (t + 1) * tile);
         for (uint32_t slot = t * tile + threadIdx.x; slot < end; slot += blockDim.x)
-            taken += advance_slot<PREC, FDT, EXT>(a, slot);
+            taken += advance_slot<PREC, FDT, MODE>(a, slot);
     }
     count_steps(a, taken);
 }
 
 
-template <int PREC, int FDT, bool EXT>
+template <int PREC, int FDT, int MODE>
 static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
     if (persistent) {
-        hipLaunchKernelGGL((k_push_persistent<PREC, FDT, EXT>), dim3(grid_blocks), dim3(block), 0, s, a);
+        hipLaunchKernelGGL((k_push_persistent<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), 0, s, a);
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;
-        if (form == kFormQuad)
-            hipLaunchKernelGGL((k_push_quad<PREC, FDT, EXT>), dim3(4 * nb), dim3(block), 0, s, a);
-        else if (form == kFormAllPairs)
-            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, EXT>), dim3(nb), dim3(block), 0, s, a);
+        if (form == kFormQuad && MODE != 2)
+            hipLaunchKernelGGL((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE>), dim3(4 * nb), dim3(block), 0, s, a);
+        else if (form != kFormThroughput)
+            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, MODE>), dim3(nb), dim3(block), 0, s, a);
         else
-            hipLaunchKernelGGL((k_push<PREC, FDT, EXT>), dim3(nb), dim3(block), 0, s, a);
+            hipLaunchKernelGGL((k_push<PREC, FDT, MODE>), dim3(nb), dim3(block), 0, s, a);
     }
     return hipGetLastError();
 }
 
 template <int PREC, int FDT>
 static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
-    return a.ext ? launch_r<PREC, FDT, true>(a, block, persistent, form, grid_blocks, s)
-                     : launch_r<PREC, FDT, false>(a, block, persistent, form, grid_blocks, s);
+    switch (a.mode) {
+        case 0: return launch_r<PREC, FDT, 0>(a, block, persistent, form, grid_blocks, s);
+        case 1: return launch_r<PREC, FDT, 1>(a, block, persistent, form, grid_blocks, s);
+        default: return launch_r<PREC, FDT, 2>(a, block, persistent, form, grid_blocks, s);
+    }
 }
 
 template <int PREC>

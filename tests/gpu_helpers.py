@@ -33,14 +33,14 @@ def say(msg):
 
 def run_gpu(wl, field, store_dtype="f64", precision="f64", order="bin", chunk=64, n_steps=None, dt=None,
             log_depth=0, block=256, persistent=False, tile=1024, coarsen=0, ensembles=None, graph=False,
-            tail_threshold=None):
+            tail_threshold=None, extra=None):
     import torch
     import paper_2403_06706_amd as gcp
     stream = torch.cuda.Stream() if graph else None
     ctx = gcp.Context(device=0, precision=precision, order=order, chunk_steps=chunk, log_depth=log_depth,
                       block_size=block, persistent=persistent, tile=tile, bin_coarsen=coarsen, stream=stream,
                       tail_threshold=tail_threshold)
-    ctx.load_field(wl.grid, field, store_dtype)
+    ctx.load_field(wl.grid, field, store_dtype, extra=extra)
     for e in (ensembles or wl.ensembles):
         ctx.inject(e)
     n = wl.n_steps if n_steps is None else n_steps
@@ -56,9 +56,9 @@ def run_gpu(wl, field, store_dtype="f64", precision="f64", order="bin", chunk=64
     return st, log
 
 
-def run_oracle(wl, field, n_steps=None, dt=None, ensembles=None, ids=None, log_depth=0, threads=0):
+def run_oracle(wl, field, n_steps=None, dt=None, ensembles=None, ids=None, log_depth=0, threads=0, extra=None):
     ens = ensembles or wl.ensembles
-    of = O.Field(wl.grid, field)
+    of = O.Field(wl.grid, field, extra=extra)
     tab = O.make_ens_table(ens)
     parts = []
     for i, e in enumerate(ens):
