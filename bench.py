@@ -120,12 +120,12 @@ def gather_ceiling(ctx, wl, store):
             "push_rate_same_state": push["rate"], "push_frac_of_gather_ceiling": push["rate"] / probe["rate"]}
 
 
-def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False, probe_ceiling=False):
+def run_gpu(args, wl, field, precision, steps, warmup, timing=True, probe=False, probe_ceiling=False, extra=None):
     import torch
     import paper_2403_06706_amd as gcp
     ctx = gcp.Context(device=0, precision=precision, order="bin", chunk_steps=64, block_size=args.block,
                       bin_coarsen=args.coarsen, persistent=args.persistent, tile=args.tile, timing=timing)
-    ctx.load_field(wl.grid, field, args.store)
+    ctx.load_field(wl.grid, field, args.store, extra=extra)
     for e in wl.ensembles:
         ctx.inject(e)
     start = {k: v.clone() for k, v in ctx.get_state().items()}
@@ -539,6 +539,8 @@ def main():
     ap.add_argument("--steady-hours", type=float, default=150.0)
     ap.add_argument("--steady-cpu-steps", type=int, default=20000)
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state summary of the default run")
+    ap.add_argument("--full-chunks", type=int, default=200,
+                    help="chunks of the paper-scale job timed with the full Eqs. 1-2 (0: skip)")
     ap.add_argument("--steady-wind", action="store_true",
                     help="steady-state job with scattering in the wind frame and only v_par b (Fig. 11 setting)")
     ap.add_argument("--mlp-particles", type=int, default=10 << 20)
@@ -638,6 +640,27 @@ def main():
                                "field_error_vs_grid_rms": nf["config"]["field_error_vs_grid_rms"],
                                "trajectory_difference_vs_grid": nf["trajectory_difference_vs_grid"],
                                "note": "full measurement: bench.py --workload mlp"}
+
+    if args.full_chunks > 0 and not args.probe_copy:
+        # the full Eqs. 1-2 (terms with derivatives of b and v_E) against the reduced form,
+        # over the first chunks of the same job
+        import numpy as np
+        from synthetic import fields
+        log("[bench] full-equation summary ...")
+        t0 = time.time()
+        extra = np.ascontiguousarray(fields.perturbed_parker_extra(wl.grid, device="cuda"))
+        log(f"[bench] extra node array built in {time.time() - t0:.1f} s")
+        el_f, cf, fin_f, _, _ = run_gpu(args, wl, field, args.precision, args.full_chunks, 1, extra=extra)
+        el_r, cr, fin_r, _, _ = run_gpu(args, wl, field, args.precision, args.full_chunks, 1)
+        act = (fin_f["status"] == 0) & (fin_r["status"] == 0)
+        dr = np.abs(fin_f["r"] - fin_r["r"])[act] / 1.495978707e11
+        out["full_equations"] = {
+            "chunks": args.full_chunks, "value": cf["particle_steps"] / el_f,
+            "reduced_same_chunks": cr["particle_steps"] / el_r,
+            "ratio": (cf["particle_steps"] / el_f) / (cr["particle_steps"] / el_r),
+            "r_difference_AU": {"median": float(np.median(dr)), "max": float(dr.max())} if act.any() else None}
+        log(f"[bench] full equations: {out['full_equations']['value']:.3e} particle-steps/s "
+            f"({out['full_equations']['ratio']:.2f} of the reduced form)")
 
     if not args.no_steady and not args.probe_copy:
         log("[bench] steady-state summary ...")
