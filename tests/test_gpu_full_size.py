@@ -1,0 +1,88 @@
+"""Parity at the benchmark sizes, in the launch configurations the benchmark
+times, on sampled particles the oracle advances one by one.
+
+* Paper scale: 2^20 electrons in three ensembles on the 256x128x256 FP32
+  perturbed-spiral field, FP64 state, cell binning every 64 steps, the tail
+  policy on; 2 h of 1 s steps.  64 sampled ids per ensemble.
+* Batched: 64 ensembles of uneven size, 4M electrons, the same field, the
+  graph-replayed persistent form with the tuned sizes; 2 h.  4 sampled ids per
+  ensemble.
+
+Bar: identical status, step and collision counts and relative errors <= 1e-6
+in position, u and mu_B for every sampled electron (the oracle reads the same
+FP32-rounded field)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2403_06706_amd as gcp
+from gpu_helpers import compare, say
+from synthetic import M_ELECTRON, workloads
+
+pytestmark = pytest.mark.gpu
+STEPS = 7200
+
+
+@pytest.fixture(scope="module")
+def field():
+    wl = workloads.config_paper_scale()
+    f = wl.build_field(wl.grid, device="cuda")
+    return np.ascontiguousarray(f.astype(np.float32).astype(np.float64))
+
+
+def _sample(st, wl, ids):
+    offs = np.cumsum([0] + [e.n for e in wl.ensembles])[:-1]
+    gsel = np.concatenate([offs[i] + ids[i] for i in range(len(ids))])
+    return {k: v[gsel] for k, v in st.items()}
+
+
+def _oracle(wl, f, ids, steps):
+    of = O.Field(wl.grid, f)
+    tab = O.make_ens_table(wl.ensembles)
+    p = np.concatenate([O.inject(of, tab, i, ids[i]) for i in range(len(wl.ensembles))])
+    O.advance(of, tab, p, wl.dt, steps)
+    return p
+
+
+def test_paper_scale_sampled_parity(field):
+    wl = workloads.config_paper_scale()
+    say(f"paper scale: {wl.n_particles} electrons, {STEPS} steps")
+    ctx = gcp.Context(device=0, precision="f64", order="bin", chunk_steps=64)
+    ctx.load_field(wl.grid, field, "f32")
+    for e in wl.ensembles:
+        ctx.inject(e)
+    ctx.advance(wl.dt, STEPS)
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    rng = np.random.default_rng(1)
+    ids = [np.sort(rng.choice(e.n, size=64, replace=False)).astype(np.uint32) for e in wl.ensembles]
+    p = _oracle(wl, field, ids, STEPS)
+    pos, u, mu = compare(_sample(st, wl, ids), p, M_ELECTRON, 1e-6, "paper-scale sample")
+    say(f"  sampled {len(p)}: max rel err pos {pos.max():.2e} u {u.max():.2e} mu {mu.max():.2e}; "
+        f"active {int((st['status'] == 0).sum())} of {len(st['status'])}")
+    assert (st["status"] == O.NONFINITE).sum() == 0
+    assert p["k"].sum() > 100 and (st["status"] == O.EXITED).sum() > 1000
+
+
+def test_batched_full_size_sampled_parity(field):
+    import torch
+    wl = workloads.config_batched()
+    say(f"batched: {wl.n_particles} electrons in {len(wl.ensembles)} ensembles, {STEPS} steps")
+    stream = torch.cuda.Stream()
+    ctx = gcp.Context(device=0, stream=stream, precision="f64", order="bin", chunk_steps=64, persistent=True,
+                      tile=512)
+    ctx.load_field(wl.grid, field, "f32")
+    for e in wl.ensembles:
+        ctx.inject(e)
+    with torch.cuda.stream(stream):
+        for _ in range(STEPS // 128):
+            ctx.advance_graph(wl.dt, 128)
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    rng = np.random.default_rng(2)
+    ids = [np.sort(rng.choice(e.n, size=4, replace=False)).astype(np.uint32) for e in wl.ensembles]
+    steps = (STEPS // 128) * 128
+    p = _oracle(wl, field, ids, steps)
+    pos, u, mu = compare(_sample(st, wl, ids), p, M_ELECTRON, 1e-6, "batched sample")
+    say(f"  sampled {len(p)}: max rel err pos {pos.max():.2e} u {u.max():.2e} mu {mu.max():.2e}")
+    assert (st["status"] == O.NONFINITE).sum() == 0
