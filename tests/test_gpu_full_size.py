@@ -7,10 +7,13 @@ times, on sampled particles the oracle advances one by one.
 * Batched: 64 ensembles of uneven size, 4M electrons, the same field, the
   graph-replayed persistent form with the tuned sizes; 2 h.  4 sampled ids per
   ensemble.
+* Network field: 10M electrons through the BF16 network for one 64-step chunk;
+  16 sampled ids against the oracle driven by the FP64 network.
 
 Bar: identical status, step and collision counts and relative errors <= 1e-6
 in position, u and mu_B for every sampled electron (the oracle reads the same
-FP32-rounded field)."""
+FP32-rounded field); for the network, positions within 1e-4 and u within 3e-4
+(BF16 weights and activations against FP64)."""
 import numpy as np
 import pytest
 
@@ -85,4 +88,47 @@ def test_batched_full_size_sampled_parity(field):
     p = _oracle(wl, field, ids, steps)
     pos, u, mu = compare(_sample(st, wl, ids), p, M_ELECTRON, 1e-6, "batched sample")
     say(f"  sampled {len(p)}: max rel err pos {pos.max():.2e} u {u.max():.2e} mu {mu.max():.2e}")
+    assert (st["status"] == O.NONFINITE).sum() == 0
+
+
+def test_network_push_full_size_sampled_parity():
+    """The network field source at the benchmark's size: 10M electrons, one
+    64-step chunk through the BF16 network; 16 sampled electrons advanced by
+    the oracle driven by the FP64 network (no scattering, so no decision can
+    flip): positions within 1e-4, u within 3e-4."""
+    from dataclasses import replace
+    from oracle import mlp_oracle as M
+    from gpu_helpers import field_of, rel_errors, small
+    from test_gpu_mlp import bf16_round
+    from synthetic import AU
+    wl = small(n=64, hours=0.1)
+    f = field_of(wl)
+    spec = M.make_spec(wl.grid, f, seed=1)
+    params = M.init_params(seed=2)
+    params["Wo"] = 0.3 * params["Wo"]
+    params["co"] = np.array([1.0, 0.3, -0.6, 0.2, 0.8, -0.4])
+    params = {k: bf16_round(v) for k, v in params.items()}
+    ens = replace(wl.ensembles[0], n=10 << 20, lambda_par=0.0, r_in=0.12 * AU, r_out=1.95 * AU)
+    say(f"network push: {ens.n} electrons, 64 steps")
+    ctx = gcp.Context(device=0, field_source="mlp", chunk_steps=64)
+    ctx.load_field(wl.grid, f, "f64")
+    ctx.mlp_set(spec.freq, spec.r_ref, spec.scale, spec.power, params)
+    ctx.inject(ens)
+    ctx.advance(1.0, 64)
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    rng = np.random.default_rng(3)
+    ids = np.sort(rng.choice(ens.n, size=16, replace=False)).astype(np.uint32)
+    tab = O.make_ens_table([ens])
+    p = O.inject(O.Field(wl.grid, f), tab, 0, ids)
+
+    def cb(r, th, ph):
+        return M.field(spec, params, np.array([r]), np.array([th]), np.array([ph]))[0]
+
+    O.advance(O.Field(wl.grid, callback=cb), tab, p, 1.0, 64, nthreads=1)
+    sub = {k: v[ids] for k, v in st.items()}
+    assert np.array_equal(sub["status"], p["status"]) and np.array_equal(sub["step"], p["step"])
+    pos, du, dmu = rel_errors(sub, p, ens.m)
+    say(f"  sampled 16: max position {pos.max():.2e}, u {du.max():.2e}")
+    assert pos.max() <= 1e-4 and du.max() <= 3e-4
     assert (st["status"] == O.NONFINITE).sum() == 0
