@@ -2,6 +2,8 @@
 // numbers, trilinear field gather, guiding-centre right-hand side.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
@@ -195,12 +197,64 @@ __device__ __forceinline__ Pair<FDT> quad_bcast_pair(const Pair<FDT> &mine) {
     return p;
 }
 
-// Four lanes of an aligned quad, one particle: lane gl loads node pair gl, the
-// quad shares the loaded words, and every lane adds the four pairs in the
-// one-lane order, so all four hold the bits of gather().  All four lanes must
+// A value of lane J of an aligned quad, to every lane of the quad.
+template <int J, typename R>
+__device__ __forceinline__ R quad_bcast_value(R x) {
+    static_assert(sizeof(R) % 4 == 0, "whole words");
+    uint32_t w[sizeof(R) / 4];
+    __builtin_memcpy(w, &x, sizeof w);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(R) / 4); ++i) w[i] = quad_bcast<J>(w[i]);
+    R y;
+    __builtin_memcpy(&y, w, sizeof w);
+    return y;
+}
+
+// Four lanes of an aligned quad, one particle (FP32 and FP64 fields): lane gl
+// loads components 3gl..3gl+2 of both nodes of the four node pairs, runs their
+// chains with the operations and order of gather_add, and the quad exchanges
+// the finished components, so all four lanes hold the bits of gather().  Each
+// lane converts and multiplies a quarter of the values.  All four lanes must
 // call it together.
 template <int FDT, typename R>
+__device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
+    using T = typename std::conditional<FDT == GC_F64, double, float>::type;
+    GatherPlan<R> gp;
+    if (!gather_plan(f, r, th, ph, gp)) return false;
+    const T *base = static_cast<const T *>(f.data) + 3 * gl;
+    T v[4][6];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[q][k] = base[gp.off[q] + k];              // node k of the pair
+            v[q][3 + k] = base[gp.off[q] + 12 + k];     // node k + 1
+        }
+    R acc[3] = {(R)0, (R)0, (R)0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const R wa = gp.w[q] * ((R)1 - gp.wp), wb = gp.w[q] * gp.wp;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[k] = fma(wb, (R)v[q][3 + k], fma(wa, (R)v[q][k], acc[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        out[k] = quad_bcast_value<0>(acc[k]);
+        out[3 + k] = quad_bcast_value<1>(acc[k]);
+        out[6 + k] = quad_bcast_value<2>(acc[k]);
+        out[9 + k] = quad_bcast_value<3>(acc[k]);
+    }
+    return finite12(out);
+}
+
+// Four lanes of an aligned quad, one particle: for FP32 and FP64 fields the
+// component split above; for FP16 fields lane gl loads node pair gl, the quad
+// shares the loaded words, and every lane adds the four pairs in the one-lane
+// order.  Either way all four lanes hold the bits of gather().  All four lanes
+// must call it together.
+template <int FDT, typename R>
 __device__ __forceinline__ bool gather_quad(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
+    if constexpr (FDT != GC_F16) return gather_quad_split<FDT, R>(f, r, th, ph, gl, out);
     GatherPlan<R> gp;
     if (!gather_plan(f, r, th, ph, gp)) return false;
     Pair<FDT> mine;
