@@ -20,8 +20,10 @@
  *     waiting, unless stated otherwise.
  *   - Units are SI.  Field vectors are in the local orthonormal spherical
  *     basis (r^, th^, ph^), right-handed.
- *   - The library owns the particle state and the packed field (device memory
- *     it allocates with hipMalloc).  Buffers passed in are owned by the caller.
+ *   - The library owns the particle state, the packed field and its scratch
+ *     buffers: device memory from the caller's allocator (gc_options.dev_alloc
+ *     / dev_free, e.g. a framework's caching allocator), else from hipMalloc.
+ *     Buffers passed in are owned by the caller.
  *   - Per-particle faults (leaving the shell, non-finite values) are particle
  *     status values, not errors.
  *   - One context must not be used from two host threads at once.
@@ -86,6 +88,14 @@ typedef struct {
                                latency form of the push (every field load of a gather in flight;
                                below a quarter of it, four lanes per particle); 0 disables.
                                Results are bitwise identical in every form. */
+    /* Device memory of the context: dev_alloc(bytes, user) returns device memory
+     * of that size or NULL, dev_free(ptr, user) releases it; both NULL: hipMalloc
+     * and hipFree.  Given together or not at all (GC_EINVAL); fixed at gc_create
+     * (gc_set_options keeps them).  The library synchronizes its stream before
+     * it releases memory its queued work may still use. */
+    void *(*dev_alloc)(size_t bytes, void *user);
+    void (*dev_free)(void *ptr, void *user);
+    void *alloc_user;
 } gc_options;
 
 enum { GC_SOURCE_GRID = 0, GC_SOURCE_MLP = 1 };

@@ -69,7 +69,9 @@ class Context:
     def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
                  bin_coarsen: int = 0, block_size: int = 256, persistent: bool = False, tile: int = 1024,
                  log_depth: int = 0, timing: bool = False, field_source: str = "grid", tail_threshold: Optional[int] = None,
-                 stream=None):
+                 stream=None, allocator: Optional[str] = None):
+        """allocator "torch": the context's device memory comes from torch's caching
+        allocator (on the context's stream) instead of hipMalloc."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the guiding-centre pusher runs only on the device")
@@ -91,6 +93,23 @@ class Context:
         o.field_source = _SOURCES[field_source]
         if tail_threshold is not None:
             o.tail_threshold = int(tail_threshold)
+        self._alloc_fns = None
+        if allocator == "torch":
+            stream_ = self._stream
+
+            def _alloc(nbytes, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(max(int(nbytes), 1), device=device, stream=stream_)
+                except RuntimeError:
+                    return None
+
+            def _free(ptr, _user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_fns = (_abi.DEV_ALLOC_FN(_alloc), _abi.DEV_FREE_FN(_free))
+            o.dev_alloc, o.dev_free = self._alloc_fns
+        elif allocator is not None:
+            raise ValueError(f"unknown allocator {allocator!r}")
         self._opt = o
         h = C.c_void_p()
         st = lib.gc_create(C.byref(h), C.byref(o))
@@ -110,8 +129,9 @@ class Context:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib.gc_destroy(self._h)
+            lib.gc_destroy(self._h)     # may call the allocator callbacks, kept alive until here
             self._h = None
+        self._alloc_fns = None
 
     def __del__(self):
         try:

@@ -15,12 +15,17 @@ GC_SOURCE_GRID, GC_SOURCE_MLP = 0, 1
 GC_MLP_PARAMS = 99846
 
 
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class gc_options(C.Structure):
     _fields_ = [("hip_stream", C.c_void_p), ("device", C.c_int32), ("precision", C.c_int32),
                 ("order", C.c_int32), ("chunk_steps", C.c_int32), ("bin_coarsen", C.c_int32),
                 ("block_size", C.c_int32), ("persistent", C.c_int32), ("tile", C.c_int32),
                 ("log_depth", C.c_int32), ("timing", C.c_int32), ("field_source", C.c_int32),
-                ("tail_threshold", C.c_int32)]
+                ("tail_threshold", C.c_int32), ("dev_alloc", DEV_ALLOC_FN), ("dev_free", DEV_FREE_FN),
+                ("alloc_user", C.c_void_p)]
 
 
 class gc_field_desc(C.Structure):

@@ -126,6 +126,7 @@ gc_status check_options(gc_ctx *ctx, const gc_options *o) {
     if (o->field_source != GC_SOURCE_GRID && o->field_source != GC_SOURCE_MLP)
         return fail(ctx, GC_EINVAL, "unknown field_source %d", o->field_source);
     if (o->tail_threshold < 0) return fail(ctx, GC_EINVAL, "tail_threshold must be >= 0");
+    if (!o->dev_alloc != !o->dev_free) return fail(ctx, GC_EINVAL, "dev_alloc and dev_free must be given together");
     return GC_OK;
 }
 
@@ -142,6 +143,22 @@ void carve(void *mem, uint64_t cap, SoA &s) {
 
 size_t soa_bytes(uint64_t cap) { return (size_t)cap * (kNumDoubleArrays * 8 + kNumU32Arrays * 4); }
 
+// Device memory of the context: the caller's allocator when one was given at
+// creation, else hipMalloc / hipFree.
+hipError_t dalloc(gc_ctx *ctx, void **p, size_t bytes) {
+    if (ctx->opt.dev_alloc) {
+        *p = ctx->opt.dev_alloc(bytes, ctx->opt.alloc_user);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+void dfree(gc_ctx *ctx, void *p) {
+    if (!p) return;
+    if (ctx->opt.dev_free) ctx->opt.dev_free(p, ctx->opt.alloc_user);
+    else (void)hipFree(p);
+}
+
 gc_status reserve(gc_ctx *ctx, uint64_t need) {
     if (need <= ctx->cap) return GC_OK;
     if (need > 0xFFFFFFF0ull) return fail(ctx, GC_EINVAL, "too many particles (%llu)", (unsigned long long)need);
@@ -149,8 +166,8 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     cap = (cap + 2047) & ~uint64_t(2047);
     void *m[2] = {nullptr, nullptr};
     for (int i = 0; i < 2; ++i)
-        if (hipMalloc(&m[i], soa_bytes(cap)) != hipSuccess) {
-            if (m[0]) (void)hipFree(m[0]);
+        if (dalloc(ctx, (void **)&m[i], soa_bytes(cap)) != hipSuccess) {
+            if (m[0]) dfree(ctx, m[0]);
             return fail(ctx, GC_ENOMEM, "cannot allocate particle state for %llu particles", (unsigned long long)cap);
         }
     SoA na{}, nb{};
@@ -159,17 +176,17 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     const uint32_t max_blocks = (uint32_t)((cap + kSortTile - 1) / kSortTile);
     const size_t scratch = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + (cap / 256 + 64) * 4;
     void *sm = nullptr;
-    if (hipMalloc(&sm, scratch) != hipSuccess) {
-        (void)hipFree(m[0]);
-        (void)hipFree(m[1]);
+    if (dalloc(ctx, (void **)&sm, scratch) != hipSuccess) {
+        dfree(ctx, m[0]);
+        dfree(ctx, m[1]);
         return fail(ctx, GC_ENOMEM, "cannot allocate sort scratch");
     }
     uint32_t *log = nullptr;
     if (ctx->opt.log_depth > 0 &&
-        hipMalloc(&log, (size_t)cap * ctx->opt.log_depth * sizeof(uint32_t)) != hipSuccess) {
-        (void)hipFree(m[0]);
-        (void)hipFree(m[1]);
-        (void)hipFree(sm);
+        dalloc(ctx, (void **)&log, (size_t)cap * ctx->opt.log_depth * sizeof(uint32_t)) != hipSuccess) {
+        dfree(ctx, m[0]);
+        dfree(ctx, m[1]);
+        dfree(ctx, sm);
         return fail(ctx, GC_ENOMEM, "cannot allocate collision log");
     }
     hipStream_t s = ctx->stream;
@@ -194,9 +211,9 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     }
     HIPCHK(hipStreamSynchronize(s));
     for (int i = 0; i < 2; ++i)
-        if (ctx->soa_mem[i]) (void)hipFree(ctx->soa_mem[i]);
-    if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);
-    if (ctx->log) (void)hipFree(ctx->log);
+        if (ctx->soa_mem[i]) dfree(ctx, ctx->soa_mem[i]);
+    if (ctx->scratch_mem) dfree(ctx, ctx->scratch_mem);
+    if (ctx->log) dfree(ctx, ctx->log);
     ctx->soa_mem[0] = m[0];
     ctx->soa_mem[1] = m[1];
     ctx->A = na;
@@ -429,9 +446,9 @@ gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int 
     }
     const size_t esz = d->store_dtype == GC_F64 ? 8 : (d->store_dtype == GC_F32 ? 4 : 2);
     void *stage = nullptr, *buf = nullptr;
-    if (hipMalloc(&stage, nodes * 12 * 8 + 64) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot stage field");
-    if (hipMalloc(&buf, packed * esz) != hipSuccess) {
-        (void)hipFree(stage);
+    if (dalloc(ctx, (void **)&stage, nodes * 12 * 8 + 64) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot stage field");
+    if (dalloc(ctx, (void **)&buf, packed * esz) != hipSuccess) {
+        dfree(ctx, stage);
         return fail(ctx, GC_ENOMEM, "cannot allocate field");
     }
     float *dscale = reinterpret_cast<float *>(static_cast<char *>(stage) + nodes * 12 * 8);
@@ -439,7 +456,7 @@ gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int 
     HIPCHK(hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s));
     HIPCHK(launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s));
     HIPCHK(hipStreamSynchronize(s));
-    (void)hipFree(stage);
+    dfree(ctx, stage);
     *out = buf;
     return GC_OK;
 }
@@ -489,10 +506,10 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     ctx->stream = static_cast<hipStream_t>(o.hip_stream);
     ctx->ens_host.assign(kMaxEnsembles, EnsDev{});
     ctx->ens_set.assign(kMaxEnsembles, 0);
-    HIPCHK(hipMalloc(&ctx->ens_dev, sizeof(EnsDev) * kMaxEnsembles));
-    HIPCHK(hipMalloc(&ctx->f_dev, sizeof(FieldDev)));
+    HIPCHK(dalloc(ctx, (void **)&ctx->ens_dev, sizeof(EnsDev) * kMaxEnsembles));
+    HIPCHK(dalloc(ctx, (void **)&ctx->f_dev, sizeof(FieldDev)));
     void *small = nullptr;
-    HIPCHK(hipMalloc(&small, 256));
+    HIPCHK(dalloc(ctx, (void **)&small, 256));
     ctx->n_active = static_cast<uint32_t *>(small);
     ctx->queue = ctx->n_active + 1;
     ctx->n_bound = ctx->n_active + 2;
@@ -523,16 +540,16 @@ void gc_destroy(gc_ctx *ctx) {
     for (hipEvent_t e : ctx->ahead)
         if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
-        if (ctx->soa_mem[i]) (void)hipFree(ctx->soa_mem[i]);
-    if (ctx->scratch_mem) (void)hipFree(ctx->scratch_mem);
-    if (ctx->log) (void)hipFree(ctx->log);
-    if (ctx->field_buf) (void)hipFree(ctx->field_buf);
-    if (ctx->extra_buf) (void)hipFree(ctx->extra_buf);
-    if (ctx->mlp.mem) (void)hipFree(ctx->mlp.mem);
-    if (ctx->mlp.ws) (void)hipFree(ctx->mlp.ws);
-    if (ctx->ens_dev) (void)hipFree(ctx->ens_dev);
-    if (ctx->f_dev) (void)hipFree(ctx->f_dev);
-    if (ctx->n_active) (void)hipFree(ctx->n_active);
+        if (ctx->soa_mem[i]) dfree(ctx, ctx->soa_mem[i]);
+    if (ctx->scratch_mem) dfree(ctx, ctx->scratch_mem);
+    if (ctx->log) dfree(ctx, ctx->log);
+    if (ctx->field_buf) dfree(ctx, ctx->field_buf);
+    if (ctx->extra_buf) dfree(ctx, ctx->extra_buf);
+    if (ctx->mlp.mem) dfree(ctx, ctx->mlp.mem);
+    if (ctx->mlp.ws) dfree(ctx, ctx->mlp.ws);
+    if (ctx->ens_dev) dfree(ctx, ctx->ens_dev);
+    if (ctx->f_dev) dfree(ctx, ctx->f_dev);
+    if (ctx->n_active) dfree(ctx, ctx->n_active);
     if (ctx->count_host) (void)hipHostFree(const_cast<uint32_t *>(ctx->count_host));
     delete ctx;
 }
@@ -542,6 +559,9 @@ const char *gc_last_error(const gc_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 gc_status gc_set_options(gc_ctx *ctx, const gc_options *opt) {
     if (!ctx || !opt) return GC_EINVAL;
     gc_options o = *opt;
+    o.dev_alloc = ctx->opt.dev_alloc;      // the allocator is fixed at creation
+    o.dev_free = ctx->opt.dev_free;
+    o.alloc_user = ctx->opt.alloc_user;
     if (o.log_depth != ctx->opt.log_depth) return fail(ctx, GC_EINVAL, "log_depth cannot change after creation");
     if (o.device != ctx->opt.device) return fail(ctx, GC_EINVAL, "device cannot change after creation");
     gc_status st = check_options(ctx, &o);
@@ -584,12 +604,12 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     if (d->extra) {
         st = pack_nodes(ctx, d, d->extra, 9, &xbuf, xscale);
         if (st != GC_OK) {
-            (void)hipFree(buf);
+            dfree(ctx, buf);
             return st;
         }
     }
-    if (ctx->field_buf) (void)hipFree(ctx->field_buf);
-    if (ctx->extra_buf) (void)hipFree(ctx->extra_buf);
+    if (ctx->field_buf) dfree(ctx, ctx->field_buf);
+    if (ctx->extra_buf) dfree(ctx, ctx->extra_buf);
     ctx->field_buf = buf;
     ctx->extra_buf = xbuf;
     FieldDev &f = ctx->f;
@@ -874,18 +894,23 @@ namespace {
 
 // Device copy of the whole state in global order, for the autotuner.
 struct Snapshot {
+    gc_ctx *ctx = nullptr;
     void *mem = nullptr;
     gc_state_view v{};
     uint64_t n = 0;
     ~Snapshot() {
-        if (mem) (void)hipFree(mem);
+        if (mem) {
+            (void)hipStreamSynchronize(ctx->stream);   // queued copies may still read it
+            dfree(ctx, mem);
+        }
     }
 };
 
 gc_status take_snapshot(gc_ctx *ctx, Snapshot &sn) {
+    sn.ctx = ctx;
     sn.n = ctx->n;
     const size_t bytes = (size_t)sn.n * (kNumDoubleArrays * 8 + 7 * 4) + 64;
-    if (hipMalloc(&sn.mem, bytes) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate tuning snapshot");
+    if (dalloc(ctx, (void **)&sn.mem, bytes) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate tuning snapshot");
     double *d = static_cast<double *>(sn.mem);
     double **dp[kNumDoubleArrays] = {&sn.v.r, &sn.v.th, &sn.v.ph, &sn.v.u, &sn.v.mu, &sn.v.fr, &sn.v.fth, &sn.v.fph,
                                      &sn.v.fu, &sn.v.dtp, &sn.v.s, &sn.v.ell, &sn.v.t, &sn.v.cr, &sn.v.cth, &sn.v.cph,
@@ -1075,9 +1100,9 @@ gc_status mlp_workspace(gc_ctx *ctx, int64_t rows) {
     size_t total = 0;
     for (size_t b : sz) total += b;
     void *mem = nullptr;
-    if (hipMalloc(&mem, total) != hipSuccess)
+    if (dalloc(ctx, (void **)&mem, total) != hipSuccess)
         return fail(ctx, GC_ENOMEM, "cannot allocate the training workspace for %lld rows", (long long)cap);
-    if (m.ws) (void)hipFree(m.ws);
+    if (m.ws) dfree(ctx, m.ws);
     m.ws = mem;
     m.ws_rows = cap;
     char *c = static_cast<char *>(mem);
@@ -1128,7 +1153,7 @@ gc_status gc_mlp_set(gc_ctx *ctx, const gc_mlp_desc *d) {
     const size_t total = 4 * fbytes + 3 * align256(nw * 2) + align256((size_t)kMlpOutPad * kMlpWidth * 2) +
                          align256((size_t)kMlpEvalRows * kMlpWidth * 2);
     if (!m.mem) {
-        if (hipMalloc(&m.mem, total) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate the network");
+        if (dalloc(ctx, (void **)&m.mem, total) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot allocate the network");
         char *c = static_cast<char *>(m.mem);
         m.p = reinterpret_cast<float *>(c); c += fbytes;
         m.mo = reinterpret_cast<float *>(c); c += fbytes;

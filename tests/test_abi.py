@@ -66,6 +66,14 @@ def test_host_side_errors_without_device():
     assert st == _abi.GC_EINVAL
     assert b"field_source" in lib.gc_last_error(h)
     lib.gc_destroy(h)
+    # an allocator needs both callbacks
+    o.field_source = 0
+    keep = _abi.DEV_ALLOC_FN(lambda n, user: None)
+    o.dev_alloc = keep
+    st = lib.gc_create(C.byref(h), C.byref(o))
+    assert st == _abi.GC_EINVAL
+    assert b"dev_alloc" in lib.gc_last_error(h)
+    lib.gc_destroy(h)
     assert lib.gc_mlp_eval(None, None, 0, None) == _abi.GC_EINVAL
     assert lib.gc_mlp_train_step(None, None, None, 1, None, None) == _abi.GC_EINVAL
 
