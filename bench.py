@@ -582,6 +582,7 @@ def main():
     algo_bytes = BYTES_PER_STEP[args.store] * steps_per_launch
     achieved = algo_bytes / avg_push_s / 1e9
     traffic = None
+    counters = None
     if os.path.exists(TRAFFIC_JSON):
         with open(TRAFFIC_JSON) as f:
             tj = json.load(f)
@@ -589,6 +590,11 @@ def main():
                 and tj.get("precision") == args.precision):
             # counters give HBM bytes per active particle-step of the push; scale to this run's launches
             traffic = round(tj["hbm_bytes_per_particle_step"] * steps_per_launch)
+            counters = {"hbm_GBps": round(traffic / avg_push_s / 1e9, 1),
+                        "hbm_frac_of_peak": round(traffic / avg_push_s / 1e9 / PEAK_HBM_GBS, 4),
+                        "l2_hit_rate": tj.get("l2_hit_rate"),
+                        "l2_requests_per_particle_step": tj.get("l2_requests_per_particle_step"),
+                        "source": "profiles/push_traffic.json (rocprofv3 FETCH_SIZE, WRITE_SIZE, TCC_HIT, TCC_MISS)"}
     tail = {}
     for i, name in ((1, "gc::k_push_allpairs"), (2, "gc::k_push_quad")):
         if c["form_launches"][i]:
@@ -600,7 +606,7 @@ def main():
                 "kernel": "gc::k_push", "avg_launch_ms": round(avg_push_s * 1e3, 4),
                 "launches": c["form_launches"][0], "algorithmic_bytes_per_launch": round(algo_bytes),
                 "bytes_per_particle_step": BYTES_PER_STEP[args.store],
-                "gather_ceiling": ceiling, "tail_forms": tail}
+                "gather_ceiling": ceiling, "tail_forms": tail, "hbm_l2_from_counters": counters}
 
     out = {
         "metric": "GC particle-steps/s on 1 MI355X at <=1e-4 rel err vs FP64 oracle",
