@@ -205,17 +205,24 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                     if (t > 0) {
                         // lane holds units 16u + 4g + jj (u = t - 1): slots 8g + 4(u&1) + jj of k block u/2
                         const int u = t - 1;
+                        // the four units side by side, one operation at a time, so that
+                        // the transcendental latencies of the units overlap
+                        float sg[4], h[4], ds[4];
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) sg[jj] = __expf(-prev[0][jj]);
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) sg[jj] = __builtin_amdgcn_rcpf(1.0f + sg[jj]);
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) h[jj] = prev[0][jj] * sg[jj];
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) ds[jj] = sg[jj] + h[jj] * (1.0f - sg[jj]);
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj) {
-                            const float z = prev[0][jj];
-                            const float sg = sigmoid_f(z);
-                            const float h = z * sg;
-                            const float ds = sg + h * (1.0f - sg);
                             const int s2 = u >> 1, i = (u & 1) * 4 + jj;
-                            Bn[s2][0][i] = (__bf16)h;
-                            Bn[s2][1][i] = (__bf16)(ds * prev[1][jj]);
-                            Bn[s2][2][i] = (__bf16)(ds * prev[2][jj]);
-                            Bn[s2][3][i] = (__bf16)(ds * prev[3][jj]);
+                            Bn[s2][0][i] = (__bf16)h[jj];
+                            Bn[s2][1][i] = (__bf16)(ds[jj] * prev[1][jj]);
+                            Bn[s2][2][i] = (__bf16)(ds[jj] * prev[2][jj]);
+                            Bn[s2][3][i] = (__bf16)(ds[jj] * prev[3][jj]);
                         }
                     }
 #pragma unroll
@@ -265,6 +272,17 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
     }
 }
 
+// x^p for the envelope: small whole exponents (the usual r^-1 and r^-2 falls)
+// by multiplication, others by pow.  The exponent is the same for every lane.
+template <typename R>
+__device__ __forceinline__ R env_pow(R x, R p) {
+    if (p == (R)1) return x;
+    if (p == (R)2) return x * x;
+    if (p == (R)3) return x * x * x;
+    if (p == (R)0) return (R)1;
+    return pow(x, p);
+}
+
 // Field components (B, E, grad|B|, (b.grad)b in the local basis) from the
 // network outputs at (r, th): envelope S_c (r_ref/r)^p_c, derivative chain rule,
 // metric factors and connection terms.  Returns false for a non-finite result.
@@ -274,7 +292,7 @@ __device__ __forceinline__ bool mlp_assemble(const MlpArgs &m, R r, R th, const 
     R env[kMlpOut], denv[kMlpOut];
 #pragma unroll
     for (int c = 0; c < kMlpOut; ++c) {
-        env[c] = (R)m.scale[c] * pow((R)m.r_ref / r, (R)m.power[c]);
+        env[c] = (R)m.scale[c] * env_pow((R)m.r_ref / r, (R)m.power[c]);
         denv[c] = -(R)m.power[c] * env[c] / r;
     }
     R B[3], dB[3][3];
