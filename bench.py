@@ -29,7 +29,8 @@ BYTES_PER_STEP = {"f32": 768, "f64": 1536, "f16": 384}     # 2 gathers x 8 nodes
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "push_traffic.json")
 KERNEL_SOURCES = ["paper_2403_06706_amd/csrc/gc_push.hip", "paper_2403_06706_amd/csrc/gc_step.h",
-                  "paper_2403_06706_amd/csrc/gc_device.h"]
+                  "paper_2403_06706_amd/csrc/gc_device.h", "paper_2403_06706_amd/csrc/gc_internal.h",
+                  "paper_2403_06706_amd/csrc/gc_kernels.hip"]
 
 
 def kernel_hash() -> str:

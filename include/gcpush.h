@@ -133,7 +133,9 @@ gc_status gc_get_options(const gc_ctx *ctx, gc_options *opt);
  *   makes a second gather at each evaluation and uses no quad form.  Not
  *   supported with the network field source (GC_EINVAL from gc_advance).
  * Errors: GC_EINVAL if nr < 2, nth < 2, nph < 2, r_min <= 0, r_max <= r_min,
- * data == NULL or a dtype is unknown.  Loading a new field keeps the particles. */
+ * data == NULL, a dtype is unknown, or the packed field exceeds 4 GiB (about
+ * nr nth (nph + 1) x 48 bytes for GC_F32, 96 for GC_F64, 24 for GC_F16; the
+ * gathers use 32-bit byte offsets).  Loading a new field keeps the particles. */
 typedef struct {
     int32_t nr, nth, nph;
     int32_t src_dtype;      /* GC_F64 or GC_F32 */

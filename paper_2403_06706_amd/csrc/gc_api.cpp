@@ -415,12 +415,13 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
 }
 
 // Stage a host [nodes][nc] node array (nc = 12, or 9 padded to 12 with zeros)
-// as float64 on the device and pack it into [nr][nth][nph+1][12] of the store
-// type; scale receives the FP16 per-component scales.  Waits.
+// as float64 on the device and pack it into the gathers' blocked layout
+// (field_layout, store type); scale receives the FP16 per-component scales.
+// Waits.
 gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int nc, void **out, float scale[12]) {
     hipStream_t s = ctx->stream;
     const size_t nodes = (size_t)d->nr * d->nth * d->nph;
-    const size_t packed = (size_t)d->nr * d->nth * (d->nph + 1) * 12;
+    const size_t packed = (size_t)field_layout(d->nr, d->nth, d->nph, d->store_dtype).total;
     std::vector<double> conv;
     const double *src = static_cast<const double *>(host);
     if (d->src_dtype == GC_F32 || nc != 12) {
@@ -593,8 +594,11 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     if (!d->data) return fail(ctx, GC_EINVAL, "data is NULL");
     if (d->src_dtype != GC_F64 && d->src_dtype != GC_F32) return fail(ctx, GC_EINVAL, "src_dtype must be F64 or F32");
     if (d->store_dtype < GC_F64 || d->store_dtype > GC_F16) return fail(ctx, GC_EINVAL, "unknown store_dtype");
-    const size_t packed = (size_t)d->nr * d->nth * (d->nph + 1) * 12;
-    if (packed >= 0xFFFFFFF0ull) return fail(ctx, GC_EINVAL, "grid too large for 32-bit offsets");
+    const FieldLayout lay = field_layout(d->nr, d->nth, d->nph, d->store_dtype);
+    const uint64_t esz = d->store_dtype == GC_F64 ? 8 : (d->store_dtype == GC_F32 ? 4 : 2);
+    if ((uint64_t)d->nr * d->nth * d->nph > 0x7FFFFFFFull || lay.total * esz > 0xFFFFFFFFull)
+        return fail(ctx, GC_EINVAL, "packed field larger than 4 GiB (%llu bytes; 32-bit load offsets)",
+                    (unsigned long long)(lay.total * esz));
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = ctx->stream;
     float scale[12], xscale[12];
@@ -627,6 +631,9 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     f.th_lo = 0.5 * pi / d->nth;
     f.th_hi = pi - 0.5 * pi / d->nth;
     for (int c = 0; c < 12; ++c) f.scale[c] = scale[c];
+    f.cs = lay.cs;
+    f.ks = lay.ks;
+    f.js = lay.js;
     ctx->fx = f;                      // same geometry, the extra node array (or none)
     ctx->fx.data = xbuf;
     if (xbuf)

@@ -48,19 +48,32 @@ enum : uint64_t { kPurposePath = 0, kPurposeInject = 1 };
 // stencil is clamped to the grid in floating point before any conversion to
 // an integer, so every load stays inside the buffer for any input.
 // Returns false if the input or any interpolated value is not finite.
+//
+// The packed layout (chunks of W components, 4 x 2 node blocks) is described
+// with field_layout in gc_internal.h.  Loads address the field as its base
+// (uniform, or plus a uniform chunk offset) and a 32-bit byte offset per lane,
+// the form of the SGPR-base global load; the packed field is at most 4 GiB.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ R clampr(R x, R lo, R hi) { return fmin(fmax(x, lo), hi); }
 
+// Chunk width and count per node of each storage type (as field_layout).
+template <int FDT> struct Layout { static constexpr uint32_t W = 4, nch = 3; };   // FP32, FP16
+template <> struct Layout<GC_F64> { static constexpr uint32_t W = 2, nch = 6; };
+
 template <int FDT> struct Pair;   // 24 values of two phi-adjacent nodes, 12 components each
 
+// Each load(): off = element offset of chunk 0 of the pair's first node, dk =
+// offset of the second node from the first, cs = element stride between
+// chunks; chunk c of node h is at off + h dk + c cs.
 template <> struct Pair<GC_F32> {
     float v[24];
-    __device__ __forceinline__ void load(const void *base, uint32_t off) {
-        const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(base) + off);
+    __device__ __forceinline__ void load(const void *base, uint32_t off, uint32_t dk, uint32_t cs) {
+        const char *b = static_cast<const char *>(base);
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            float4 x = p[q];
+            const float4 x = *reinterpret_cast<const float4 *>(b + (size_t)((q % 3) * cs) * 4u +
+                                                               (off + (q / 3) * dk) * 4u);
             v[4 * q + 0] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
         }
     }
@@ -69,11 +82,12 @@ template <> struct Pair<GC_F32> {
 
 template <> struct Pair<GC_F64> {
     double v[24];
-    __device__ __forceinline__ void load(const void *base, uint32_t off) {
-        const double2 *p = reinterpret_cast<const double2 *>(static_cast<const double *>(base) + off);
+    __device__ __forceinline__ void load(const void *base, uint32_t off, uint32_t dk, uint32_t cs) {
+        const char *b = static_cast<const char *>(base);
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
-            double2 x = p[q];
+            const double2 x = *reinterpret_cast<const double2 *>(b + (size_t)((q % 6) * cs) * 8u +
+                                                                (off + (q / 6) * dk) * 8u);
             v[2 * q + 0] = x.x; v[2 * q + 1] = x.y;
         }
     }
@@ -82,11 +96,12 @@ template <> struct Pair<GC_F64> {
 
 template <> struct Pair<GC_F16> {
     __half v[24];
-    __device__ __forceinline__ void load(const void *base, uint32_t off) {
-        const uint2 *p = reinterpret_cast<const uint2 *>(static_cast<const __half *>(base) + off);
+    __device__ __forceinline__ void load(const void *base, uint32_t off, uint32_t dk, uint32_t cs) {
+        const char *b = static_cast<const char *>(base);
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            uint2 x = p[q];
+            const uint2 x = *reinterpret_cast<const uint2 *>(b + (size_t)((q % 3) * cs) * 2u +
+                                                             (off + (q / 3) * dk) * 2u);
             __half h[4];
             __builtin_memcpy(h, &x, 8);
             v[4 * q + 0] = h[0]; v[4 * q + 1] = h[1]; v[4 * q + 2] = h[2]; v[4 * q + 3] = h[3];
@@ -103,10 +118,12 @@ template <typename R>
 struct GatherPlan {
     R w[4];              // (r, theta) weight of each node pair
     R wp;                // phi weight of the second node of a pair
-    uint32_t off[4];     // element offset of each pair in the packed field
+    uint32_t off[4];     // element offset of chunk 0 of each pair's first node
+    uint32_t dk;         // offset of a pair's second (phi) node from its first
+    uint32_t cs;         // element stride between chunks
 };
 
-template <typename R>
+template <int FDT, typename R>
 __device__ __forceinline__ bool gather_plan(const FieldDev &f, R r, R th, R ph, GatherPlan<R> &gp) {
     R x = (r - (R)f.r_min) * (R)f.inv_dr;
     R y = th * (R)f.inv_dth - (R)0.5;
@@ -124,17 +141,23 @@ __device__ __forceinline__ bool gather_plan(const FieldDev &f, R r, R th, R ph, 
     km = km >= nph ? km - nph : km;
     km = clampr(km, (R)0, nph - (R)1);
     const uint32_t i = (uint32_t)fi, j = (uint32_t)fj, k = (uint32_t)km;
-    const uint32_t row = (uint32_t)(f.nph + 1) * 12u;
-    const uint32_t o00 = (i * (uint32_t)f.nth + j) * row + k * 12u;
-    const uint32_t dI = (uint32_t)f.nth * row;
+    constexpr uint32_t W = Layout<FDT>::W;
+    // separable offsets of the blocked layout (field_layout)
+    const uint32_t i1 = i + 1u;
+    const uint32_t gi0 = (i >> 2) * (kLayB * W) + (i & 3u) * W;
+    const uint32_t gi1 = (i1 >> 2) * (kLayB * W) + (i1 & 3u) * W;
+    const uint32_t gk0 = (k >> 1) * f.ks + (k & 1u) * (kLayBr * W);
+    gp.dk = (k & 1u) ? f.ks - kLayBr * W : kLayBr * W;          // gK(k + 1) - gK(k)
+    const uint32_t gj0 = j * f.js;
+    gp.cs = f.cs;
     gp.w[0] = ((R)1 - wr) * ((R)1 - wt);
     gp.w[1] = ((R)1 - wr) * wt;
     gp.w[2] = wr * ((R)1 - wt);
     gp.w[3] = wr * wt;
-    gp.off[0] = o00;
-    gp.off[1] = o00 + row;
-    gp.off[2] = o00 + dI;
-    gp.off[3] = o00 + dI + row;
+    gp.off[0] = gj0 + gk0 + gi0;
+    gp.off[1] = gj0 + f.js + gk0 + gi0;
+    gp.off[2] = gj0 + gk0 + gi1;
+    gp.off[3] = gj0 + f.js + gk0 + gi1;
     return true;
 }
 
@@ -164,13 +187,13 @@ __device__ __forceinline__ bool finite12(const R out[12]) {
 template <int FDT, typename R, bool kAllPairs = false>
 __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
     GatherPlan<R> gp;
-    if (!gather_plan(f, r, th, ph, gp)) return false;
+    if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = (R)0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         Pair<FDT> p;
-        p.load(f.data, gp.off[q]);
+        p.load(f.data, gp.off[q], gp.dk, gp.cs);
         gather_add<FDT, R>(f, gp, q, p, out);
         if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
     }
@@ -211,38 +234,49 @@ __device__ __forceinline__ R quad_bcast_value(R x) {
 }
 
 // Four lanes of an aligned quad, one particle (FP32 and FP64 fields): lane gl
-// loads components 3gl..3gl+2 of both nodes of the four node pairs, runs their
-// chains with the operations and order of gather_add, and the quad exchanges
-// the finished components, so all four lanes hold the bits of gather().  Each
-// lane converts and multiplies a quarter of the values.  All four lanes must
-// call it together.
+// (0-2) loads components 4gl..4gl+3 of both nodes of the four node pairs (one
+// chunk of FP32, two of FP64), runs their chains with the operations and order
+// of gather_add, and the quad exchanges the finished components, so all four
+// lanes hold the bits of gather().  Lane 3 repeats lane 2's loads (the same
+// cache lines) and its chains are not used.  All four lanes must call it
+// together.
 template <int FDT, typename R>
 __device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
     using T = typename std::conditional<FDT == GC_F64, double, float>::type;
+    constexpr uint32_t W = Layout<FDT>::W, kPer = 4 / W;
     GatherPlan<R> gp;
-    if (!gather_plan(f, r, th, ph, gp)) return false;
-    const T *base = static_cast<const T *>(f.data) + 3 * gl;
-    T v[4][6];
+    if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
+    const uint32_t lc = gl < 3u ? gl : 2u;
+    const uint32_t lo = lc * kPer * gp.cs;
+    const char *base = static_cast<const char *>(f.data);
+    T v[4][8];     // [pair][4 h + e]: component 4 lc + e of node h
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            v[q][k] = base[gp.off[q] + k];              // node k of the pair
-            v[q][3 + k] = base[gp.off[q] + 12 + k];     // node k + 1
-        }
-    R acc[3] = {(R)0, (R)0, (R)0};
+        for (uint32_t h = 0; h < 2; ++h)
+#pragma unroll
+            for (uint32_t m = 0; m < kPer; ++m) {
+                const uint32_t o = gp.off[q] + h * gp.dk + lo + m * gp.cs;
+                if constexpr (W == 4) {
+                    const float4 x = *reinterpret_cast<const float4 *>(base + o * 4u);
+                    v[q][4 * h + 0] = x.x; v[q][4 * h + 1] = x.y; v[q][4 * h + 2] = x.z; v[q][4 * h + 3] = x.w;
+                } else {
+                    const double2 x = *reinterpret_cast<const double2 *>(base + o * 8u);
+                    v[q][4 * h + 2 * m + 0] = x.x; v[q][4 * h + 2 * m + 1] = x.y;
+                }
+            }
+    R acc[4] = {(R)0, (R)0, (R)0, (R)0};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const R wa = gp.w[q] * ((R)1 - gp.wp), wb = gp.w[q] * gp.wp;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) acc[k] = fma(wb, (R)v[q][3 + k], fma(wa, (R)v[q][k], acc[k]));
+        for (int e = 0; e < 4; ++e) acc[e] = fma(wb, (R)v[q][4 + e], fma(wa, (R)v[q][e], acc[e]));
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        out[k] = quad_bcast_value<0>(acc[k]);
-        out[3 + k] = quad_bcast_value<1>(acc[k]);
-        out[6 + k] = quad_bcast_value<2>(acc[k]);
-        out[9 + k] = quad_bcast_value<3>(acc[k]);
+    for (int e = 0; e < 4; ++e) {
+        out[e] = quad_bcast_value<0>(acc[e]);
+        out[4 + e] = quad_bcast_value<1>(acc[e]);
+        out[8 + e] = quad_bcast_value<2>(acc[e]);
     }
     return finite12(out);
 }
@@ -256,9 +290,9 @@ template <int FDT, typename R>
 __device__ __forceinline__ bool gather_quad(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
     if constexpr (FDT != GC_F16) return gather_quad_split<FDT, R>(f, r, th, ph, gl, out);
     GatherPlan<R> gp;
-    if (!gather_plan(f, r, th, ph, gp)) return false;
+    if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
     Pair<FDT> mine;
-    mine.load(f.data, gp.off[gl]);
+    mine.load(f.data, gp.off[gl], gp.dk, gp.cs);
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = (R)0;
     gather_add<FDT, R>(f, gp, 0, quad_bcast_pair<FDT, 0>(mine), out);

@@ -31,8 +31,41 @@ struct EnsDev {
     double v_wind;          // > 0: scattering centres move with a radial wind of this speed (m/s)
 };
 
-// Packed field on the device: [nr][nth][nph+1][12], the extra phi node repeats
-// node 0 so that every phi pair (k, k+1) is contiguous.
+// Packed field on the device.  nph + 1 phi nodes (the last repeats node 0, so
+// a phi pair (k, k+1) needs no wrap).  The 12 components of a node are cut in
+// nch chunks of W consecutive components, one load each (16 bytes for FP32
+// and FP64, 8 for FP16).  Nodes are grouped in blocks of 4 (r) x 2 (phi);
+// one chunk of a block's 8 nodes is contiguous (one 128-byte line for FP32
+// and FP64), and blocks follow one another along r, then the chunk index,
+// then phi, then theta.  Chunk c of node (i, j, k) is at element
+//   gI(i) + gK(k) + gJ(j) + c cs,
+//   gI(i) = (i >> 2) 8 W + (i & 3) W,
+//   gK(k) = (k >> 1) ks + (k & 1) 4 W,   ks = nch cs,
+//   gJ(j) = j js,                        js = nK ks,
+// with cs = nI 8 W, nI = ceil(nr / 4), nK = ceil((nph + 1) / 2); padding
+// nodes hold zeros.  A cell-sorted wavefront spreads along the field, mostly
+// in r and phi; in this order lanes at nearby nodes share the cache line of
+// each load.
+constexpr uint32_t kLayBr = 4, kLayBk = 2, kLayB = kLayBr * kLayBk;   // nodes per block (r, phi)
+
+struct FieldLayout {
+    uint32_t W, nch;      // components per chunk, chunks per node
+    uint32_t cs, ks, js;  // element strides: chunk, phi block, theta row
+    uint64_t total;       // elements, padding included
+};
+
+__host__ __device__ inline FieldLayout field_layout(int nr, int nth, int nph, int dtype) {
+    FieldLayout L;
+    L.W = dtype == GC_F64 ? 2u : 4u;
+    L.nch = 12u / L.W;
+    const uint32_t nI = ((uint32_t)nr + kLayBr - 1) / kLayBr, nK = ((uint32_t)nph + 1 + kLayBk - 1) / kLayBk;
+    L.cs = nI * kLayB * L.W;
+    L.ks = L.nch * L.cs;
+    L.js = nK * L.ks;
+    L.total = (uint64_t)nth * L.js;
+    return L;
+}
+
 struct FieldDev {
     const void *data;
     int32_t nr, nth, nph, dtype;
@@ -40,6 +73,7 @@ struct FieldDev {
     double inv_dr, inv_dth, inv_dph, inv_nph;
     double th_lo, th_hi;  // first and last theta node (exit bounds)
     float scale[12];      // GC_F16: stored value * scale = field value
+    uint32_t cs, ks, js;  // layout strides (field_layout)
 };
 
 // Structure-of-arrays particle state (one slot per particle).

@@ -10,22 +10,35 @@
 namespace gc {
 
 // ---------------------------------------------------------------------------
-// Field packing: [nr][nth][nph][12] float64 (staged on the device) ->
-// [nr][nth][nph+1][12] in the storage type, the extra phi node repeating node 0.
+// Field packing: [nr][nth][nph][12] float64 (staged on the device) -> the
+// blocked layout of field_layout in the storage type, the extra phi node
+// k = nph repeating node 0, padding nodes zero.
 // ---------------------------------------------------------------------------
 __global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
                              const float *inv_scale_in) {
-    const size_t total = (size_t)nr * nth * (nph + 1) * 12;
-    for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total; o += (size_t)gridDim.x * blockDim.x) {
-        const int c = (int)(o % 12);
-        size_t node = o / 12;
-        const int k = (int)(node % (nph + 1));
-        const size_t ij = node / (nph + 1);
-        const size_t si = (ij * nph + (k == nph ? 0 : k)) * 12 + c;
-        const double v = src[si];
+    const FieldLayout L = field_layout(nr, nth, nph, dtype);
+    const uint64_t nI = L.cs / (kLayB * L.W), nK = L.js / L.ks;
+    for (uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; o < L.total;
+         o += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t t = o / L.W;
+        const uint64_t e = o % L.W;
+        const uint64_t ii = t % kLayBr;
+        t /= kLayBr;
+        const uint64_t kk = t % kLayBk;
+        t /= kLayBk;
+        const uint64_t I = t % nI;
+        t /= nI;
+        const uint64_t c = t % L.nch;
+        t /= L.nch;
+        const uint64_t K = t % nK, j = t / nK;
+        const uint64_t i = I * kLayBr + ii, k = K * kLayBk + kk;
+        const int comp = (int)(c * L.W + e);
+        double v = 0.0;
+        if (i < (uint64_t)nr && k <= (uint64_t)nph)
+            v = src[((i * nth + j) * nph + (k == (uint64_t)nph ? 0 : k)) * 12 + comp];
         if (dtype == GC_F64) static_cast<double *>(dst)[o] = v;
         else if (dtype == GC_F32) static_cast<float *>(dst)[o] = (float)v;
-        else static_cast<__half *>(dst)[o] = __float2half((float)(v * (double)inv_scale_in[c]));
+        else static_cast<__half *>(dst)[o] = __float2half((float)(v * (double)inv_scale_in[comp]));
     }
 }
 

@@ -102,14 +102,14 @@ __device__ __forceinline__ BirthState birth_state(const FieldDev &f, const EnsDe
         // runs out of line, and its register count bounds the caller's)
         double g[12];
         GatherPlan<double> gp;
-        bool ok = gather_plan(f, b.r, b.th, b.ph, gp);
+        bool ok = gather_plan<FDT>(f, b.r, b.th, b.ph, gp);
         if (ok) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) g[c] = 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 Pair<FDT> p;
-                p.load(f.data, gp.off[q]);
+                p.load(f.data, gp.off[q], gp.dk, gp.cs);
                 gather_add<FDT, double>(f, gp, q, p, g);
                 __builtin_amdgcn_sched_barrier(0);
             }
