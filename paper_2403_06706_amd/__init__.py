@@ -183,6 +183,9 @@ class Context:
         arr = np.ascontiguousarray(data)
         if arr.dtype not in (np.float64, np.float32):
             raise TypeError("field data must be float64 or float32")
+        if arr.size != grid.nr * grid.nth * grid.nph * 12:
+            raise ValueError(f"field data must hold [nr][nth][nph][12] = {grid.nr * grid.nth * grid.nph * 12} values "
+                             f"(got {arr.size})")
         xp = None
         if extra is not None:
             xarr = np.ascontiguousarray(extra, dtype=arr.dtype)

@@ -190,7 +190,23 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
         return fail(ctx, GC_ENOMEM, "cannot allocate collision log");
     }
     hipStream_t s = ctx->stream;
-    if (log) HIPCHK(launch_fill_u32(log, 0xFFFFFFFFu, (size_t)cap * ctx->opt.log_depth, s));
+    // a failing device call releases the new buffers (the old state stays)
+    auto release_new = [&]() {
+        (void)hipStreamSynchronize(s);
+        dfree(ctx, m[0]);
+        dfree(ctx, m[1]);
+        dfree(ctx, sm);
+        dfree(ctx, log);
+    };
+#define RESERVE_CHK(expr)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess) {                                                                        \
+            release_new();                                                                             \
+            return fail(ctx, GC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));                      \
+        }                                                                                              \
+    } while (0)
+    if (log) RESERVE_CHK(launch_fill_u32(log, 0xFFFFFFFFu, (size_t)cap * ctx->opt.log_depth, s));
     if (ctx->n > 0) {
         // keep the current state (and log) of the first n slots
         double **src_d[kNumDoubleArrays] = {&ctx->A.r, &ctx->A.th, &ctx->A.ph, &ctx->A.u, &ctx->A.mu, &ctx->A.fr,
@@ -199,17 +215,18 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
         double **dst_d[kNumDoubleArrays] = {&na.r, &na.th, &na.ph, &na.u, &na.mu, &na.fr, &na.fth, &na.fph, &na.fu,
                                             &na.dtp, &na.s, &na.ell, &na.t, &na.cr, &na.cth, &na.cph, &na.cu, &na.ct};
         for (int i = 0; i < kNumDoubleArrays; ++i)
-            HIPCHK(hipMemcpyAsync(*dst_d[i], *src_d[i], ctx->n * 8, hipMemcpyDeviceToDevice, s));
+            RESERVE_CHK(hipMemcpyAsync(*dst_d[i], *src_d[i], ctx->n * 8, hipMemcpyDeviceToDevice, s));
         uint32_t **src_u[kNumU32Arrays] = {&ctx->A.k, &ctx->A.flags, &ctx->A.status, &ctx->A.step,
                                            &ctx->A.id, &ctx->A.ens, &ctx->A.gid, &ctx->A.birth};
         uint32_t **dst_u[kNumU32Arrays] = {&na.k, &na.flags, &na.status, &na.step, &na.id, &na.ens, &na.gid,
                                            &na.birth};
         for (int i = 0; i < kNumU32Arrays; ++i)
-            HIPCHK(hipMemcpyAsync(*dst_u[i], *src_u[i], ctx->n * 4, hipMemcpyDeviceToDevice, s));
+            RESERVE_CHK(hipMemcpyAsync(*dst_u[i], *src_u[i], ctx->n * 4, hipMemcpyDeviceToDevice, s));
         if (log && ctx->log)
-            HIPCHK(hipMemcpyAsync(log, ctx->log, ctx->n * ctx->opt.log_depth * 4, hipMemcpyDeviceToDevice, s));
+            RESERVE_CHK(hipMemcpyAsync(log, ctx->log, ctx->n * ctx->opt.log_depth * 4, hipMemcpyDeviceToDevice, s));
     }
-    HIPCHK(hipStreamSynchronize(s));
+    RESERVE_CHK(hipStreamSynchronize(s));
+#undef RESERVE_CHK
     for (int i = 0; i < 2; ++i)
         if (ctx->soa_mem[i]) dfree(ctx, ctx->soa_mem[i]);
     if (ctx->scratch_mem) dfree(ctx, ctx->scratch_mem);
@@ -453,11 +470,17 @@ gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int 
         return fail(ctx, GC_ENOMEM, "cannot allocate field");
     }
     float *dscale = reinterpret_cast<float *>(static_cast<char *>(stage) + nodes * 12 * 8);
-    HIPCHK(hipMemcpyAsync(stage, src, nodes * 12 * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s));
-    HIPCHK(launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s));
-    HIPCHK(hipStreamSynchronize(s));
+    hipError_t e = hipMemcpyAsync(stage, src, nodes * 12 * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
     dfree(ctx, stage);
+    if (e != hipSuccess) {
+        dfree(ctx, buf);
+        return fail(ctx, GC_EDEVICE, "field packing: %s", hipGetErrorString(e));
+    }
     *out = buf;
     return GC_OK;
 }
@@ -478,7 +501,7 @@ void gc_default_options(gc_options *o) {
     o->log_depth = 0;
     o->timing = 0;
     o->field_source = GC_SOURCE_GRID;
-    o->tail_threshold = 65536;
+    o->tail_threshold = 131072;
 }
 
 gc_status gc_create(gc_ctx **out, const gc_options *opt) {

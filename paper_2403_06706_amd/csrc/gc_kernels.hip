@@ -12,7 +12,8 @@ namespace gc {
 // ---------------------------------------------------------------------------
 // Field packing: [nr][nth][nph][12] float64 (staged on the device) -> the
 // blocked layout of field_layout in the storage type, the extra phi node
-// k = nph repeating node 0, padding nodes zero.
+// k = nph repeating node 0, padding nodes zero.  FP16 stores v / scale
+// rounded once from double to half.
 // ---------------------------------------------------------------------------
 __global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
                              const float *inv_scale_in) {
@@ -38,7 +39,8 @@ __global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int 
             v = src[((i * nth + j) * nph + (k == (uint64_t)nph ? 0 : k)) * 12 + comp];
         if (dtype == GC_F64) static_cast<double *>(dst)[o] = v;
         else if (dtype == GC_F32) static_cast<float *>(dst)[o] = (float)v;
-        else static_cast<__half *>(dst)[o] = __float2half((float)(v * (double)inv_scale_in[comp]));
+        else   // one rounding, double -> half (to nearest even)
+            static_cast<__half *>(dst)[o] = __half_raw{static_cast<_Float16>(v * (double)inv_scale_in[comp])};
     }
 }
 
