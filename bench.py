@@ -495,6 +495,17 @@ def cpu_baseline_mlp(args, small, f, spec, params):
                       f"{steps} particle-steps in {el:.1f} s"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args, wl, field):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
     import numpy as np
@@ -511,7 +522,8 @@ def cpu_baseline(args, wl, field):
     steps = int(p["step"].sum())
     return {"value": steps / el, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(p)} electrons (ids 0..{n_per - 1} of each ensemble) x {args.cpu_steps} steps "
-                      f"of the same field and injection; {steps} active particle-steps in {el:.1f} s"}
+                      f"of the same field and injection; {steps} active particle-steps in {el:.1f} s",
+            "cpu_model": cpu_model(), "per_core": steps / el / threads}
 
 
 def main():

@@ -200,6 +200,36 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
     return finite12(out);
 }
 
+// The field and the extra node array of the full Eqs. 1-2 (same geometry and
+// layout, fx the extra array's description) at one point, with one stencil:
+// the same operations and order as gather() on each array.  Returns what
+// gather() returns for the field; xok what it returns for the extra array.
+template <int FDT, typename R, bool kAllPairs = false>
+__device__ __forceinline__ bool gather2(const FieldDev &f, const FieldDev &fx, R r, R th, R ph, R out[12],
+                                        R xout[12], bool &xok) {
+    GatherPlan<R> gp;
+    xok = false;
+    if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = xout[c] = (R)0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Pair<FDT> p;
+        p.load(f.data, gp.off[q], gp.dk, gp.cs);
+        gather_add<FDT, R>(f, gp, q, p, out);
+        if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Pair<FDT> p;
+        p.load(fx.data, gp.off[q], gp.dk, gp.cs);
+        gather_add<FDT, R>(fx, gp, q, p, xout);
+        if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);
+    }
+    xok = finite12(xout);
+    return finite12(out);
+}
+
 // Word j of lane J of an aligned group of four lanes, to every lane of the
 // group (DPP quad permutation [J, J, J, J]).
 template <int J>

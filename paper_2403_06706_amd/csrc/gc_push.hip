@@ -78,9 +78,11 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         int stage = 0;
         bool bad = false;
         for (;;) {
-            R g[12];
-            const bool ok = FORM == kFormQuad ? gather_quad<FDT, R>(a.f, px, pth, pph, gl, g)
-                                              : gather<FDT, R, FORM == kFormAllPairs>(a.f, px, pth, pph, g);
+            R g[12], x[12];   // x: the extra node array (full equations only)
+            bool ok, xok = true;
+            if constexpr (FULL) ok = gather2<FDT, R, FORM == kFormAllPairs>(a.f, a.fx, px, pth, pph, g, x, xok);
+            else if constexpr (FORM == kFormQuad) ok = gather_quad<FDT, R>(a.f, px, pth, pph, gl, g);
+            else ok = gather<FDT, R, FORM == kFormAllPairs>(a.f, px, pth, pph, g);
             if (!ok) { bad = true; break; }
             if (stage == 0 && (flags & GC_FLAG_PENDING)) {
                 // collision k+1 (Eqs. 9-10): |p| kept, new pitch cosine and free path
@@ -102,8 +104,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             }
             R F[4], vp;
             if (FULL) {
-                R x[12];
-                if (!gather<FDT, R, FORM == kFormAllPairs>(a.fx, px, pth, pph, x)) { bad = true; break; }
+                if (!xok) { bad = true; break; }   // after the collision, as the field's own check
                 gc_rhs<R, true>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp, x);
             } else {
                 gc_rhs<R>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp);
