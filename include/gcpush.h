@@ -122,7 +122,9 @@ gc_status gc_get_options(const gc_ctx *ctx, gc_options *opt);
  *   B_r B_th B_ph | E_r E_th E_ph | (grad|B|)_r,th,ph | ((b.grad)b)_r,th,ph.
  * The library copies and repacks the data in store_dtype (GC_F16 stores each
  * component divided by a per-component power-of-two scale); the caller's buffer
- * may be freed when the call returns.  The call waits for the upload.
+ * may be freed when the call returns.  The call waits for the upload.  For
+ * GC_F32 and GC_F64 stores it keeps a second copy as node records for its
+ * four-lanes-per-particle form (device memory about twice the packed field).
  * extra: NULL (the reduced Eqs. 1-2, dropping the terms with derivatives of b
  *   and v_E), or a HOST pointer to [nr][nth][nph][9] values of src_dtype:
  *   (v_E.grad)b | (b.grad)v_E | (v_E.grad)v_E, local basis, v_E = E x B / B^2;

@@ -54,6 +54,7 @@ struct gc_ctx {
     // field
     bool have_field = false;
     void *field_buf = nullptr;
+    void *field_rec_buf = nullptr;    // node records of the field (quad form; FP32/FP64 stores)
     FieldDev f{};
     FieldDev *f_dev = nullptr;        // device copy of f
     FieldDev fx{};                    // the extra node array of the full Eqs. 1-2 (data NULL if none)
@@ -433,9 +434,11 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
 
 // Stage a host [nodes][nc] node array (nc = 12, or 9 padded to 12 with zeros)
 // as float64 on the device and pack it into the gathers' blocked layout
-// (field_layout, store type); scale receives the FP16 per-component scales.
-// Waits.
-gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int nc, void **out, float scale[12]) {
+// (field_layout, store type), and with rec_out also into node records
+// [nr][nth][nph+1][12] of the store type; scale receives the FP16
+// per-component scales.  Waits.
+gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int nc, void **out, void **rec_out,
+                     float scale[12]) {
     hipStream_t s = ctx->stream;
     const size_t nodes = (size_t)d->nr * d->nth * d->nph;
     const size_t packed = (size_t)field_layout(d->nr, d->nth, d->nph, d->store_dtype).total;
@@ -463,25 +466,34 @@ gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int 
         }
     }
     const size_t esz = d->store_dtype == GC_F64 ? 8 : (d->store_dtype == GC_F32 ? 4 : 2);
-    void *stage = nullptr, *buf = nullptr;
+    const size_t recs = (size_t)d->nr * d->nth * (d->nph + 1) * 12;
+    void *stage = nullptr, *buf = nullptr, *rec = nullptr;
     if (dalloc(ctx, (void **)&stage, nodes * 12 * 8 + 64) != hipSuccess) return fail(ctx, GC_ENOMEM, "cannot stage field");
-    if (dalloc(ctx, (void **)&buf, packed * esz) != hipSuccess) {
+    if (dalloc(ctx, (void **)&buf, packed * esz) != hipSuccess ||
+        (rec_out && dalloc(ctx, (void **)&rec, recs * esz) != hipSuccess)) {
         dfree(ctx, stage);
+        dfree(ctx, buf);
         return fail(ctx, GC_ENOMEM, "cannot allocate field");
     }
     float *dscale = reinterpret_cast<float *>(static_cast<char *>(stage) + nodes * 12 * 8);
     hipError_t e = hipMemcpyAsync(stage, src, nodes * 12 * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dscale, inv_scale, sizeof inv_scale, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, dscale, s);
+        e = launch_pack_field(static_cast<const double *>(stage), buf, d->nr, d->nth, d->nph, d->store_dtype, 0,
+                              dscale, s);
+    if (e == hipSuccess && rec)
+        e = launch_pack_field(static_cast<const double *>(stage), rec, d->nr, d->nth, d->nph, d->store_dtype, 1,
+                              dscale, s);
     const hipError_t es = hipStreamSynchronize(s);
     if (e == hipSuccess) e = es;
     dfree(ctx, stage);
     if (e != hipSuccess) {
         dfree(ctx, buf);
+        dfree(ctx, rec);
         return fail(ctx, GC_EDEVICE, "field packing: %s", hipGetErrorString(e));
     }
     *out = buf;
+    if (rec_out) *rec_out = rec;
     return GC_OK;
 }
 
@@ -568,6 +580,7 @@ void gc_destroy(gc_ctx *ctx) {
     if (ctx->scratch_mem) dfree(ctx, ctx->scratch_mem);
     if (ctx->log) dfree(ctx, ctx->log);
     if (ctx->field_buf) dfree(ctx, ctx->field_buf);
+    if (ctx->field_rec_buf) dfree(ctx, ctx->field_rec_buf);
     if (ctx->extra_buf) dfree(ctx, ctx->extra_buf);
     if (ctx->mlp.mem) dfree(ctx, ctx->mlp.mem);
     if (ctx->mlp.ws) dfree(ctx, ctx->mlp.ws);
@@ -625,19 +638,23 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = ctx->stream;
     float scale[12], xscale[12];
-    void *buf = nullptr, *xbuf = nullptr;
-    gc_status st = pack_nodes(ctx, d, d->data, 12, &buf, scale);
+    void *buf = nullptr, *rbuf = nullptr, *xbuf = nullptr;
+    // node records for the four-lanes-per-particle form (FP32 and FP64 stores)
+    gc_status st = pack_nodes(ctx, d, d->data, 12, &buf, d->store_dtype == GC_F16 ? nullptr : &rbuf, scale);
     if (st != GC_OK) return st;
     if (d->extra) {
-        st = pack_nodes(ctx, d, d->extra, 9, &xbuf, xscale);
+        st = pack_nodes(ctx, d, d->extra, 9, &xbuf, nullptr, xscale);
         if (st != GC_OK) {
             dfree(ctx, buf);
+            dfree(ctx, rbuf);
             return st;
         }
     }
     if (ctx->field_buf) dfree(ctx, ctx->field_buf);
+    if (ctx->field_rec_buf) dfree(ctx, ctx->field_rec_buf);
     if (ctx->extra_buf) dfree(ctx, ctx->extra_buf);
     ctx->field_buf = buf;
+    ctx->field_rec_buf = rbuf;
     ctx->extra_buf = xbuf;
     FieldDev &f = ctx->f;
     f.data = buf;
@@ -657,8 +674,10 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     f.cs = lay.cs;
     f.ks = lay.ks;
     f.js = lay.js;
+    f.rec = rbuf;
     ctx->fx = f;                      // same geometry, the extra node array (or none)
     ctx->fx.data = xbuf;
+    ctx->fx.rec = nullptr;
     if (xbuf)
         for (int c = 0; c < 12; ++c) ctx->fx.scale[c] = xscale[c];
     HIPCHK(hipMemcpyAsync(ctx->f_dev, &ctx->f, sizeof(FieldDev), hipMemcpyHostToDevice, s));

@@ -121,6 +121,7 @@ struct GatherPlan {
     uint32_t off[4];     // element offset of chunk 0 of each pair's first node
     uint32_t dk;         // offset of a pair's second (phi) node from its first
     uint32_t cs;         // element stride between chunks
+    uint32_t rec;        // element offset of the first node of pair 0 in the node records
 };
 
 template <int FDT, typename R>
@@ -150,6 +151,7 @@ __device__ __forceinline__ bool gather_plan(const FieldDev &f, R r, R th, R ph, 
     gp.dk = (k & 1u) ? f.ks - kLayBr * W : kLayBr * W;          // gK(k + 1) - gK(k)
     const uint32_t gj0 = j * f.js;
     gp.cs = f.cs;
+    gp.rec = ((i * (uint32_t)f.nth + j) * (uint32_t)(f.nph + 1) + k) * 12u;
     gp.w[0] = ((R)1 - wr) * ((R)1 - wt);
     gp.w[1] = ((R)1 - wr) * wt;
     gp.w[2] = wr * ((R)1 - wt);
@@ -263,50 +265,47 @@ __device__ __forceinline__ R quad_bcast_value(R x) {
     return y;
 }
 
-// Four lanes of an aligned quad, one particle (FP32 and FP64 fields): lane gl
-// (0-2) loads components 4gl..4gl+3 of both nodes of the four node pairs (one
-// chunk of FP32, two of FP64), runs their chains with the operations and order
-// of gather_add, and the quad exchanges the finished components, so all four
-// lanes hold the bits of gather().  Lane 3 repeats lane 2's loads (the same
-// cache lines) and its chains are not used.  All four lanes must call it
-// together.
+// Four lanes of an aligned quad, one particle (FP32 and FP64 fields), on the
+// node records f.rec: lane gl loads components 3gl..3gl+2 of both nodes of the
+// four node pairs (a pair's nodes are adjacent records, 48 or 96 bytes each),
+// runs their chains with the operations and order of gather_add, and the quad
+// exchanges the finished components, so all four lanes hold the bits of
+// gather().  Each lane converts and multiplies a quarter of the values.  All
+// four lanes must call it together.
 template <int FDT, typename R>
 __device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
     using T = typename std::conditional<FDT == GC_F64, double, float>::type;
-    constexpr uint32_t W = Layout<FDT>::W, kPer = 4 / W;
     GatherPlan<R> gp;
     if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
-    const uint32_t lc = gl < 3u ? gl : 2u;
-    const uint32_t lo = lc * kPer * gp.cs;
-    const char *base = static_cast<const char *>(f.data);
-    T v[4][8];     // [pair][4 h + e]: component 4 lc + e of node h
+    const uint32_t row = (uint32_t)(f.nph + 1) * 12u;                 // theta stride of the records
+    const uint32_t o[4] = {gp.rec, gp.rec + row, gp.rec + (uint32_t)f.nth * row,
+                           gp.rec + (uint32_t)f.nth * row + row};     // the pairs, in gather_add's order
+    // per-lane 64-bit addresses: the three components of a node merge into one
+    // load and the second node is a constant offset from the first
+    const T *base = static_cast<const T *>(f.rec) + 3u * gl;
+    T v[4][6];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+        const T *p = base + o[q];
 #pragma unroll
-        for (uint32_t h = 0; h < 2; ++h)
-#pragma unroll
-            for (uint32_t m = 0; m < kPer; ++m) {
-                const uint32_t o = gp.off[q] + h * gp.dk + lo + m * gp.cs;
-                if constexpr (W == 4) {
-                    const float4 x = *reinterpret_cast<const float4 *>(base + o * 4u);
-                    v[q][4 * h + 0] = x.x; v[q][4 * h + 1] = x.y; v[q][4 * h + 2] = x.z; v[q][4 * h + 3] = x.w;
-                } else {
-                    const double2 x = *reinterpret_cast<const double2 *>(base + o * 8u);
-                    v[q][4 * h + 2 * m + 0] = x.x; v[q][4 * h + 2 * m + 1] = x.y;
-                }
-            }
-    R acc[4] = {(R)0, (R)0, (R)0, (R)0};
+        for (int c = 0; c < 3; ++c) {
+            v[q][c] = p[c];            // node k
+            v[q][3 + c] = p[12 + c];   // node k + 1
+        }
+    }
+    R acc[3] = {(R)0, (R)0, (R)0};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const R wa = gp.w[q] * ((R)1 - gp.wp), wb = gp.w[q] * gp.wp;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = fma(wb, (R)v[q][4 + e], fma(wa, (R)v[q][e], acc[e]));
+        for (int c = 0; c < 3; ++c) acc[c] = fma(wb, (R)v[q][3 + c], fma(wa, (R)v[q][c], acc[c]));
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        out[e] = quad_bcast_value<0>(acc[e]);
-        out[4 + e] = quad_bcast_value<1>(acc[e]);
-        out[8 + e] = quad_bcast_value<2>(acc[e]);
+    for (int c = 0; c < 3; ++c) {
+        out[c] = quad_bcast_value<0>(acc[c]);
+        out[3 + c] = quad_bcast_value<1>(acc[c]);
+        out[6 + c] = quad_bcast_value<2>(acc[c]);
+        out[9 + c] = quad_bcast_value<3>(acc[c]);
     }
     return finite12(out);
 }

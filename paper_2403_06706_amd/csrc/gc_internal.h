@@ -74,6 +74,10 @@ struct FieldDev {
     double th_lo, th_hi;  // first and last theta node (exit bounds)
     float scale[12];      // GC_F16: stored value * scale = field value
     uint32_t cs, ks, js;  // layout strides (field_layout)
+    // Node records of the same values, [nr][nth][nph+1][12] of the storage
+    // type, for the four-lanes-per-particle form of FP32 and FP64 fields (its
+    // lanes take three components of a node each); NULL otherwise.
+    const void *rec;
 };
 
 // Structure-of-arrays particle state (one slot per particle).

@@ -11,29 +11,43 @@ namespace gc {
 
 // ---------------------------------------------------------------------------
 // Field packing: [nr][nth][nph][12] float64 (staged on the device) -> the
-// blocked layout of field_layout in the storage type, the extra phi node
-// k = nph repeating node 0, padding nodes zero.  FP16 stores v / scale
-// rounded once from double to half.
+// blocked layout of field_layout in the storage type (records == 0), or node
+// records [nr][nth][nph+1][12] (records != 0); the extra phi node k = nph
+// repeats node 0, padding nodes are zero.  FP16 stores v / scale rounded once
+// from double to half.
 // ---------------------------------------------------------------------------
-__global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
+__global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype, int records,
                              const float *inv_scale_in) {
     const FieldLayout L = field_layout(nr, nth, nph, dtype);
     const uint64_t nI = L.cs / (kLayB * L.W), nK = L.js / L.ks;
-    for (uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; o < L.total;
+    const uint64_t total = records ? (uint64_t)nr * nth * (nph + 1) * 12 : L.total;
+    for (uint64_t o = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; o < total;
          o += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t t = o / L.W;
-        const uint64_t e = o % L.W;
-        const uint64_t ii = t % kLayBr;
-        t /= kLayBr;
-        const uint64_t kk = t % kLayBk;
-        t /= kLayBk;
-        const uint64_t I = t % nI;
-        t /= nI;
-        const uint64_t c = t % L.nch;
-        t /= L.nch;
-        const uint64_t K = t % nK, j = t / nK;
-        const uint64_t i = I * kLayBr + ii, k = K * kLayBk + kk;
-        const int comp = (int)(c * L.W + e);
+        uint64_t i, j, k;
+        int comp;
+        if (records) {
+            comp = (int)(o % 12);
+            const uint64_t node = o / 12;
+            k = node % (nph + 1);
+            j = (node / (nph + 1)) % nth;
+            i = node / ((uint64_t)(nph + 1) * nth);
+        } else {
+            uint64_t t = o / L.W;
+            const uint64_t e = o % L.W;
+            const uint64_t ii = t % kLayBr;
+            t /= kLayBr;
+            const uint64_t kk = t % kLayBk;
+            t /= kLayBk;
+            const uint64_t I = t % nI;
+            t /= nI;
+            const uint64_t c = t % L.nch;
+            t /= L.nch;
+            const uint64_t K = t % nK;
+            j = t / nK;
+            i = I * kLayBr + ii;
+            k = K * kLayBk + kk;
+            comp = (int)(c * L.W + e);
+        }
         double v = 0.0;
         if (i < (uint64_t)nr && k <= (uint64_t)nph)
             v = src[((i * nth + j) * nph + (k == (uint64_t)nph ? 0 : k)) * 12 + comp];
@@ -44,9 +58,9 @@ __global__ void k_pack_field(const double *src, void *dst, int nr, int nth, int 
     }
 }
 
-hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
+hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype, int records,
                              const float *inv_scale, hipStream_t s) {
-    hipLaunchKernelGGL(k_pack_field, dim3(2048), dim3(256), 0, s, src, dst, nr, nth, nph, dtype, inv_scale);
+    hipLaunchKernelGGL(k_pack_field, dim3(2048), dim3(256), 0, s, src, dst, nr, nth, nph, dtype, records, inv_scale);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ hipError_t launch_state_in(const SoA &st, const gc_state_view &src, uint32_t n, 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t n, hipStream_t s);
 hipError_t launch_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t s);
-hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype,
+hipError_t launch_pack_field(const double *src, void *dst, int nr, int nth, int nph, int dtype, int records,
                              const float *inv_scale, hipStream_t s);
 
 // reordering (gc_order.hip)

@@ -72,6 +72,26 @@ def test_full_equations_forms_bitwise():
     assert np.array_equal(generation(ref), p["gen"]) and generation(ref).sum() > 500
 
 
+def test_nonfinite_extra_array_marks_particles():
+    """NaN in the extra node array over one radial shell: electrons that reach it
+    end NONFINITE at the same step on both sides, a collision pending there
+    applied first (the order of the field's own check), and the rest match."""
+    from oracle import NONFINITE
+    wl = small(n=600, hours=0.5, lambda_par=0.05 * AU)
+    f = field_of(wl)
+    x = extra_of(wl).copy()
+    i = int((0.45 * AU - wl.grid.r_min) / wl.grid.dr)
+    x[i, :, :, 7] = np.nan
+    st, log = run_gpu(wl, f, log_depth=64, extra=x)
+    p, ologs, *_ = run_oracle(wl, f, log_depth=64, extra=x)
+    assert np.array_equal(st["status"], p["status"])
+    assert np.array_equal(st["step"], p["step"]) and np.array_equal(st["k"], p["k"])
+    assert np.array_equal(log, ologs[0])
+    bad = p["status"] == NONFINITE
+    assert bad.sum() > 10
+    compare({k: v[~bad] for k, v in st.items()}, p[~bad], M_ELECTRON, TOL64, "finite part")
+
+
 def test_full_equations_argument_errors():
     wl = small(n=4, hours=0.0)
     f = field_of(wl)
