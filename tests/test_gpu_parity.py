@@ -2,7 +2,7 @@
 
 Bar (FP64 arithmetic on the GPU): identical status, step count and collision
 count for every particle, relative errors <= 1e-6 in position, u = gamma v_par
-and mu_B after 2 h of 1 s steps (the benchmark spec's tolerance for the FP64 form).
+and mu_B after 2 h of 1 s steps (the bar for the FP64 form).
 """
 import math
 from dataclasses import replace
