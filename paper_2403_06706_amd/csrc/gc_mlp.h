@@ -135,7 +135,7 @@ __device__ __forceinline__ void mlp_store(const u32x4 v[U], __bf16 *dst) {
 // halves while the current one is in use.  Per pass and hidden layer: 8 unit
 // tiles x 4 k-blocks x 4 column tiles = 128 MFMAs, the products of tile t
 // issued before the activation of tile t - 1, which they overlap.
-template <int NT>
+template <int NT, int kUnroll = 1>
 __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, float ph, MlpLds<NT> &L,
                                           float y[kMlpOut], float dy[3][kMlpOut]) {
     constexpr int kPer = kMlpPieces / NT;                  // pieces per thread
@@ -176,6 +176,11 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                 B[s][3][2 * i2 + 1] = (__bf16)(-sn * fn);
             }
         }
+        // kUnroll = kMlpDepth + 1 unrolls the layers: the next layer's operands
+        // (Bn) and the current ones (B) then swap register sets instead of being
+        // copied after every layer (measured: +9 % in the push, -7 % in the
+        // plain evaluation kernel, which keeps the loop)
+#pragma unroll(kUnroll)
         for (int mi = 0; mi <= kMlpDepth; ++mi) {
             __syncthreads();                                 // L.w[cur] holds matrix mi
             const int next = mi < kMlpDepth ? mi + 1 : 0;    // after the last: unused

@@ -75,7 +75,7 @@ void k_push_mlp(PushArgs a, MlpArgs m) {
     int stage = 0;
     while (__syncthreads_or(active)) {                        // uniform over the workgroup
         float y[kMlpOut], dy[3][kMlpOut];
-        mlp_block<kPushMlpThreads>(m, (float)px, (float)pth, (float)pph, L, y, dy);
+        mlp_block<kPushMlpThreads, kMlpDepth + 1>(m, (float)px, (float)pth, (float)pph, L, y, dy);
         if (!active) continue;
         R g[12];
         if (!mlp_assemble<R>(m, px, pth, y, dy, g)) { status = GC_NONFINITE; active = false; continue; }
