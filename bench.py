@@ -34,10 +34,17 @@ KERNEL_SOURCES = ["paper_2403_06706_amd/csrc/gc_push.hip", "paper_2403_06706_amd
 
 
 def kernel_hash() -> str:
+    """Hash of the push and field-layout sources without their comments and
+    blank lines (a change of wording does not invalidate measured counters)."""
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

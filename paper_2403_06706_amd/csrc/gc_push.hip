@@ -24,8 +24,8 @@ enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 // MODE 0: the reduced equations, no rebirth, centres at rest.  MODE 1: also
 // rebirth and scattering in the wind frame (Sect. 3 and 3.3); a separate
 // instantiation because the out-of-line rebirth raises the register count of
-// the FP32 forms.  MODE 2: also the full Eqs. 1-2 (a second gather of the
-// extra node array at each evaluation; no quad form).
+// the FP32 forms.  MODE 2: also the full Eqs. 1-2 (the extra node array is
+// gathered with the field's stencil at each evaluation; no quad form).
 template <int PREC, int FDT, int MODE, int FORM = kFormThroughput>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
     constexpr bool EXT = MODE >= 1;
