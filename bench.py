@@ -543,7 +543,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--store", default="f32", choices=["f32", "f64", "f16"])
     ap.add_argument("--precision", default="f64", choices=["f64", "f32_acc64", "f32_kahan"])
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=64)
     ap.add_argument("--coarsen", type=int, default=0)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--tile", type=int, default=1024)

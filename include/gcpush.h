@@ -77,7 +77,8 @@ typedef struct {
     int32_t order;          /* GC_ORDER_* */
     int32_t chunk_steps;    /* steps per push launch (and per reorder); > 0 */
     int32_t bin_coarsen;    /* cells per bin along each axis = 2^bin_coarsen (GC_ORDER_BIN) */
-    int32_t block_size;     /* push workgroup size: 64, 128 or 256 */
+    int32_t block_size;     /* push workgroup size: 64 (default), 128 or 256; the four-lanes-per-particle
+                               form always runs 256-thread workgroups */
     int32_t persistent;     /* 1: persistent push with a tile work queue */
     int32_t tile;           /* particles per work-queue tile (persistent mode, multiple of block_size) */
     int32_t log_depth;      /* per particle, record the step of the first log_depth collisions (0: off) */

@@ -67,7 +67,7 @@ class Context:
     """One gc_ctx on one device, using torch's current stream unless one is given."""
 
     def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
-                 bin_coarsen: int = 0, block_size: int = 256, persistent: bool = False, tile: int = 1024,
+                 bin_coarsen: int = 0, block_size: Optional[int] = None, persistent: bool = False, tile: int = 1024,
                  log_depth: int = 0, timing: bool = False, field_source: str = "grid", tail_threshold: Optional[int] = None,
                  stream=None, allocator: Optional[str] = None):
         """allocator "torch": the context's device memory comes from torch's caching
@@ -85,7 +85,8 @@ class Context:
         o.order = _ORDERS[order]
         o.chunk_steps = chunk_steps
         o.bin_coarsen = bin_coarsen
-        o.block_size = block_size
+        if block_size is not None:          # else the library's default
+            o.block_size = block_size
         o.persistent = int(persistent)
         o.tile = tile
         o.log_depth = log_depth

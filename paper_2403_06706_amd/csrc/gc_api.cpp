@@ -507,7 +507,7 @@ void gc_default_options(gc_options *o) {
     o->order = GC_ORDER_BIN;
     o->chunk_steps = 64;
     o->bin_coarsen = 0;
-    o->block_size = 256;
+    o->block_size = 64;
     o->persistent = 0;
     o->tile = 1024;
     o->log_depth = 0;
@@ -1093,7 +1093,7 @@ gc_status gc_gather_probe(gc_ctx *ctx, double dt, int32_t n_steps, double *sink)
         HIPCHK(launch_set_count(ctx->queue, (uint32_t)ctx->n, ctx->stream));
         a.n_active = ctx->queue;
     }
-    HIPCHK(launch_gather_probe(a, sink, ctx->stream));
+    HIPCHK(launch_gather_probe(a, sink, ctx->opt.block_size, ctx->stream));
     return GC_OK;
 }
 

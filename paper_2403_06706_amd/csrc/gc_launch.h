@@ -19,7 +19,7 @@ hipError_t launch_push(const PushArgs &a, int precision, int block, bool persist
                        hipStream_t s);
 
 // gather ceiling (gc_probe.hip): sink[slot] for every slot below *a.n_active
-hipError_t launch_gather_probe(const PushArgs &a, double *sink, hipStream_t s);
+hipError_t launch_gather_probe(const PushArgs &a, double *sink, int block, hipStream_t s);
 
 // injection, moments, state copies, fills (gc_kernels.hip)
 hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, uint32_t n0, uint32_t n,

@@ -42,13 +42,13 @@ __global__ __launch_bounds__(256) void k_gather_probe(PushArgs a, double *sink) 
     sink[slot] = acc;
 }
 
-hipError_t launch_gather_probe(const PushArgs &a, double *sink, hipStream_t s) {
-    const uint32_t nb = (a.n_slots + 255) / 256;
+hipError_t launch_gather_probe(const PushArgs &a, double *sink, int block, hipStream_t s) {
+    const uint32_t nb = (a.n_slots + block - 1) / block;      // the push's workgroup size
     if (nb == 0) return hipSuccess;
     switch (a.f.dtype) {
-        case GC_F64: hipLaunchKernelGGL(k_gather_probe<GC_F64>, dim3(nb), dim3(256), 0, s, a, sink); break;
-        case GC_F32: hipLaunchKernelGGL(k_gather_probe<GC_F32>, dim3(nb), dim3(256), 0, s, a, sink); break;
-        default:     hipLaunchKernelGGL(k_gather_probe<GC_F16>, dim3(nb), dim3(256), 0, s, a, sink); break;
+        case GC_F64: hipLaunchKernelGGL(k_gather_probe<GC_F64>, dim3(nb), dim3(block), 0, s, a, sink); break;
+        case GC_F32: hipLaunchKernelGGL(k_gather_probe<GC_F32>, dim3(nb), dim3(block), 0, s, a, sink); break;
+        default:     hipLaunchKernelGGL(k_gather_probe<GC_F16>, dim3(nb), dim3(block), 0, s, a, sink); break;
     }
     return hipGetLastError();
 }

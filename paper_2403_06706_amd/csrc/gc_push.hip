@@ -279,9 +279,12 @@ static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int fo
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;
-        if (form == kFormQuad && MODE != 2)
-            hipLaunchKernelGGL((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE>), dim3(4 * nb), dim3(block), 0, s, a);
-        else if (form != kFormThroughput)
+        if (form == kFormQuad && MODE != 2) {
+            // 256-thread workgroups whatever the block size (64 particles each;
+            // measured faster for this form than 64 threads)
+            const uint32_t qb = (4 * a.n_slots + 255) / 256;
+            hipLaunchKernelGGL((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE>), dim3(qb), dim3(256), 0, s, a);
+        } else if (form != kFormThroughput)
             hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, MODE>), dim3(nb), dim3(block), 0, s, a);
         else
             hipLaunchKernelGGL((k_push<PREC, FDT, MODE>), dim3(nb), dim3(block), 0, s, a);

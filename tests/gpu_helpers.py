@@ -32,7 +32,7 @@ def say(msg):
 
 
 def run_gpu(wl, field, store_dtype="f64", precision="f64", order="bin", chunk=64, n_steps=None, dt=None,
-            log_depth=0, block=256, persistent=False, tile=1024, coarsen=0, ensembles=None, graph=False,
+            log_depth=0, block=None, persistent=False, tile=1024, coarsen=0, ensembles=None, graph=False,
             tail_threshold=None, extra=None):
     import torch
     import paper_2403_06706_amd as gcp

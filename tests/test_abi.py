@@ -52,7 +52,7 @@ def test_host_side_errors_without_device():
     assert lib.gc_moments_size(None) == -1
     o = _abi.gc_options()
     lib.gc_default_options(C.byref(o))
-    assert o.chunk_steps == 64 and o.block_size == 256 and o.order == _abi.GC_ORDER_BIN
+    assert o.chunk_steps == 64 and o.block_size == 64 and o.order == _abi.GC_ORDER_BIN
     # invalid options are reported with a message, on a context that must be destroyed
     o.block_size = 100
     h = C.c_void_p()

@@ -23,7 +23,8 @@ def base():
     dict(order="bin", chunk=64),
     dict(order="bin", chunk=7, coarsen=2),
     dict(order="bin", chunk=1),
-    dict(order="bin", chunk=64, block=64),
+    dict(order="bin", chunk=64, block=256),
+    dict(order="bin", chunk=64, block=256, tail_threshold=0),
     dict(order="compact", chunk=100, block=128),
     dict(order="bin", chunk=64, persistent=True, tile=256),
     dict(order="none", chunk=64, persistent=True, tile=1024, block=128),
