@@ -11,7 +11,7 @@ cell keys + radix sort + permute, the push kernel, and the snapshot moments.
 The default --steps 1350 covers the full 24 h of simulated time.  The metric
 counts steps of active particles only.
 
-Prints one JSON line.  --gpus > 1 is rejected: this build targets one GPU.
+Prints one JSON line.  --gpus > 1 is rejected: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -569,7 +569,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the guiding-centre push is data-parallel over particles "
-              "and this build runs no multi-GPU path (see DESIGN.md for how it would shard).", file=sys.stderr)
+              "and the library has no multi-GPU path (particles would be sharded by id, the field replicated, "
+              "and the integer moments summed by one all-reduce).", file=sys.stderr)
         sys.exit(2)
 
     import torch
