@@ -140,6 +140,13 @@ class Context:
         except Exception:
             pass
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     @property
     def stream(self):
         return self._stream
