@@ -62,6 +62,12 @@ __device__ __forceinline__ float dsilu_f(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
+// The evaluation carries every hidden pre-activation and activation in log2
+// units, z' = z log2(e) and h' = h log2(e) (the biases and the layer-1 inputs
+// are scaled by log2(e), the output products by ln 2): then e^-z = 2^-z' is one
+// hardware exp2, and the weights are used as stored.
+constexpr float kMlpLog2e = 1.4426950408889634f, kMlpLn2 = 0.6931471805599453f;
+
 // Workgroup LDS of the evaluation (NT threads): two staged weight matrices
 // (rows padded to 144 BF16, 288 bytes: measured on the network push, the LDS
 // bank-conflict cycles per conflict-free cycle are 0.08 with this pitch, 0.65
@@ -84,7 +90,7 @@ struct MlpLds {
 // a barrier).
 template <int NT>
 __device__ __forceinline__ void mlp_lds_init(const MlpArgs &m, MlpLds<NT> &L) {
-    for (int i = threadIdx.x; i < kMlpDepth * kMlpWidth; i += NT) L.c[i] = m.c[i];
+    for (int i = threadIdx.x; i < kMlpDepth * kMlpWidth; i += NT) L.c[i] = m.c[i] * kMlpLog2e;
     if (threadIdx.x < kMlpEvalRows) L.co[threadIdx.x] = threadIdx.x < kMlpOut ? m.co[threadIdx.x] : 0.0f;
     if (threadIdx.x < kMlpFreq) {
         L.fa[threadIdx.x] = m.fa[threadIdx.x];
@@ -165,6 +171,8 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                 const float psi = two_pi * (fa * rt + fb * tt) + fn * pph;
                 float sn, cs;
                 __sincosf(psi, &sn, &cs);
+                sn *= kMlpLog2e;                             // inputs in log2 units (see mlp_block)
+                cs *= kMlpLog2e;
                 const float dr = two_pi * fa * m.inv_rspan, dth = 2.0f * fb;
                 B[s][0][2 * i2] = (__bf16)sn;
                 B[s][0][2 * i2 + 1] = (__bf16)cs;
@@ -216,13 +224,14 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
                         // the transcendental latencies of the units overlap
                         float sg[4], h[4], ds[4];
 #pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) sg[jj] = __expf(-prev[0][jj]);
+                        for (int jj = 0; jj < 4; ++jj) sg[jj] = __builtin_amdgcn_exp2f(-prev[0][jj]);   // e^-z
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj) sg[jj] = __builtin_amdgcn_rcpf(1.0f + sg[jj]);
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj) h[jj] = prev[0][jj] * sg[jj];
+                        // silu'(z) = s + z s (1 - s) = s + h' ln2 (1 - s)
 #pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) ds[jj] = sg[jj] + h[jj] * (1.0f - sg[jj]);
+                        for (int jj = 0; jj < 4; ++jj) ds[jj] = fmaf(h[jj], fmaf(-kMlpLn2, sg[jj], kMlpLn2), sg[jj]);
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj) {
                             const int s2 = u >> 1, i = (u & 1) * 4 + jj;
@@ -259,7 +268,7 @@ __device__ __forceinline__ void mlp_block(const MlpArgs &m, float r, float th, f
 #pragma unroll
                         for (int jj = 0; jj < 4; ++jj)
                             if (4 * g + jj < kMlpOut)
-                                yw[(16 * p + col) * (4 * kMlpOut) + q * kMlpOut + 4 * g + jj] = o[q][jj];
+                                yw[(16 * p + col) * (4 * kMlpOut) + q * kMlpOut + 4 * g + jj] = o[q][jj] * kMlpLn2;
                 }
                 mlp_store<NT, 0, kPer>(pf, nbuf);
             }
