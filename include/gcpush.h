@@ -88,7 +88,10 @@ typedef struct {
                                earlier reorder) is below this reorder only every 8 chunks and use a
                                latency form of the push (every field load of a gather in flight;
                                below a quarter of it, four lanes per particle); 0 disables.
-                               Results are bitwise identical in every form. */
+                               Results are bitwise identical in every form.  While it is > 0,
+                               gc_advance keeps the host at most 3 chunks ahead of the device
+                               (it waits for the chunk it issued 3 chunks earlier), so that the
+                               live count it reads back is recent. */
     /* Device memory of the context: dev_alloc(bytes, user) returns device memory
      * of that size or NULL, dev_free(ptr, user) releases it; both NULL: hipMalloc
      * and hipFree.  Given together or not at all (GC_EINVAL); fixed at gc_create
@@ -101,7 +104,10 @@ typedef struct {
 
 enum { GC_SOURCE_GRID = 0, GC_SOURCE_MLP = 1 };
 
-/* Fill *opt with the defaults (FP64, binning every 64 steps, 256 threads). */
+/* Fill *opt with the defaults: FP64, cell binning (bin_coarsen 0) every 64
+ * steps, 64-thread workgroups, grid form (not persistent; tile 1024), no
+ * collision log, no timing, trilinear grid field, tail_threshold 131072,
+ * device memory from hipMalloc, the null stream, device 0. */
 void gc_default_options(gc_options *opt);
 
 /* Create a context on opt->device.  out receives the handle. */
@@ -217,12 +223,17 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *desc);
  * rebirth when the ensemble asks for it); finish test.
  * tau = dt / (previous dt) on the first step after a change of dt.
  * The work is split in launches of chunk_steps steps, each preceded by the
- * configured reordering.  Errors: GC_ESTATE without field; GC_EINVAL if dt is
- * not finite and > 0 or n_steps < 0. */
+ * configured reordering.  Host waits: with tail_threshold > 0 the call waits,
+ * after queueing each chunk, for the chunk queued 3 chunks before it (so a
+ * call returns with at most 3 chunks still running); with tail_threshold = 0
+ * it returns without waiting.  Errors: GC_ESTATE without field; GC_EINVAL if
+ * dt is not finite and > 0 or n_steps < 0. */
 gc_status gc_advance(gc_ctx *ctx, double dt, int64_t n_steps);
 
 /* Same work as gc_advance, captured once per (dt, n_steps, options) into a
- * hipGraph and replayed on later calls with identical arguments. */
+ * hipGraph and replayed on later calls with identical arguments.  The graph
+ * has no tail policy (it needs a host read-back): every chunk reorders and
+ * runs the push the options select, and the call never waits for the device. */
 gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps);
 
 /* -------------------------------------------------------------- moments */
@@ -289,6 +300,24 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n);
  * uint32, entry [g][k] = step count at which collision k+1 of particle g was
  * applied, 0xFFFFFFFF if none.  GC_ESTATE if log_depth is 0. */
 gc_status gc_get_log(gc_ctx *ctx, uint32_t *dst);
+
+/* Slot order of the particles after the last reorder (the cell binning of the
+ * trilinear gathers' locality, Sect. 2.2): every pointer is a caller-owned
+ * DEVICE buffer or NULL (skipped).  slot_gid: gc_count() uint32, the global
+ * injection index of the particle in each slot.  slot_key: gc_count() uint32,
+ * the cell key the last reorder sorted that slot on (GC_ORDER_BIN only; with
+ * c = bin_coarsen, key = ((i >> c) nth_c + (j >> c)) nph_c + (k >> c) for the
+ * lower stencil node (i, j, k) of the particle's position, nth_c and nph_c the
+ * coarsened node counts; inactive particles, and every slot past the prefix
+ * that reorder sorted, get nr_c nth_c nph_c).  n_live: one uint32, the
+ * number of particles that were active at that reorder (they fill the slots
+ * below it).  Async.  The push moves particles between reorders and the tail
+ * policy skips reorders, so the keys describe the positions of the last
+ * reorder, not the current ones.  Errors: GC_EINVAL if every pointer is NULL;
+ * GC_ESTATE if no reorder ran since the last gc_inject, gc_set_state or
+ * growth of the state, or if slot_key is given and the last reorder was not a
+ * cell binning. */
+gc_status gc_get_order(gc_ctx *ctx, uint32_t *slot_gid, uint32_t *slot_key, uint32_t *n_live);
 
 /* ----------------------------------------------------------- counters */
 /* Waits for the stream.  push_ms: summed duration of push launches recorded

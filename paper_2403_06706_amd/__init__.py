@@ -7,7 +7,9 @@ outputs and the HIP stream.  Importing this package needs the built library
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from typing import Dict, Optional
 
 import numpy as np
@@ -52,6 +54,17 @@ def mlp_unflatten(flat: np.ndarray) -> Dict[str, np.ndarray]:
     return out
 
 
+# Contexts still open at interpreter exit are closed while torch is alive
+# (their memory may come from torch's allocator through callbacks).
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for ctx in list(_live):
+        ctx.close()
+
+
 class GCError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"gc status {status}: {message}")
@@ -69,9 +82,9 @@ class Context:
     def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
                  bin_coarsen: int = 0, block_size: Optional[int] = None, persistent: bool = False, tile: int = 1024,
                  log_depth: int = 0, timing: bool = False, field_source: str = "grid", tail_threshold: Optional[int] = None,
-                 stream=None, allocator: Optional[str] = None):
-        """allocator "torch": the context's device memory comes from torch's caching
-        allocator (on the context's stream) instead of hipMalloc."""
+                 stream=None, allocator: str = "torch"):
+        """allocator "torch" (default): the context's device memory comes from
+        torch's caching allocator, on the context's stream; "hip": from hipMalloc."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the guiding-centre pusher runs only on the device")
@@ -109,7 +122,7 @@ class Context:
 
             self._alloc_fns = (_abi.DEV_ALLOC_FN(_alloc), _abi.DEV_FREE_FN(_free))
             o.dev_alloc, o.dev_free = self._alloc_fns
-        elif allocator is not None:
+        elif allocator != "hip":
             raise ValueError(f"unknown allocator {allocator!r}")
         self._opt = o
         h = C.c_void_p()
@@ -122,6 +135,7 @@ class Context:
             self._h = None
             raise GCError(st, msg)
         self.log_depth = log_depth
+        _live.add(self)
 
     # -------------------------------------------------------------- basics
     def _check(self, st: int):
@@ -285,6 +299,22 @@ class Context:
         self._check(lib.gc_get_log(self._h, C.c_void_p(out.data_ptr())))
         self._outputs_ready(out)
         return out[:n]
+
+    def get_order(self, keys: bool = True):
+        """Slot order after the last reorder (gc_get_order): (slot -> global
+        index, slot -> sorted cell key or None, live count at that reorder),
+        as device int32 tensors and an int."""
+        torch = _torch()
+        n = self.count()
+        dev = f"cuda:{self.device}"
+        gid = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        key = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if keys else None
+        live = torch.empty(1, dtype=torch.int32, device=dev)
+        self._inputs_ready()
+        self._check(lib.gc_get_order(self._h, C.c_void_p(gid.data_ptr()),
+                                     C.c_void_p(key.data_ptr()) if keys else None, C.c_void_p(live.data_ptr())))
+        self._outputs_ready(gid, live, *([key] if keys else []))
+        return gid[:n], (key[:n] if keys else None), int(live.item())
 
     # ------------------------------------------------------------ counters
     def counters(self) -> dict:

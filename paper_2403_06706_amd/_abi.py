@@ -117,6 +117,7 @@ def load():
         "gc_get_state": (S, [P, C.POINTER(gc_state_view)]),
         "gc_set_state": (S, [P, C.POINTER(gc_state_view), C.c_uint64]),
         "gc_get_log": (S, [P, P]),
+        "gc_get_order": (S, [P, P, P, P]),
         "gc_get_counters": (S, [P, C.POINTER(gc_counters)]),
         "gc_reset_counters": (S, [P]),
         "gc_copy_probe": (S, [P, P, P, C.c_uint64]),
@@ -139,7 +140,7 @@ def load():
 DECLARED = (
     "gc_default_options", "gc_create", "gc_destroy", "gc_last_error", "gc_set_options", "gc_get_options",
     "gc_load_field", "gc_inject", "gc_advance", "gc_advance_graph", "gc_moments_size", "gc_moments",
-    "gc_count", "gc_get_state", "gc_set_state", "gc_get_log", "gc_get_counters", "gc_reset_counters",
+    "gc_count", "gc_get_state", "gc_set_state", "gc_get_log", "gc_get_order", "gc_get_counters", "gc_reset_counters",
     "gc_copy_probe", "gc_autotune", "gc_mlp_set", "gc_mlp_get_params", "gc_mlp_get_grads", "gc_mlp_train_step",
     "gc_mlp_eval", "gc_field_sample", "gc_gather_probe",
 )

@@ -28,6 +28,14 @@ struct GraphKey {
     gc_options opt{};
 };
 
+// Training workspace of the neural field for some number of rows (carve_ws).
+struct TrainWs {
+    __bf16 *H = nullptr, *dZ = nullptr;                  // H: activations H0..H6, [7][rows][128]
+    float *Z = nullptr, *Y = nullptr, *dY = nullptr;     // Z: pre-activations [6][rows][128]
+    float *dH = nullptr, *part = nullptr;                // part: split-K and column-sum partials
+    double *loss_part = nullptr;
+};
+
 // Neural field: FP32 master parameters (padded device layout), Adam moments,
 // gradient and the BF16 copies used by the matrix-core products; training
 // workspace sized for ws_rows rows.
@@ -40,10 +48,7 @@ struct MlpState {
     __bf16 *We = nullptr, *Woe = nullptr;                 // evaluation order (mlp_perm)
     void *ws = nullptr;
     int64_t ws_rows = 0;
-    __bf16 *H = nullptr, *dZ = nullptr;                  // H: activations H0..H6, [7][rows][128]
-    float *Z = nullptr, *Y = nullptr, *dY = nullptr;     // Z: pre-activations [6][rows][128]
-    float *dH = nullptr, *part = nullptr;
-    double *loss_part = nullptr;
+    TrainWs w{};                                         // carved from ws
 };
 
 struct gc_ctx {
@@ -74,7 +79,11 @@ struct gc_ctx {
     uint32_t *n_active = nullptr;
     uint32_t *queue = nullptr;
     uint32_t *n_bound = nullptr;      // live prefix: slots at or past it hold no active particle
+    uint32_t *sorted_n = nullptr;     // length of the prefix the last reorder sorted
     bool bound_dirty = true;          // the bound must be reset to n before the next reorder
+    bool order_known = false;         // a reorder ran since the particle set last changed
+    bool keys_known = false;          // ... and it was a cell binning (its keys are in sc.sorted_keys)
+    uint32_t sorted_dead = 0;         // the inactive key of that binning
     unsigned long long *steps = nullptr;       // [kPushForms] active particle-steps by push form
     uint32_t *log = nullptr;
     volatile uint32_t *count_host = nullptr;   // live count of the latest completed reorder (pinned)
@@ -175,9 +184,9 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     carve(m[0], cap, na);
     carve(m[1], cap, nb);
     const uint32_t max_blocks = (uint32_t)((cap + kSortTile - 1) / kSortTile);
-    const size_t scratch = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + (cap / 256 + 64) * 4;
+    const size_t sort_bytes = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + (cap / 256 + 64) * 4;
     void *sm = nullptr;
-    if (dalloc(ctx, (void **)&sm, scratch) != hipSuccess) {
+    if (dalloc(ctx, (void **)&sm, sort_bytes) != hipSuccess) {
         dfree(ctx, m[0]);
         dfree(ctx, m[1]);
         return fail(ctx, GC_ENOMEM, "cannot allocate sort scratch");
@@ -249,6 +258,7 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     ctx->log = log;
     ctx->cap = cap;
     ctx->bound_dirty = true;
+    ctx->order_known = ctx->keys_known = false;
     if (ctx->gexec) {
         (void)hipGraphExecDestroy(ctx->gexec);
         ctx->gexec = nullptr;
@@ -310,6 +320,7 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     if (order == GC_ORDER_NONE) {
         HIPCHK(launch_set_count(ctx->n_active, n, s));
         ctx->bound_dirty = true;    // active particles may sit anywhere until the next reorder
+        ctx->order_known = ctx->keys_known = false;
         return GC_OK;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -332,6 +343,7 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
         const uint32_t nthc = ((uint32_t)ctx->f.nth + (1u << c) - 1) >> c;
         const uint32_t nphc = ((uint32_t)ctx->f.nph + (1u << c) - 1) >> c;
         const uint32_t dead = nrc * nthc * nphc;
+        ctx->sorted_dead = dead;
         HIPCHK(launch_cell_keys(ctx->A, ctx->f, ctx->n_bound, n, c, dead, ctx->sc.keys[0], ctx->sc.block_alive,
                                 ctx->n_active, s));
         HIPCHK(launch_radix_sort(ctx->sc, ctx->n_bound, n, (int)bits_for(dead), &perm, s));
@@ -339,7 +351,10 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
     // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
     HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, s));
-    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->capturing ? nullptr : ctx->count_host, s));
+    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->capturing ? nullptr : ctx->count_host, ctx->sorted_n,
+                             s));
+    ctx->order_known = true;
+    ctx->keys_known = order == GC_ORDER_BIN;
     std::swap(ctx->A, ctx->B);
     std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
     if (timed) {
@@ -549,8 +564,9 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     ctx->n_active = static_cast<uint32_t *>(small);
     ctx->queue = ctx->n_active + 1;
     ctx->n_bound = ctx->n_active + 2;
+    ctx->sorted_n = ctx->n_active + 3;
     ctx->steps = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 64);
-    HIPCHK(launch_fill_u32(ctx->n_active, 0u, 3, ctx->stream));
+    HIPCHK(launch_fill_u32(ctx->n_active, 0u, 4, ctx->stream));
     HIPCHK(launch_fill_u64(ctx->steps, 0ull, kPushForms, ctx->stream));
     void *pinned = nullptr;
     HIPCHK(hipHostMalloc(&pinned, 64, hipHostMallocCoherent));
@@ -747,6 +763,7 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *d) {
                          ctx->stream));
     ctx->n += d->n;
     ctx->bound_dirty = true;
+    ctx->order_known = ctx->keys_known = false;
     if (ctx->count_host) *ctx->count_host = 0xFFFFFFFFu;
     return GC_OK;
 }
@@ -873,6 +890,7 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
     HIPCHK(launch_state_in(ctx->A, *src, (uint32_t)n, ctx->stream));
     ctx->n = n;
     ctx->bound_dirty = true;
+    ctx->order_known = ctx->keys_known = false;
     if (ctx->count_host) *ctx->count_host = 0xFFFFFFFFu;
     if (ctx->gexec) {
         (void)hipGraphExecDestroy(ctx->gexec);
@@ -887,6 +905,20 @@ gc_status gc_get_log(gc_ctx *ctx, uint32_t *dst) {
     if (ctx->n == 0) return GC_OK;
     HIPCHK(hipMemcpyAsync(dst, ctx->log, ctx->n * ctx->opt.log_depth * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                           ctx->stream));
+    return GC_OK;
+}
+
+gc_status gc_get_order(gc_ctx *ctx, uint32_t *slot_gid, uint32_t *slot_key, uint32_t *n_live) {
+    if (!ctx) return GC_EINVAL;
+    if (!slot_gid && !slot_key && !n_live) return fail(ctx, GC_EINVAL, "no output given");
+    if (!ctx->order_known) return fail(ctx, GC_ESTATE, "no reorder since the particle set last changed");
+    if (slot_key && !ctx->keys_known) return fail(ctx, GC_ESTATE, "the last reorder was not a cell binning");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    hipStream_t s = ctx->stream;
+    const uint32_t n = (uint32_t)ctx->n;
+    if (slot_gid && n) HIPCHK(hipMemcpyAsync(slot_gid, ctx->A.gid, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    if (slot_key) HIPCHK(launch_keys_out(ctx->sc.sorted_keys, ctx->sorted_n, ctx->sorted_dead, n, slot_key, s));
+    if (n_live) HIPCHK(hipMemcpyAsync(n_live, ctx->n_active, 4, hipMemcpyDeviceToDevice, s));
     return GC_OK;
 }
 
@@ -1133,38 +1165,51 @@ void to_user_layout(const std::vector<float> &d, float *u) {
     std::copy(d.begin() + kMlpOffCo, d.begin() + kMlpOffCo + kMlpOut, u + kUserOffCo);
 }
 
-size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Partials of the training step for R rows: the split-K weight gradients
+// (row groups, at most kTrainGroups), and the column sums of the output layer
+// (one block per kColRows rows, plus the summed block).
+constexpr size_t ws_part_floats(size_t R, size_t wgrad_groups) {
+    return std::max<size_t>(wgrad_groups * kMlpWidth * kMlpWidth,
+                            (size_t)(mlp_col_groups((int)std::min<size_t>(R, 1u << 30)) + 1) *
+                                (kMlpOut * kMlpWidth + kMlpOut));
+}
+
+// Bytes of the training workspace for R rows; with base, also carve it.
+constexpr size_t ws_bytes(size_t R, size_t part) {
+    return align256(7 * R * kMlpWidth * 2) + align256(R * kMlpWidth * 2) + align256(6 * R * kMlpWidth * 4) +
+           2 * align256(R * kMlpOut * 4) + align256(R * kMlpWidth * 4) + align256(part * 4) +
+           align256(kLossBlocks * 8);
+}
+
+void carve_ws(char *c, size_t R, size_t part, TrainWs &w) {
+    w.H = reinterpret_cast<__bf16 *>(c); c += align256(7 * R * kMlpWidth * 2);
+    w.dZ = reinterpret_cast<__bf16 *>(c); c += align256(R * kMlpWidth * 2);
+    w.Z = reinterpret_cast<float *>(c); c += align256(6 * R * kMlpWidth * 4);
+    w.Y = reinterpret_cast<float *>(c); c += align256(R * kMlpOut * 4);
+    w.dY = reinterpret_cast<float *>(c); c += align256(R * kMlpOut * 4);
+    w.dH = reinterpret_cast<float *>(c); c += align256(R * kMlpWidth * 4);
+    w.part = reinterpret_cast<float *>(c); c += align256(part * 4);
+    w.loss_part = reinterpret_cast<double *>(c);
+}
 
 gc_status mlp_workspace(gc_ctx *ctx, int64_t rows) {
     MlpState &m = ctx->mlp;
     if (rows <= m.ws_rows) return GC_OK;
     const int64_t cap = std::max<int64_t>(rows, 2 * m.ws_rows);
     const size_t R = (size_t)cap;
-    const size_t part = std::max<size_t>((size_t)kTrainGroups * kMlpWidth * kMlpWidth,
-                                         (size_t)(mlp_col_groups((int)std::min<int64_t>(cap, 1 << 30)) + 1) *
-                                             (kMlpOut * kMlpWidth + kMlpOut));
-    const size_t sz[] = {align256(7 * R * kMlpWidth * 2), align256(R * kMlpWidth * 2),
-                         align256(6 * R * kMlpWidth * 4), align256(R * kMlpOut * 4), align256(R * kMlpOut * 4),
-                         align256(R * kMlpWidth * 4), align256(part * 4), align256(kLossBlocks * 8)};
-    size_t total = 0;
-    for (size_t b : sz) total += b;
+    const size_t part = ws_part_floats(R, kTrainGroups);
     void *mem = nullptr;
-    if (dalloc(ctx, (void **)&mem, total) != hipSuccess)
+    if (dalloc(ctx, (void **)&mem, ws_bytes(R, part)) != hipSuccess)
         return fail(ctx, GC_ENOMEM, "cannot allocate the training workspace for %lld rows", (long long)cap);
     if (m.ws) dfree(ctx, m.ws);
     m.ws = mem;
     m.ws_rows = cap;
-    char *c = static_cast<char *>(mem);
-    m.H = reinterpret_cast<__bf16 *>(c); c += sz[0];
-    m.dZ = reinterpret_cast<__bf16 *>(c); c += sz[1];
-    m.Z = reinterpret_cast<float *>(c); c += sz[2];
-    m.Y = reinterpret_cast<float *>(c); c += sz[3];
-    m.dY = reinterpret_cast<float *>(c); c += sz[4];
-    m.dH = reinterpret_cast<float *>(c); c += sz[5];
-    m.part = reinterpret_cast<float *>(c); c += sz[6];
-    m.loss_part = reinterpret_cast<double *>(c);
+    carve_ws(static_cast<char *>(mem), R, part, m.w);
     return GC_OK;
 }
+
 
 gc_status check_mlp_points(gc_ctx *ctx, const double *pts, int64_t n, const double *out) {
     if (n < 0) return fail(ctx, GC_EINVAL, "n must be >= 0");
@@ -1267,56 +1312,79 @@ gc_status gc_mlp_get_grads(gc_ctx *ctx, float *host_out) {
     return mlp_copy_out(ctx, ctx ? ctx->mlp.g : nullptr, host_out);
 }
 
-gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
-                            const gc_mlp_train_opts *o, double *loss) {
-    if (!ctx || !o) return GC_EINVAL;
+}  // extern "C"
+
+namespace {
+
+gc_status check_train(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs, const gc_mlp_train_opts *o,
+                      int64_t max_pairs) {
     if (!ctx->mlp.set) return fail(ctx, GC_ESTATE, "no neural field (gc_mlp_set)");
-    if (n_pairs <= 0 || n_pairs > (1 << 26)) return fail(ctx, GC_EINVAL, "n_pairs must be in [1, 2^26]");
+    if (n_pairs <= 0 || n_pairs > max_pairs)
+        return fail(ctx, GC_EINVAL, "n_pairs must be in [1, %lld] (got %lld)", (long long)max_pairs, (long long)n_pairs);
     if (!pts || !tgt) return fail(ctx, GC_EINVAL, "pts and tgt must be set");
     if (o->apply && (o->step < 1 || !(o->lr > 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) ||
                      !(o->beta2 >= 0.0 && o->beta2 < 1.0) || !(o->eps > 0.0)))
         return fail(ctx, GC_EINVAL, "Adam needs step >= 1, lr > 0, 0 <= beta1, beta2 < 1 and eps > 0");
     if (!(o->beta_pair >= 0.0) || !std::isfinite(o->beta_pair)) return fail(ctx, GC_EINVAL, "beta_pair must be >= 0");
-    HIPCHK(hipSetDevice(ctx->opt.device));
-    const int rows = (int)(2 * n_pairs);
-    gc_status st = mlp_workspace(ctx, rows);
-    if (st != GC_OK) return st;
+    return GC_OK;
+}
+
+// Forward, loss, backward and the optional Adam update on the workspace w
+// (which holds at least 2 n_pairs rows); the loss partials are read back.
+gc_status train_step(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs, const gc_mlp_train_opts *o,
+                     double *loss, const TrainWs &w) {
     MlpState &m = ctx->mlp;
     hipStream_t s = ctx->stream;
+    const int rows = (int)(2 * n_pairs);
     const size_t RW = (size_t)rows * kMlpWidth, WW = (size_t)kMlpWidth * kMlpWidth;
     // forward: H0 = features, H_{l+1} = silu(H_l W_l^T + c_l), Y = H6 W_o^T + c_o
-    HIPCHK(mlp_launch_features(m.args, pts, rows, m.H, s));
+    HIPCHK(mlp_launch_features(m.args, pts, rows, w.H, s));
     for (int l = 0; l < kMlpDepth; ++l)
-        HIPCHK(mlp_launch_forward_layer(m.H + l * RW, m.W + l * WW, m.p + kMlpOffC + l * kMlpWidth, rows, m.Z + l * RW,
-                                        m.H + (l + 1) * RW, s));
-    HIPCHK(mlp_launch_output(m.H + kMlpDepth * RW, m.Wo, m.p + kMlpOffCo, rows, m.Y, s));
+        HIPCHK(mlp_launch_forward_layer(w.H + l * RW, m.W + l * WW, m.p + kMlpOffC + l * kMlpWidth, rows, w.Z + l * RW,
+                                        w.H + (l + 1) * RW, s));
+    HIPCHK(mlp_launch_output(w.H + kMlpDepth * RW, m.Wo, m.p + kMlpOffCo, rows, w.Y, s));
     // loss and its gradient with respect to the outputs
     MlpLoss L{};
     for (int c = 0; c < kMlpOut; ++c) L.wc[c] = o->wc[c];
     L.beta = o->beta_pair;
     const int lb = (int)std::min<int64_t>(kLossBlocks, (n_pairs + 255) / 256);
-    HIPCHK(mlp_launch_loss(m.args, pts, tgt, m.Y, (int)n_pairs, L, m.dY, m.loss_part, lb, s));
+    HIPCHK(mlp_launch_loss(m.args, pts, tgt, w.Y, (int)n_pairs, L, w.dY, w.loss_part, lb, s));
     // backward; weight-gradient products split over row groups of about kRowsPerGroup rows
     const int groups = std::max(1, std::min(kTrainGroups, rows / kRowsPerGroup));
-    HIPCHK(mlp_launch_out_grad(m.dY, m.H + kMlpDepth * RW, rows, m.part, m.g + kMlpOffWo, m.g + kMlpOffCo, s));
-    HIPCHK(mlp_launch_out_back(m.dY, m.p + kMlpOffWo, rows, m.dH, s));
+    HIPCHK(mlp_launch_out_grad(w.dY, w.H + kMlpDepth * RW, rows, w.part, m.g + kMlpOffWo, m.g + kMlpOffCo, s));
+    HIPCHK(mlp_launch_out_back(w.dY, m.p + kMlpOffWo, rows, w.dH, s));
     for (int l = kMlpDepth - 1; l >= 0; --l) {
-        HIPCHK(mlp_launch_dz(m.dH, m.Z + l * RW, rows, m.dZ, m.part, m.g + kMlpOffC + l * kMlpWidth, s));
-        HIPCHK(mlp_launch_wgrad(m.dZ, m.H + l * RW, rows, groups, m.part, m.g + kMlpOffW + l * WW, s));
-        if (l > 0) HIPCHK(mlp_launch_backward_data(m.dZ, m.WT + l * WW, rows, m.dH, s));
+        HIPCHK(mlp_launch_dz(w.dH, w.Z + l * RW, rows, w.dZ, w.part, m.g + kMlpOffC + l * kMlpWidth, s));
+        HIPCHK(mlp_launch_wgrad(w.dZ, w.H + l * RW, rows, groups, w.part, m.g + kMlpOffW + l * WW, s));
+        if (l > 0) HIPCHK(mlp_launch_backward_data(w.dZ, m.WT + l * WW, rows, w.dH, s));
     }
     if (o->apply) {
         HIPCHK(mlp_launch_adam(m.p, m.mo, m.ve, m.g, kMlpParams, (float)o->lr, (float)o->beta1, (float)o->beta2,
                                (float)o->eps, o->step, s));
         HIPCHK(mlp_launch_refresh(m.p, m.W, m.WT, m.Wo, m.We, m.Woe, s));
     }
-    std::vector<double> lp(lb);
-    HIPCHK(hipMemcpyAsync(lp.data(), m.loss_part, lb * sizeof(double), hipMemcpyDeviceToHost, s));
+    double lp[kLossBlocks];
+    HIPCHK(hipMemcpyAsync(lp, w.loss_part, lb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double sum = 0.0;
-    for (double v : lp) sum += v;
+    for (int i = 0; i < lb; ++i) sum += lp[i];
     if (loss) *loss = sum;
     return GC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
+                            const gc_mlp_train_opts *o, double *loss) {
+    if (!ctx || !o) return GC_EINVAL;
+    gc_status st = check_train(ctx, pts, tgt, n_pairs, o, 1 << 26);
+    if (st != GC_OK) return st;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    st = mlp_workspace(ctx, 2 * n_pairs);
+    if (st != GC_OK) return st;
+    return train_step(ctx, pts, tgt, n_pairs, o, loss, ctx->mlp.w);
 }
 
 gc_status gc_mlp_eval(gc_ctx *ctx, const double *pts, int64_t n, double *out) {

@@ -42,6 +42,7 @@ struct OrderScratch {
     uint32_t *totals;      // [256]
     uint32_t *block_alive; // [n / 256] active particles per 256-slot block
     uint32_t max_blocks;
+    uint32_t *sorted_keys; // keys[0] or keys[1]: the keys in slot order after the last radix sort
 };
 constexpr int kSortTile = 2048;     // items per radix-sort block
 // Reorder kernels act on the live prefix [0, *np) of the slots (np in device
@@ -57,8 +58,13 @@ hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, 
                           bool with_comp, hipStream_t s);
 hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,
                              bool with_comp, hipStream_t s);
-// *dst = *src; also *host_mirror = *src when host_mirror (host-coherent pinned memory) is set
-hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, hipStream_t s);
+// *dst = *src; also *host_mirror = *src when host_mirror (host-coherent pinned memory) is set,
+// and *prev = the old *dst when prev is set
+hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, uint32_t *prev,
+                             hipStream_t s);
+// out[i] = i < *sorted_n ? sorted_keys[i] : dead_key for i < n
+hipError_t launch_keys_out(const uint32_t *sorted_keys, const uint32_t *sorted_n, uint32_t dead_key, uint32_t n,
+                           uint32_t *out, hipStream_t s);
 hipError_t launch_set_count(uint32_t *n_active, uint32_t n, hipStream_t s);
 
 }  // namespace gc

@@ -175,9 +175,8 @@ __global__ void k_mlp_out_back(const float *dY, const float *Wo_master, int rows
     dH[(size_t)row * kMlpWidth + k] = s;
 }
 
-// Row-parallel column work: a 256-thread block takes 64 rows, thread
+// Row-parallel column work: a 256-thread block takes kColRows = 64 rows, thread
 // (half = tid / 128, k = tid % 128) the rows r0 + half + 2i of column k.
-constexpr int kColRows = 64;
 
 // dZ = dH * silu'(Z) -> bf16, and per-block column sums (bias gradient)
 __global__ __launch_bounds__(256) void k_mlp_dz(const float *dH, const float *Z, int rows, __bf16 *dZ,
@@ -359,13 +358,16 @@ hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, floa
     // the partial block is [c][k] then [c]: sum into a staging area laid out the same way
     hipLaunchKernelGGL(k_sum_partials, dim3((count + 255) / 256), dim3(256), 0, s, partial, g, count,
                        partial + (size_t)g * count, 0);
-    hipMemcpyAsync(dWo, partial + (size_t)g * count, kMlpOut * kMlpWidth * sizeof(float), hipMemcpyDeviceToDevice, s);
-    hipMemcpyAsync(dco, partial + (size_t)g * count + kMlpOut * kMlpWidth, kMlpOut * sizeof(float),
-                   hipMemcpyDeviceToDevice, s);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dWo, partial + (size_t)g * count, kMlpOut * kMlpWidth * sizeof(float),
+                           hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dco, partial + (size_t)g * count + kMlpOut * kMlpWidth, kMlpOut * sizeof(float),
+                           hipMemcpyDeviceToDevice, s);
+    return e;
 }
 
-int mlp_col_groups(int rows) { return (rows + kColRows - 1) / kColRows; }
 
 hipError_t mlp_launch_adam(float *p, float *mo, float *ve, const float *g, int n, float lr, float b1, float b2,
                            float eps, int step, hipStream_t s) {

@@ -26,7 +26,9 @@ hipError_t mlp_launch_dz(const float *dH, const float *Z, int rows, __bf16 *dZ, 
                          float *bias_out, hipStream_t s);
 hipError_t mlp_launch_out_grad(const float *dY, const __bf16 *H6, int rows, float *partial, float *dWo, float *dco,
                                hipStream_t s);
-int mlp_col_groups(int rows);   // partial blocks of the row-parallel column sums
+constexpr int kColRows = 64;     // rows per block of the row-parallel column sums
+// partial blocks of the row-parallel column sums
+__host__ __device__ constexpr int mlp_col_groups(int rows) { return (rows + kColRows - 1) / kColRows; }
 hipError_t mlp_launch_adam(float *p, float *mo, float *ve, const float *g, int n, float lr, float b1, float b2,
                            float eps, int step, hipStream_t s);
 hipError_t mlp_launch_refresh(const float *p, __bf16 *W, __bf16 *WT, __bf16 *Wo, __bf16 *We, __bf16 *Woe,

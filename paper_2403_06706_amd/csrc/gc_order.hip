@@ -181,6 +181,7 @@ hipError_t launch_radix_sort(OrderScratch &sc, const uint32_t *np, uint32_t n_ma
         cur ^= 1;
     }
     *perm_out = sc.vals[cur];
+    sc.sorted_keys = sc.keys[cur];
     return hipGetLastError();
 }
 
@@ -297,14 +298,32 @@ hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo,
     return hipGetLastError();
 }
 
-__global__ void k_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror) {
+__global__ void k_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, uint32_t *prev) {
     const uint32_t v = *src;
+    if (prev) *prev = *dst;
     *dst = v;
     if (host_mirror) *host_mirror = v;
 }
 
-hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, dst, src, host_mirror);
+hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, uint32_t *prev,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, dst, src, host_mirror, prev);
+    return hipGetLastError();
+}
+
+// Cell keys of the last sort in slot order: the sorted keys over the sorted
+// prefix [0, *sorted_n), the inactive key past it.
+__global__ void k_keys_out(const uint32_t *sorted_keys, const uint32_t *sorted_n, uint32_t dead_key, uint32_t n,
+                           uint32_t *out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = i < *sorted_n ? sorted_keys[i] : dead_key;
+}
+
+hipError_t launch_keys_out(const uint32_t *sorted_keys, const uint32_t *sorted_n, uint32_t dead_key, uint32_t n,
+                           uint32_t *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys_out, dim3((n + 255) / 256), dim3(256), 0, s, sorted_keys, sorted_n, dead_key, n, out);
     return hipGetLastError();
 }
 

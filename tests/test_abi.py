@@ -52,7 +52,12 @@ def test_host_side_errors_without_device():
     assert lib.gc_moments_size(None) == -1
     o = _abi.gc_options()
     lib.gc_default_options(C.byref(o))
-    assert o.chunk_steps == 64 and o.block_size == 64 and o.order == _abi.GC_ORDER_BIN
+    # the defaults gcpush.h documents for gc_default_options
+    assert o.precision == _abi.GC_PREC_F64 and o.order == _abi.GC_ORDER_BIN
+    assert o.chunk_steps == 64 and o.bin_coarsen == 0 and o.block_size == 64
+    assert o.persistent == 0 and o.tile == 1024 and o.log_depth == 0 and o.timing == 0
+    assert o.field_source == _abi.GC_SOURCE_GRID and o.tail_threshold == 131072
+    assert not o.dev_alloc and not o.dev_free and not o.hip_stream and o.device == 0
     # invalid options are reported with a message, on a context that must be destroyed
     o.block_size = 100
     h = C.c_void_p()

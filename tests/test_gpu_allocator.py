@@ -1,7 +1,8 @@
 """Device memory from the caller's allocator (gc_options.dev_alloc / dev_free):
-with torch's caching allocator behind it the context's state, field and
-scratch buffers show up in torch's accounting, are returned on destruction,
-and the results are bitwise those of the hipMalloc-backed context."""
+with torch's caching allocator behind it (the binding's default) the
+context's state, field and scratch buffers show up in torch's accounting, are
+returned on destruction, and the results are bitwise those of the
+hipMalloc-backed context (allocator "hip")."""
 import numpy as np
 import pytest
 
@@ -35,7 +36,7 @@ def test_torch_allocator_backs_the_context():
     ctx.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated(0) - before < held // 4      # returned (outputs above are host copies)
-    ctx2, st_h, log_h = _run(wl, f, None)
+    ctx2, st_h, log_h = _run(wl, f, "hip")
     ctx2.close()
     same_state(st_t, st_h)
     assert np.array_equal(log_t, log_h)
@@ -44,3 +45,14 @@ def test_torch_allocator_backs_the_context():
 def test_allocator_choice_is_checked():
     with pytest.raises(ValueError):
         gcp.Context(device=0, allocator="bogus")
+
+
+def test_torch_allocator_is_the_default():
+    import torch
+    wl = small(n=512, hours=0.01)
+    f = field_of(wl)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated(0)
+    with gcp.Context(device=0) as ctx:
+        ctx.load_field(wl.grid, f, "f32")
+        assert torch.cuda.memory_allocated(0) - before >= wl.grid.nr * wl.grid.nth * (wl.grid.nph + 1) * 12 * 4

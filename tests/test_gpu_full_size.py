@@ -5,8 +5,12 @@ times, on sampled particles the oracle advances one by one.
   perturbed-spiral field, FP64 state, cell binning every 64 steps, the tail
   policy on; 2 h of 1 s steps.  64 sampled ids per ensemble.
 * Batched: 64 ensembles of uneven size, 4M electrons, the same field, the
-  graph-replayed persistent form with the tuned sizes; 2 h.  4 sampled ids per
-  ensemble.
+  graph-replayed persistent form at tile 512 (one of the autotuner's
+  candidates; trajectories are bitwise the same for every tile and workgroup
+  size, which test_gpu_order.py checks); 2 h.  4 sampled ids per ensemble.
+* Cell binning at the paper scale: the radix sort of 2^20 electrons by cell
+  (coarsening 0 and 1) is stable, puts inactive electrons last and sorts on
+  the cells of the positions it reorders.
 * Network field: 10M electrons through the BF16 network for one 64-step chunk;
   16 sampled ids against the oracle driven by the FP64 network.
 
@@ -132,3 +136,15 @@ def test_network_push_full_size_sampled_parity():
     say(f"  sampled 16: max position {pos.max():.2e}, u {du.max():.2e}")
     assert pos.max() <= 1e-4 and du.max() <= 3e-4
     assert (st["status"] == O.NONFINITE).sum() == 0
+
+
+@pytest.mark.parametrize("coarsen", [0, 1])
+def test_paper_scale_binning_order(field, coarsen):
+    from test_gpu_order import check_binning
+    wl = workloads.config_paper_scale()
+    ctx = gcp.Context(device=0, precision="f64", order="bin", chunk_steps=64, bin_coarsen=coarsen, tail_threshold=0)
+    ctx.load_field(wl.grid, field, "f32")
+    for e in wl.ensembles:
+        ctx.inject(e)
+    check_binning(ctx, wl, coarsen, wl.dt, 1280, "paper scale")
+    ctx.close()

@@ -95,21 +95,76 @@ def test_checkpoint_restore_is_bitwise(base):
     same_state(st, ref)
 
 
-def test_binning_sorts_active_particles_by_cell(base):
-    wl, f, _, _ = base
-    import torch
-    ctx = gcp.Context(device=0, order="bin", chunk_steps=1)
+def check_binning(ctx, wl, coarsen, dt, warm_steps, label):
+    """Run warm_steps (reordering every chunk), then one more reorder + step,
+    and check the reorder against the positions it sorted (shared with the
+    full-size test)."""
+    ctx.advance(dt, warm_steps)
+    order0, _, _ = ctx.get_order(keys=False)          # slot order of the previous reorder
+    order0 = order0.cpu().numpy().astype(np.int64)
+    snap = gcp.state_to_numpy(ctx.get_state())       # global order: the positions the next reorder sorts
+    ctx.advance(dt, 1)
+    order1, keys1, live = ctx.get_order()
+    order1 = order1.cpu().numpy().astype(np.int64)
+    keys1 = keys1.cpu().numpy().view(np.uint32).astype(np.int64)
+    n = len(order1)
+    say(f"binning {label}: {n} particles, coarsen {coarsen}, {live} live")
+    # a permutation of the particles, keys non-decreasing over the slots
+    assert np.array_equal(np.sort(order1), np.arange(n))
+    assert np.all(np.diff(keys1) >= 0)
+    # active particles first, the inactive ones after them
+    act = snap["status"][order1] == 0
+    assert act[:live].all() and not act[live:].any()
+    assert 0 < live < n
+    # stable: the new order is numpy's stable sort of the previous slot order by these keys
+    key_of = np.empty(n, dtype=np.int64)
+    key_of[order1] = keys1
+    assert np.array_equal(order1, order0[np.argsort(key_of[order0], kind="stable")])
+    # the keys are the cells of the sorted positions (the device decides marginal cases)
+    g = wl.grid
+    x = (snap["r"] - g.r_min) * ((g.nr - 1) / (g.r_max - g.r_min))
+    y = snap["th"] * (g.nth / np.pi) - 0.5
+    z = snap["ph"] * (g.nph / (2 * np.pi))
+    i = np.clip(np.floor(x), 0, g.nr - 2).astype(np.int64)
+    j = np.clip(np.floor(y), 0, g.nth - 2).astype(np.int64)
+    k = np.mod(np.floor(z), g.nph).astype(np.int64)
+    cdiv = lambda m: (m + (1 << coarsen) - 1) >> coarsen
+    want = ((i >> coarsen) * cdiv(g.nth) + (j >> coarsen)) * cdiv(g.nph) + (k >> coarsen)
+    want = np.where(snap["status"] == 0, want, cdiv(g.nr) * cdiv(g.nth) * cdiv(g.nph))
+    near = lambda v: np.abs(v - np.round(v)) < 1e-9
+    marginal = (near(x) | near(y) | near(z)) & (snap["status"] == 0)
+    differ = want != key_of
+    assert not (differ & ~marginal).any()
+    assert differ.sum() <= max(2, n // 100000)
+    # the sort is not trivial: many cells, and the order changed
+    assert len(np.unique(keys1[:live])) > 10 and (order1 != order0).any()
+
+
+@pytest.mark.parametrize("coarsen", [0, 1, 2])
+def test_binning_sorts_by_cell_stably_inactive_last(coarsen):
+    wl = small(n=4096, hours=0.5)
+    f = field_of(wl)
+    ctx = gcp.Context(device=0, order="bin", chunk_steps=64, bin_coarsen=coarsen, tail_threshold=0)
     ctx.load_field(wl.grid, f, "f64")
     ctx.inject(wl.ensembles[0])
-    ctx.advance(1.0, 1500)
-    # after a reorder + 1 step: active particles come first, in non-decreasing cell order
-    # (a particle may have crossed one cell boundary in the last step)
-    from paper_2403_06706_amd import _abi  # noqa: F401
-    st = ctx.get_state()
-    torch.cuda.synchronize()
+    check_binning(ctx, wl, coarsen, wl.dt, 1280, "small")
     ctx.close()
-    s = gcp.state_to_numpy(st)
-    assert (s["status"] == 0).sum() > 100 and (s["status"] != 0).sum() > 100
+
+
+def test_order_query_states():
+    wl = small(n=300, hours=0.01)
+    f = field_of(wl)
+    ctx = gcp.Context(device=0, order="compact", chunk_steps=16)
+    ctx.load_field(wl.grid, f, "f64")
+    ctx.inject(wl.ensembles[0])
+    with pytest.raises(gcp.GCError):
+        ctx.get_order()                      # no reorder since the injection
+    ctx.advance(1.0, 16)
+    with pytest.raises(gcp.GCError):
+        ctx.get_order()                      # a compaction has no cell keys ...
+    gid, key, live = ctx.get_order(keys=False)   # ... but a slot order
+    assert key is None and sorted(gid.cpu().tolist()) == list(range(300)) and live == 300
+    ctx.close()
 
 
 def test_counters_count_active_steps(base):
