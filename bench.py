@@ -27,7 +27,13 @@ sys.path.insert(0, ROOT)
 
 BYTES_PER_STEP = {"f32": 768, "f64": 1536, "f16": 384}     # 2 gathers x 8 nodes x 12 components
 PEAK_HBM_GBS = 8000.0
+# VALU issue of MI355X: one wave64 instruction per 4 cycles per SIMD (16 lanes, full-rate FP64 FMA
+# included), 256 CUs x 4 SIMDs at 2.4 GHz; in FP64 FMA flops this is the 78.6 TFLOP/s vector peak
+PEAK_VALU_GINST = 256 * 4 * 2.4e9 / 4 / 1e9
+PEAK_FP64_TFLOPS = 78.6
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "push_traffic.json")
+VALU_JSON = os.path.join(ROOT, "profiles", "push_valu.json")
+WHOLE_JOB_CHUNKS = 1350          # 24 h of 1 s steps in chunks of 64
 KERNEL_SOURCES = ["paper_2403_06706_amd/csrc/gc_push.hip", "paper_2403_06706_amd/csrc/gc_step.h",
                   "paper_2403_06706_amd/csrc/gc_device.h", "paper_2403_06706_amd/csrc/gc_internal.h",
                   "paper_2403_06706_amd/csrc/gc_kernels.hip"]
@@ -302,7 +308,7 @@ def cpu_baseline_steady(args, wl, field):
             "job_estimate_s": round(wl.n_steps / steps * el, 1)}
 
 
-def run_batched(args):
+def run_batched(args, wl=None, field=None):
     """64 ensembles of uneven size (4M electrons), ragged stop times, advanced by
     the persistent push in hipGraph replays of 128 steps, launch parameters
     from the autotuner."""
@@ -310,8 +316,9 @@ def run_batched(args):
     import torch
     import paper_2403_06706_amd as gcp
     from synthetic import workloads
-    wl = workloads.config_batched(seed=args.seed, store_dtype=args.store)
-    field = np.ascontiguousarray(wl.build_field(wl.grid, device="cuda"))
+    if wl is None:
+        wl = workloads.config_batched(seed=args.seed, store_dtype=args.store)
+        field = np.ascontiguousarray(wl.build_field(wl.grid, device="cuda"))
     stream = torch.cuda.Stream()
     ctx = gcp.Context(device=0, precision=args.precision, persistent=True, tile=args.tile, stream=stream)
     ctx.load_field(wl.grid, field, args.store)
@@ -502,6 +509,144 @@ def cpu_baseline_mlp(args, small, f, spec, params):
                       f"{steps} particle-steps in {el:.1f} s"}
 
 
+def load_profile(path, args):
+    """A committed counter summary of the push, if it belongs to these kernel
+    sources, field store and precision (else None: the counters are stale)."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tj = json.load(f)
+    if tj.get("kernel_hash") == kernel_hash() and tj.get("store") == args.store and tj.get("precision") == args.precision:
+        return tj
+    return None
+
+
+def push_roofline(args, c):
+    """Roofline of the dominant kernel, the throughput form of the push
+    (gc::k_push): bound by its VALU issue (profiles/push_valu.json).  achieved =
+    VALU wavefront instructions per active particle-step (committed counters)
+    x particle-steps per launch / mean launch time (HIP events of this run)."""
+    n0 = max(c["form_launches"][0], 1)
+    avg_push_s = c["form_ms"][0] / 1e3 / n0
+    steps_per_launch = c["form_steps"][0] / n0
+    valu = load_profile(VALU_JSON, args)
+    tj = load_profile(TRAFFIC_JSON, args)
+    traffic = round(tj["hbm_bytes_per_particle_step"] * steps_per_launch) if tj else None
+    gather_gbps = BYTES_PER_STEP[args.store] * steps_per_launch / avg_push_s / 1e9
+    tail = {}
+    for i, name in ((1, "gc::k_push_allpairs"), (2, "gc::k_push_quad")):
+        if c["form_launches"][i]:
+            tail[name] = {"launches": c["form_launches"][i], "avg_launch_ms": c["form_ms"][i] / c["form_launches"][i],
+                          "particle_steps": c["form_steps"][i],
+                          "rate": c["form_steps"][i] / (c["form_ms"][i] * 1e-3) if c["form_ms"][i] else None}
+    r = {"bound": "alu", "unit": "Ginst/s", "peak": PEAK_VALU_GINST, "achieved": None, "frac": None,
+         "traffic": traffic, "kernel": "gc::k_push", "avg_launch_ms": round(avg_push_s * 1e3, 4),
+         "launches": c["form_launches"][0], "particle_steps_per_launch": round(steps_per_launch),
+         "peak_derivation": "VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction",
+         "counters": "profiles/push_valu.json" if valu else "stale or missing (kernel sources changed)"}
+    if valu:
+        ipt = valu["valu_instructions_per_particle_step"]
+        achieved = ipt * steps_per_launch / avg_push_s / 1e9
+        flops = valu["fp64_flops_per_particle_step"] * steps_per_launch / avg_push_s / 1e12
+        r.update({"achieved": round(achieved, 1), "frac": round(achieved / PEAK_VALU_GINST, 4),
+                  "valu_instructions_per_particle_step": round(ipt, 3),
+                  "valu_busy_in_profile": round(valu["valu_busy"], 3),
+                  "fp64": {"flops_per_particle_step": round(valu["fp64_flops_per_particle_step"], 1),
+                           "TFLOPs": round(flops, 2), "frac_of_78.6": round(flops / PEAK_FP64_TFLOPS, 4)},
+                  "vector_memory_in_profile": {"ta_busy": round(valu["ta_busy"], 3), "td_busy": round(valu["td_busy"], 3),
+                                               "l1_tag_accesses_per_load": round(valu["l1_tag_accesses_per_load"], 2)}})
+    r["gathers"] = {"algorithmic_bytes_per_particle_step": BYTES_PER_STEP[args.store],
+                    "logical_GBps": round(gather_gbps, 1), "served_by": "L1/L2 (HBM traffic in 'traffic')"}
+    if tj:
+        r["hbm_l2_from_counters"] = {
+            "hbm_GBps": round(traffic / avg_push_s / 1e9, 1), "hbm_frac_of_peak": round(traffic / avg_push_s / 1e9 / PEAK_HBM_GBS, 4),
+            "l2_hit_rate": tj.get("l2_hit_rate"), "l2_requests_per_particle_step": tj.get("l2_requests_per_particle_step"),
+            "source": "profiles/push_traffic.json (rocprofv3 FETCH_SIZE, WRITE_SIZE, TCC_HIT, TCC_MISS)"}
+    r["tail_forms"] = tail
+    return r
+
+
+def whole_job(args, wl, field):
+    """The whole 24 h paper-scale job from injection (1,350 chunks of 64 steps,
+    with the tail forms once few electrons remain), timed like the main run."""
+    el, c, final, mom, _ = run_gpu(args, wl, field, args.precision, WHOLE_JOB_CHUNKS, 1)
+    total_ms = el * 1e3
+    return {"chunks": WHOLE_JOB_CHUNKS, "simulated_hours": WHOLE_JOB_CHUNKS * 64 * wl.dt / 3600.0,
+            "value": c["particle_steps"] / el, "particle_steps": c["particle_steps"], "wall_s": round(el, 3),
+            "push_ms": round(c["push_ms"], 1), "reorder_ms": round(c["reorder_ms"], 1),
+            "reorder_share": round(c["reorder_ms"] / total_ms, 4),
+            "forms": {"launches": c["form_launches"], "ms": [round(x, 1) for x in c["form_ms"]],
+                      "particle_steps": c["form_steps"]},
+            "active_at_end": int((final["status"] == 0).sum())}
+
+
+def precision_forms_gpu(args):
+    """The small spiral workload (1,024 electrons, 2 h, lambda 0.5 AU) in every
+    arithmetic and field-storage form on the device, with collision logs and
+    |B| at the final positions sampled by the device; compared with the FP64
+    oracle in the CPU-baseline leg."""
+    import numpy as np
+    import torch
+    import paper_2403_06706_amd as gcp
+    from synthetic import workloads
+    wl = workloads.config_small()
+    f64 = wl.build_field(wl.grid)
+    f32 = f64.astype(np.float32).astype(np.float64)
+    out = []
+    for prec, store in (("f64", "f32"), ("f32_acc64", "f32"), ("f32_kahan", "f32"), ("f32_kahan", "f16"),
+                        ("f64", "f16")):
+        ctx = gcp.Context(device=0, precision=prec, log_depth=256)
+        ctx.load_field(wl.grid, f32 if store == "f32" else f64, store)
+        ctx.inject(wl.ensembles[0])
+        ctx.advance(wl.dt, wl.n_steps)
+        st = gcp.state_to_numpy(ctx.get_state())
+        log = ctx.get_log().cpu().numpy().view(np.uint32)
+        pts = torch.tensor(np.stack([st["r"], st["th"], st["ph"]]), dtype=torch.float64, device="cuda").contiguous()
+        bmag = np.linalg.norm(ctx.field_sample(pts).cpu().numpy()[:, 0:3], axis=1)
+        ctx.close()
+        out.append({"precision": prec, "fields": store, "state": st, "log": log, "bmag": bmag})
+    return wl, f32, out
+
+
+def run_batched_pair(args):
+    """The 64-ensemble workload (4M electrons, ragged stops up to 48 h) twice
+    from injection: the graph-replayed persistent form with autotuned sizes,
+    and the eager grid form (gc_advance, default sizes, tail policy)."""
+    import numpy as np
+    import torch
+    import paper_2403_06706_amd as gcp
+    from synthetic import workloads
+    wl = workloads.config_batched(seed=args.seed, store_dtype=args.store)
+    field = np.ascontiguousarray(wl.build_field(wl.grid, device="cuda"))
+    graph = run_batched(args, wl=wl, field=field)
+    ctx = gcp.Context(device=0, precision=args.precision, timing=True)
+    ctx.load_field(wl.grid, field, args.store)
+    for e in wl.ensembles:
+        ctx.inject(e)
+    reps = (wl.n_steps + 127) // 128
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(reps):
+        ctx.advance(wl.dt, 128)
+        if (i + 1) % 300 == 0:
+            log(f"[bench] batched eager: {i + 1}/{reps}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    c = ctx.counters()
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    eager = {"value": c["particle_steps"] / el, "wall_s": round(el, 3), "particle_steps": c["particle_steps"],
+             "form": "eager grid form (gc_advance, 64-thread workgroups, tail policy)",
+             "final_status_counts": np.bincount(st["status"], minlength=4).tolist()}
+    return {"workload": graph["config"]["workload"], "particles": graph["config"]["particles"],
+            "ensembles": graph["config"]["ensembles"], "simulated_hours": graph["config"]["simulated_hours"],
+            "graph_persistent": {"value": graph["value"], "wall_s": round(graph["ms_per_step"] * graph["steps"] / 1e3, 3),
+                                 "tuned_options": graph["config"]["tuned_options"],
+                                 "tune_rates": graph["config"]["tune_rates"],
+                                 "final_status_counts": graph["final_status_counts"]},
+            "eager": eager, "ratio_graph_persistent_over_eager": graph["value"] / eager["value"]}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -511,6 +656,49 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def precision_table(forms):
+    """CPU-baseline leg: the FP64 oracle on the small workload (FP32-rounded
+    field, collision logs), timed, and each device form's final positions,
+    energies and decisions against it.  Particles whose status, step, collision
+    count and collision log agree with the oracle's are compared; the others
+    are counted (decisions taken one step apart by round-off)."""
+    import numpy as np
+    import oracle as O
+    from synthetic import C_LIGHT, E_CHARGE, M_ELECTRON
+    wl, f32, runs = forms
+    of = O.Field(wl.grid, f32)
+    tab = O.make_ens_table(wl.ensembles)
+    p = O.inject(of, tab, 0, np.arange(wl.ensembles[0].n, dtype=np.uint32))
+    t0 = time.perf_counter()
+    logs = O.advance(of, tab, p, wl.dt, wl.n_steps, O.max_threads(), log_depth=256)
+    el = time.perf_counter() - t0
+    olog = logs[0]
+    b_o = np.array([np.linalg.norm(O.field_eval(of, p["r"][i], p["th"][i], p["ph"][i])[0][0:3]) for i in range(len(p))])
+
+    def energy_ev(B, u, mu):
+        return (np.sqrt(1 + (u ** 2 + 2 * mu * B) / C_LIGHT ** 2) - 1) * M_ELECTRON * C_LIGHT ** 2 / E_CHARGE
+
+    e_o = energy_ev(b_o, p["u"], p["mu_B"] / M_ELECTRON)
+    R = lambda r, th, ph: np.stack([r * np.sin(th) * np.cos(ph), r * np.sin(th) * np.sin(ph), r * np.cos(th)], 1)
+    rows = []
+    for run in runs:
+        st, glog = run["state"], run["log"]
+        same = ((st["k"] == p["k"]) & (st["step"] == p["step"]) & (st["status"] == p["status"])
+                & np.all(glog == olog, axis=1))
+        Rg, Ro = R(st["r"], st["th"], st["ph"])[same], R(p["r"], p["th"], p["ph"])[same]
+        pos = np.linalg.norm(Rg - Ro, axis=1) / np.linalg.norm(Ro, axis=1)
+        e_g = energy_ev(run["bmag"], st["u"], st["mu"])[same]
+        de = np.abs(e_g - e_o[same]) / e_o[same]
+        rows.append({"precision": run["precision"], "fields": run["fields"], "agreeing": int(same.sum()),
+                     "decisions_differing": int((~same).sum()),
+                     "rel_position": {"max": float(pos.max()), "median": float(np.median(pos))},
+                     "rel_energy": {"max": float(de.max()), "median": float(np.median(de))}})
+    return {"workload": f"spiral-64x32x64-{wl.ensembles[0].n}e-2h", "particles": int(len(p)), "steps": wl.n_steps,
+            "reference": "FP64 oracle on the FP32-rounded field", "bar_fp64": 1e-6, "bar_fp32": 1e-4, "forms": rows,
+            "oracle": {"value": int(p["step"].astype(np.int64).sum()) / el, "unit": "particle-steps/s",
+                       "cores": O.max_threads(), "seconds": round(el, 3)}}
 
 
 def cpu_baseline(args, wl, field):
@@ -565,6 +753,9 @@ def main():
                     help="steady-state job with scattering in the wind frame and only v_par b (Fig. 11 setting)")
     ap.add_argument("--mlp-particles", type=int, default=10 << 20)
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (batched workload)")
+    ap.add_argument("--no-whole-job", action="store_true", help="skip the whole-24 h sub-record")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched graph-versus-eager sub-record")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision-form table")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -595,40 +786,8 @@ def main():
     log(f"[bench] {c['particle_steps']:.3e} particle-steps in {elapsed:.2f} s -> {value:.3e}/s; "
         f"push {c['push_ms']:.0f} ms over {c['n_push']} launches, reorder {c['reorder_ms']:.0f} ms")
 
-    # roofline of the dominant kernel: the throughput form of the push (k_push);
-    # the latency forms of the tail are reported beside it
-    n0 = max(c["form_launches"][0], 1)
-    avg_push_s = c["form_ms"][0] / 1e3 / n0
-    steps_per_launch = c["form_steps"][0] / n0
-    algo_bytes = BYTES_PER_STEP[args.store] * steps_per_launch
-    achieved = algo_bytes / avg_push_s / 1e9
-    traffic = None
-    counters = None
-    if os.path.exists(TRAFFIC_JSON):
-        with open(TRAFFIC_JSON) as f:
-            tj = json.load(f)
-        if (tj.get("kernel_hash") == kernel_hash() and tj.get("store") == args.store
-                and tj.get("precision") == args.precision):
-            # counters give HBM bytes per active particle-step of the push; scale to this run's launches
-            traffic = round(tj["hbm_bytes_per_particle_step"] * steps_per_launch)
-            counters = {"hbm_GBps": round(traffic / avg_push_s / 1e9, 1),
-                        "hbm_frac_of_peak": round(traffic / avg_push_s / 1e9 / PEAK_HBM_GBS, 4),
-                        "l2_hit_rate": tj.get("l2_hit_rate"),
-                        "l2_requests_per_particle_step": tj.get("l2_requests_per_particle_step"),
-                        "source": "profiles/push_traffic.json (rocprofv3 FETCH_SIZE, WRITE_SIZE, TCC_HIT, TCC_MISS)"}
-    tail = {}
-    for i, name in ((1, "gc::k_push_allpairs"), (2, "gc::k_push_quad")):
-        if c["form_launches"][i]:
-            tail[name] = {"launches": c["form_launches"][i], "avg_launch_ms": c["form_ms"][i] / c["form_launches"][i],
-                          "particle_steps": c["form_steps"][i],
-                          "rate": c["form_steps"][i] / (c["form_ms"][i] * 1e-3) if c["form_ms"][i] else None}
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                "kernel": "gc::k_push", "avg_launch_ms": round(avg_push_s * 1e3, 4),
-                "launches": c["form_launches"][0], "algorithmic_bytes_per_launch": round(algo_bytes),
-                "bytes_per_particle_step": BYTES_PER_STEP[args.store],
-                "gather_ceiling": ceiling, "tail_forms": tail, "hbm_l2_from_counters": counters}
-
+    roofline = push_roofline(args, c)
+    roofline["gather_ceiling"] = ceiling
     out = {
         "metric": "GC particle-steps/s on 1 MI355X at <=1e-4 rel err vs FP64 oracle",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -694,10 +853,31 @@ def main():
         out["steady_state"] = run_steady(args, field=field, with_cpu=False)
         out["steady_state"]["note"] = "with the oracle beside it: bench.py --workload steady"
 
+    if args.steps < WHOLE_JOB_CHUNKS and not args.no_whole_job and not args.probe_copy:
+        log("[bench] whole 24 h job ...")
+        out["whole_job"] = whole_job(args, wl, field)
+        log(f"[bench] whole job: {out['whole_job']['value']:.3e} particle-steps/s in {out['whole_job']['wall_s']} s")
+
+    if not args.no_batched and not args.probe_copy:
+        log("[bench] batched 64-ensemble workload: graph + persistent against eager ...")
+        out["batched"] = run_batched_pair(args)
+        log(f"[bench] batched: graph+persistent {out['batched']['graph_persistent']['value']:.3e}, "
+            f"eager {out['batched']['eager']['value']:.3e} particle-steps/s")
+
+    forms_gpu = None
+    if not args.no_precision and not args.probe_copy and not args.no_cpu_baseline:
+        log("[bench] precision forms on the small workload ...")
+        forms_gpu = precision_forms_gpu(args)
+
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(args, wl, field)
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} particle-steps/s on {out['cpu_baseline']['cores']} threads")
+        if forms_gpu is not None:
+            out["precision_forms"] = precision_table(forms_gpu)
+            for row in out["precision_forms"]["forms"]:
+                log(f"[bench] form {row['precision']}/{row['fields']}: max rel position {row['rel_position']['max']:.2e}, "
+                    f"{row['decisions_differing']} decisions differ")
     print(json.dumps(out), flush=True)
 
 
