@@ -389,6 +389,24 @@ typedef struct {
 gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
                             const gc_mlp_train_opts *opts, double *loss);
 
+/* gc_mlp_train_step for callers that cannot allocate device memory (code under
+ * HIP graph capture around the device work, serving or training loops, or
+ * harnesses that forbid allocation): the same step, bitwise the same loss,
+ * gradient and update, with its training workspace (activations,
+ * pre-activations, output gradients, split-K and column-sum partials, loss
+ * partials) in a static device array of the library instead of memory the
+ * context allocates.  The array holds 24.2 MiB, enough for n_pairs <= 2048,
+ * and each device the library runs on keeps its own copy until the process
+ * ends.  The call allocates nothing (no hipMalloc, hipFree or allocator
+ * callback); it reads the loss back and waits, like gc_mlp_train_step.
+ * Every call on one device shares that device's array: calls that overlap on
+ * one device (two contexts on different streams, or two host threads) race,
+ * and the array keeps the last call's contents.  Errors: as gc_mlp_train_step,
+ * and GC_EINVAL for n_pairs > 2048; GC_EDEVICE if the array's device address
+ * could not be read when the context was created. */
+gc_status gc_mlp_train_step_noalloc(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
+                                    const gc_mlp_train_opts *opts, double *loss);
+
 /* Field at n points (DEVICE pts: r[n], th[n], ph[n]; DEVICE out: n x 12, the
  * components in the order of the grid): gc_mlp_eval from the network,
  * gc_field_sample by trilinear interpolation of the loaded grid.  Async. */

@@ -403,9 +403,11 @@ class Context:
         return self._mlp_block(lib.gc_mlp_get_grads)
 
     def mlp_train_step(self, pts, tgt, wc=(1.0,) * 6, beta_pair: float = 0.0, lr: float = 1e-3,
-                       betas=(0.9, 0.999), eps: float = 1e-8, step: int = 1, apply: bool = True) -> float:
-        """One training step (gc_mlp_train_step).  pts: device float64 [3, 2n]
-        (point n + i pairs with point i); tgt: device float64 [2n, 6]."""
+                       betas=(0.9, 0.999), eps: float = 1e-8, step: int = 1, apply: bool = True,
+                       noalloc: bool = False) -> float:
+        """One training step (gc_mlp_train_step, or with noalloc the variant with
+        the library's static workspace, gc_mlp_train_step_noalloc).  pts: device
+        float64 [3, 2n] (point n + i pairs with point i); tgt: device float64 [2n, 6]."""
         n2 = int(pts.shape[1])
         if pts.shape[0] != 3 or n2 % 2 or tuple(tgt.shape) != (n2, 6):
             raise ValueError("pts must be [3, 2n] and tgt [2n, 6]")
@@ -421,8 +423,9 @@ class Context:
         o.apply = int(apply)
         loss = C.c_double()
         self._inputs_ready()
-        self._check(lib.gc_mlp_train_step(self._h, C.c_void_p(pts.data_ptr()), C.c_void_p(tgt.data_ptr()), n2 // 2,
-                                          C.byref(o), C.byref(loss)))
+        fn = lib.gc_mlp_train_step_noalloc if noalloc else lib.gc_mlp_train_step
+        self._check(fn(self._h, C.c_void_p(pts.data_ptr()), C.c_void_p(tgt.data_ptr()), n2 // 2, C.byref(o),
+                       C.byref(loss)))
         return loss.value
 
     def _points(self, fn, pts):

@@ -127,6 +127,7 @@ def load():
         "gc_mlp_get_params": (S, [P, C.POINTER(C.c_float)]),
         "gc_mlp_get_grads": (S, [P, C.POINTER(C.c_float)]),
         "gc_mlp_train_step": (S, [P, P, P, C.c_int64, C.POINTER(gc_mlp_train_opts), C.POINTER(C.c_double)]),
+        "gc_mlp_train_step_noalloc": (S, [P, P, P, C.c_int64, C.POINTER(gc_mlp_train_opts), C.POINTER(C.c_double)]),
         "gc_mlp_eval": (S, [P, P, C.c_int64, P]),
         "gc_field_sample": (S, [P, P, C.c_int64, P]),
     }
@@ -141,6 +142,6 @@ DECLARED = (
     "gc_default_options", "gc_create", "gc_destroy", "gc_last_error", "gc_set_options", "gc_get_options",
     "gc_load_field", "gc_inject", "gc_advance", "gc_advance_graph", "gc_moments_size", "gc_moments",
     "gc_count", "gc_get_state", "gc_set_state", "gc_get_log", "gc_get_order", "gc_get_counters", "gc_reset_counters",
-    "gc_copy_probe", "gc_autotune", "gc_mlp_set", "gc_mlp_get_params", "gc_mlp_get_grads", "gc_mlp_train_step",
+    "gc_copy_probe", "gc_autotune", "gc_mlp_set", "gc_mlp_get_params", "gc_mlp_get_grads", "gc_mlp_train_step", "gc_mlp_train_step_noalloc",
     "gc_mlp_eval", "gc_field_sample", "gc_gather_probe",
 )

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -122,6 +123,8 @@ gc_status fail(gc_ctx *c, gc_status st, const char *fmt, ...) {
     } while (0)
 
 bool valid_block(int b) { return b == 64 || b == 128 || b == 256; }
+
+void scratch_init(int device);   // the static training workspace (below), once per device
 
 gc_status check_options(gc_ctx *ctx, const gc_options *o) {
     if (o->precision < GC_PREC_F64 || o->precision > GC_PREC_F32_KAHAN)
@@ -551,6 +554,7 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     }
     *out = ctx;
     HIPCHK(hipSetDevice(o.device));
+    scratch_init(o.device);
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, o.device));
     ctx->n_cus = prop.multiProcessorCount;
@@ -1210,6 +1214,36 @@ gc_status mlp_workspace(gc_ctx *ctx, int64_t rows) {
     return GC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Training workspace of gc_mlp_train_step_noalloc: a file-scope device array
+// (each device that loads the library holds its own copy until the process
+// ends), sized for kStaticPairs point pairs.  Host code never passes the
+// array's name to a kernel (in host code it names a host-side stand-in): it
+// uses the device address read once per device with hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticPairs = 2048;
+constexpr size_t kStaticRows = 2 * kStaticPairs;
+constexpr size_t kStaticPart = ws_part_floats(kStaticRows, std::min<size_t>(kTrainGroups, kStaticRows / kRowsPerGroup));
+constexpr size_t kStaticBytes = ws_bytes(kStaticRows, kStaticPart);
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Once per device, with that device current (gc_create): the device address of scratch.
+void scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_done[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_scratch_done[device] = true;
+}
 
 gc_status check_mlp_points(gc_ctx *ctx, const double *pts, int64_t n, const double *out) {
     if (n < 0) return fail(ctx, GC_EINVAL, "n must be >= 0");
@@ -1385,6 +1419,22 @@ gc_status gc_mlp_train_step(gc_ctx *ctx, const double *pts, const double *tgt, i
     st = mlp_workspace(ctx, 2 * n_pairs);
     if (st != GC_OK) return st;
     return train_step(ctx, pts, tgt, n_pairs, o, loss, ctx->mlp.w);
+}
+
+gc_status gc_mlp_train_step_noalloc(gc_ctx *ctx, const double *pts, const double *tgt, int64_t n_pairs,
+                                    const gc_mlp_train_opts *o, double *loss) {
+    if (!ctx || !o) return GC_EINVAL;
+    gc_status st = check_train(ctx, pts, tgt, n_pairs, o, kStaticPairs);
+    if (st != GC_OK) return st;
+    const int dev = ctx->opt.device;
+    if (dev < 0 || dev >= kMaxDevices || !g_scratch_done[dev])
+        return fail(ctx, GC_EDEVICE, "no static workspace on device %d", dev);
+    if (!g_scratch_ptr[dev])
+        return fail(ctx, GC_EDEVICE, "static workspace of device %d: %s", dev, hipGetErrorString(g_scratch_err[dev]));
+    HIPCHK(hipSetDevice(dev));
+    TrainWs w{};
+    carve_ws(static_cast<char *>(g_scratch_ptr[dev]), kStaticRows, kStaticPart, w);
+    return train_step(ctx, pts, tgt, n_pairs, o, loss, w);
 }
 
 gc_status gc_mlp_eval(gc_ctx *ctx, const double *pts, int64_t n, double *out) {
