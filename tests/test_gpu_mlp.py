@@ -6,32 +6,26 @@ training on samples drawn along trajectories, judged against the grid.
 The device multiplies in BF16 with FP32 accumulation.  The test networks have
 BF16-representable weights (rounded on the host before upload), so that the
 device's BF16 weight copy is exact and the remaining difference is the BF16
-rounding of the activations and tangents (relative 2^-9 per value) plus FP32
-features and accumulation.  Rounding errors of 2^-9 in sums of 128 terms of
-random sign partly cancel: the outputs come out at a few 1e-4 of their size
-(RMS).  Derivative quantities are judged against the Jacobian norm of B (for
-grad|B|, which is a projection of it) and that norm over |B| plus 1/r (for the
-curvature (b.grad)b); the tolerances are 3-4x the errors measured on MI355X."""
+rounding of the activations and tangents (at most 2^-8 of each value) plus
+FP32 features and accumulation.  Every tolerance comes from the arithmetic
+model in bf16_model.py, evaluated on the CPU from the oracle's network: the
+oracle's network with the device's BF16 rounding points.  The device must stay
+within a small multiple of the model's error (3x its maximum, 2x its RMS,
+3x its relative gradient error); no bar is set from device output."""
 import math
 from dataclasses import replace
 
 import numpy as np
 import pytest
 
+import bf16_model as BM
 import oracle as O
 from gpu_helpers import field_of, oracle_to_state, rel_errors, say, small
 from oracle import mlp_oracle as M
 from synthetic import AU
 
 pytestmark = pytest.mark.gpu
-
-
-def bf16_round(a):
-    """Nearest BF16-representable values (round half to even), as float64."""
-    f = np.ascontiguousarray(a, dtype=np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+bf16_round = BM.bf16
 
 
 @pytest.fixture(scope="module")
@@ -59,6 +53,15 @@ def _points(rng, n):
                      rng.uniform(-1.0, 7.0, n)])
 
 
+@pytest.fixture(scope="module")
+def eval_bars(net):
+    """(max, rms) bars per vector from the arithmetic model at 4,096 points."""
+    _, _, _, spec, params = net
+    bars = BM.eval_bars(spec, params, _points(np.random.default_rng(5), 4096))
+    say("evaluation bars from the BF16 model: " + ", ".join(f"{k} {v[0]:.2e}/{v[1]:.2e}" for k, v in bars.items()))
+    return bars
+
+
 def test_parameters_round_trip(net):
     ctx, wl, f, spec, params = net
     back = ctx.mlp_params()
@@ -67,7 +70,7 @@ def test_parameters_round_trip(net):
 
 
 @pytest.mark.parametrize("n", [1, 63, 1000, 4096 + 17])
-def test_eval_matches_oracle(net, n):
+def test_eval_matches_oracle(net, eval_bars, n):
     import torch
     ctx, wl, f, spec, params = net
     rng = np.random.default_rng(11 + n)
@@ -77,21 +80,14 @@ def test_eval_matches_oracle(net, n):
     assert np.all(np.isfinite(got))
     # per-point scales: |B|, |E|; the Jacobian norm of B in the local basis for
     # grad|B|; that norm over |B| plus 1/r (field-line curvature scale) for K
-    r, th = pts[0], pts[1]
-    h0, dh0 = M.features(spec, pts[0], pts[1], pts[2])
-    y, dy = M.forward_jvp(params, h0, dh0)
-    env, denv = M.envelope(spec, r)
-    J = np.stack([denv[:, :3] * y[:, :3] + env[:, :3] * dy[0][:, :3], env[:, :3] * dy[1][:, :3] / r[:, None],
-                  env[:, :3] * dy[2][:, :3] / (r * np.sin(th))[:, None]])
-    jn = np.sqrt(np.sum(J ** 2, axis=(0, 2)))
-    bn = np.linalg.norm(ref[:, 0:3], axis=1)
-    scales = {"B": bn, "E": np.linalg.norm(ref[:, 3:6], axis=1), "G": jn, "K": jn / bn + 1.0 / r}
-    tol = {"B": (4e-3, 1e-3), "E": (4e-3, 1e-3), "G": (4e-2, 6e-3), "K": (1.5e-2, 3e-3)}   # (max, rms)
-    for name, sl in (("B", slice(0, 3)), ("E", slice(3, 6)), ("G", slice(6, 9)), ("K", slice(9, 12))):
-        err = np.linalg.norm(got[:, sl] - ref[:, sl], axis=1) / scales[name]
-        say(f"eval n={n} {name}: max {err.max():.2e} rms {np.sqrt(np.mean(err ** 2)):.2e}")
-        assert err.max() <= tol[name][0], (name, err.max())
-        assert np.sqrt(np.mean(err ** 2)) <= tol[name][1], name
+    errs = BM.field_errors(got, ref, BM.field_scales(spec, params, pts, ref))
+    for name, err in errs.items():
+        rms = np.sqrt(np.mean(err ** 2))
+        say(f"eval n={n} {name}: max {err.max():.2e} rms {rms:.2e} (bars {eval_bars[name][0]:.2e} / "
+            f"{eval_bars[name][1]:.2e})")
+        assert err.max() <= eval_bars[name][0], (name, err.max())
+        if n >= 1000:            # an RMS over few points says little
+            assert rms <= eval_bars[name][1], (name, rms)
 
 
 def _pairs(spec, rng, npair):
@@ -118,14 +114,19 @@ def test_training_gradient_matches_oracle(net):
     loss = ctx.mlp_train_step(P, T, wc=wc, beta_pair=beta, apply=False)
     g = ctx.mlp_grads()
     L, gref = M.loss_and_grad(spec, params, p1, t1, p2, t2, wc, beta)
-    say(f"loss device {loss:.6e} oracle {L:.6e}")
-    assert abs(loss - L) <= 1e-3 * L
+    Lm, gmod = BM.loss_and_grad(spec, params, p1, t1, p2, t2, wc, beta)
+    # bars: 3x the model's error, plus FP32 accumulation over the 2 x 333 rows
+    # (the device's partial sums in another order: rows x 2^-24, doubled)
+    fp32 = 2 * (2 * npair) * 2.0 ** -24
+    say(f"loss device {loss:.6e} oracle {L:.6e} model {Lm:.6e}")
+    assert abs(loss - L) <= BM.MAX_OVER_MODEL * abs(Lm - L) + fp32 * L
     for k in gref:
-        a, b = g[k].astype(np.float64).ravel(), gref[k].ravel()
+        a, b, m = g[k].astype(np.float64).ravel(), gref[k].ravel(), gmod[k].ravel()
         rel = np.linalg.norm(a - b) / np.linalg.norm(b)
-        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
-        say(f"grad {k}: rel {rel:.2e} cos {cos:.6f}")
-        assert rel <= 2e-2 and cos >= 0.9998, (k, rel, cos)
+        rel_m = np.linalg.norm(m - b) / np.linalg.norm(b)
+        bar = BM.MAX_OVER_MODEL * rel_m + fp32
+        say(f"grad {k}: rel {rel:.2e} (model {rel_m:.2e}, bar {bar:.2e})")
+        assert rel <= bar, (k, rel, bar)
     # the parameters did not move (apply = 0)
     back = ctx.mlp_params()
     assert all(np.array_equal(back[k].astype(np.float64), params[k]) for k in params)
@@ -181,12 +182,23 @@ def test_push_with_network_matches_oracle(net):
     def cb(r, th, ph):
         return M.field(spec, params, np.array([r]), np.array([th]), np.array([ph]))[0]
 
+    # the arithmetic model: the oracle integrator driven by the BF16-rounded network
+    q = p.copy()
+
+    def cb_model(r, th, ph):
+        return BM.field(spec, params, np.array([r]), np.array([th]), np.array([ph]))[0]
+
     O.advance(O.Field(wl.grid, callback=cb), tab, p, 1.0, n_steps, nthreads=1)
+    O.advance(O.Field(wl.grid, callback=cb_model), tab, q, 1.0, n_steps, nthreads=1)
     assert np.all(p["status"] == O.ACTIVE)
     assert np.array_equal(st["status"], p["status"])
     assert np.array_equal(st["step"], p["step"])
     pos, du, dmu = rel_errors(st, p, ens.m)
-    say(f"network push: max position {pos.max():.2e}, u {du.max():.2e}, mu {dmu.max():.2e}")
-    assert pos.max() <= 1e-4
-    assert du.max() <= 3e-4
+    mq = {k: q[k] for k in ("r", "th", "ph", "u")}
+    mq["mu"] = q["mu_B"] / ens.m
+    pos_m, du_m, _ = rel_errors(mq, p, ens.m)
+    say(f"network push: max position {pos.max():.2e} (model {pos_m.max():.2e}), u {du.max():.2e} "
+        f"(model {du_m.max():.2e}), mu {dmu.max():.2e}")
+    assert pos.max() <= BM.MAX_OVER_MODEL * pos_m.max()
+    assert du.max() <= BM.MAX_OVER_MODEL * du_m.max()
     assert dmu.max() == 0.0          # no collision: mu_B is never touched
