@@ -767,7 +767,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batched":
-        print(json.dumps(run_batched(args)), flush=True)
+        print(json.dumps(run_batched_pair(args)), flush=True)
         return
     if args.workload == "mlp":
         print(json.dumps(run_mlp(args)), flush=True)

@@ -251,11 +251,16 @@ __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
 
 // Persistent form: a fixed grid pulls tiles of consecutive slots from an
 // atomic counter until the tiles run out (every workgroup reaches the exit).
+// A tile holds a.tile slots, fewer when the live prefix would not give every
+// workgroup a tile (down to one slot per thread), so that a thinning
+// population stays spread over the machine instead of queueing behind few
+// workgroups.
 template <int PREC, int FDT, int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
-    const uint32_t tile = (uint32_t)a.tile;
+    const uint32_t share = ((n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const uint32_t tile = min((uint32_t)a.tile, max(blockDim.x, share));
     const uint32_t ntiles = (n + tile - 1) / tile;
     uint32_t taken = 0;
     for (;;) {
