@@ -88,6 +88,8 @@ typedef struct {
                                earlier reorder) is below this reorder only every 8 chunks and use a
                                latency form of the push (every field load of a gather in flight;
                                below a quarter of it, four lanes per particle); 0 disables.
+                               Persistent form (also in gc_advance_graph): the device picks the same
+                               forms from the live count of the chunk's reorder.
                                Results are bitwise identical in every form.  While it is > 0,
                                gc_advance keeps the host at most 3 chunks ahead of the device
                                (it waits for the chunk it issued 3 chunks earlier), so that the
@@ -231,9 +233,14 @@ gc_status gc_inject(gc_ctx *ctx, const gc_inject_desc *desc);
 gc_status gc_advance(gc_ctx *ctx, double dt, int64_t n_steps);
 
 /* Same work as gc_advance, captured once per (dt, n_steps, options) into a
- * hipGraph and replayed on later calls with identical arguments.  The graph
- * has no tail policy (it needs a host read-back): every chunk reorders and
- * runs the push the options select, and the call never waits for the device. */
+ * hipGraph and replayed on later calls with identical arguments.  In the graph
+ * every chunk reorders and runs the push the options select (the persistent
+ * push picks its tail forms on the device).  With tail_threshold > 0 the call
+ * keeps the host at most 3 calls ahead of the device (it waits for the replay
+ * issued 3 calls earlier), and once the live count read back is below
+ * tail_threshold it runs the chunks eagerly with the tail policy, as
+ * gc_advance, instead of replaying; results are bitwise the same either way.
+ * With tail_threshold = 0 it always replays and never waits. */
 gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps);
 
 /* -------------------------------------------------------------- moments */
@@ -323,9 +330,11 @@ gc_status gc_get_order(gc_ctx *ctx, uint32_t *slot_gid, uint32_t *slot_key, uint
 /* Waits for the stream.  push_ms: summed duration of push launches recorded
  * with timing = 1; n_push: their number; particle_steps: steps taken by active
  * particles since the context was created or counters were reset.  form_*: the
- * same split by form of the grid push: [0] throughput form (and every other
- * push: persistent, neural field), [1] all loads of a gather in flight, [2]
- * four lanes per particle (tail_threshold). */
+ * same split by form of the grid push: [0] throughput form (and the
+ * neural-field push), [1] all loads of a gather in flight, [2] four lanes per
+ * particle (tail_threshold).  The persistent push splits its steps by form the
+ * same way (the device picks the form from the live count) and books the time
+ * of its launches under [0]. */
 typedef struct {
     double push_ms;
     int64_t n_push;

@@ -354,8 +354,7 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
     // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
     HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, s));
-    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->capturing ? nullptr : ctx->count_host, ctx->sorted_n,
-                             s));
+    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->count_host, ctx->sorted_n, s));
     ctx->order_known = true;
     ctx->keys_known = order == GC_ORDER_BIN;
     std::swap(ctx->A, ctx->B);
@@ -388,6 +387,7 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     a.tile = ctx->opt.tile;
     a.queue = ctx->queue;
     const bool pers = ctx->opt.persistent != 0;
+    a.tail = pers && ctx->opt.field_source == GC_SOURCE_GRID ? (uint32_t)ctx->opt.tail_threshold : 0u;
     const int grid_blocks = ctx->n_cus * (1024 / ctx->opt.block_size);
     if (pers) HIPCHK(launch_fill_u32(ctx->queue, 0u, 1, s));
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -407,6 +407,17 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     return GC_OK;
 }
 
+// Bound the host's lead: wait for the work issued kAhead calls ago, then mark
+// the end of the work issued now.
+gc_status keep_close(gc_ctx *ctx) {
+    hipEvent_t &ev = ctx->ahead[ctx->ahead_pos];
+    if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    else HIPCHK(hipEventSynchronize(ev));
+    HIPCHK(hipEventRecord(ev, ctx->stream));
+    ctx->ahead_pos = (ctx->ahead_pos + 1) % kAhead;
+    return GC_OK;
+}
+
 gc_status enqueue_advance(gc_ctx *ctx, double dt, int64_t n_steps, bool timed) {
     int64_t left = n_steps;
     while (left > 0) {
@@ -423,11 +434,8 @@ gc_status enqueue_advance(gc_ctx *ctx, double dt, int64_t n_steps, bool timed) {
         st = push(ctx, dt, c, timed);
         if (st != GC_OK) return st;
         if (ctx->opt.tail_threshold > 0 && !ctx->capturing) {
-            hipEvent_t &ev = ctx->ahead[ctx->ahead_pos];
-            if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-            else HIPCHK(hipEventSynchronize(ev));          // the chunk issued kAhead chunks ago
-            HIPCHK(hipEventRecord(ev, ctx->stream));
-            ctx->ahead_pos = (ctx->ahead_pos + 1) % kAhead;
+            gc_status st2 = keep_close(ctx);
+            if (st2 != GC_OK) return st2;
         }
         left -= c;
     }
@@ -786,6 +794,10 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
     if (ctx->n == 0 || n_steps == 0) return GC_OK;
     if (!ctx->stream) return fail(ctx, GC_EINVAL, "graph capture needs a non-null stream");
     HIPCHK(hipSetDevice(ctx->opt.device));
+    // The tail: once the live count read back is below tail_threshold, a replay
+    // would mostly pay for its fixed launches (a reorder every chunk); the chunks
+    // then run eagerly with the tail policy (bitwise the same results).
+    if (tail_mode(ctx) && ctx->opt.order != GC_ORDER_NONE) return enqueue_advance(ctx, dt, n_steps, ctx->opt.timing != 0);
     const bool same = ctx->gexec && ctx->gkey.dt == dt && ctx->gkey.n_steps == n_steps && ctx->gkey.n == ctx->n &&
                       ctx->gkey.state == ctx->soa_mem[0] &&
                       std::memcmp(&ctx->gkey.opt, &ctx->opt, sizeof(gc_options)) == 0;
@@ -821,6 +833,7 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
         ctx->gkey.opt = ctx->opt;
     }
     HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+    if (ctx->opt.tail_threshold > 0) return keep_close(ctx);   // keeps the count read back recent
     return GC_OK;
 }
 

@@ -106,6 +106,7 @@ struct PushArgs {
     int32_t log_depth;
     int32_t tile;                  // persistent mode: particles per work item
     uint32_t *queue;               // persistent mode: next tile counter
+    uint32_t tail;                 // persistent mode: tail threshold of the live count (0: throughput form only)
     int32_t mode;                  // 0 plain, 1 rebirth or wind-frame scattering, 2 also the full Eqs. 1-2
 };
 

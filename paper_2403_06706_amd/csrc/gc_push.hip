@@ -249,18 +249,34 @@ __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
     push_grid<PREC, FDT, MODE, kFormQuad>(a);
 }
 
-// Persistent form: a fixed grid pulls tiles of consecutive slots from an
+// Persistent forms: a fixed grid pulls tiles of consecutive slots from an
 // atomic counter until the tiles run out (every workgroup reaches the exit).
-// A tile holds a.tile slots, fewer when the live prefix would not give every
-// workgroup a tile (down to one slot per thread), so that a thinning
-// population stays spread over the machine instead of queueing behind few
-// workgroups.
-template <int PREC, int FDT, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
+// A tile holds a.tile particles, fewer when the live prefix would not give
+// every workgroup a tile (down to one particle per thread, or per quad), so
+// that a thinning population stays spread over the machine instead of
+// queueing behind few workgroups.
+//
+// With a tail threshold T = a.tail > 0 each chunk launches the throughput,
+// all-pairs and four-lanes-per-particle kernels in turn, and the live count on
+// the device (written by the reorder) selects the one that works, the others
+// returning at once: T and more, the throughput form; [T/4, T), all pairs
+// (for the full equations, [0, T)); below T/4, four lanes per particle.  These
+// are the forms of the eager tail policy, chosen on the device so that a
+// captured graph follows the count without a host read-back.  Steps are
+// counted per form (a.steps_done + form).
+template <int PREC, int FDT, int MODE, int FORM>
+__device__ __forceinline__ void push_persistent(const PushArgs &a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
-    const uint32_t share = ((n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
-    const uint32_t tile = min((uint32_t)a.tile, max(blockDim.x, share));
+    const uint32_t T = a.tail;
+    const uint32_t q4 = MODE == 2 ? 0u : T / 4;               // the full equations have no quad form
+    const uint32_t lo = FORM == kFormThroughput ? T : (FORM == kFormAllPairs ? q4 : 0u);
+    const uint32_t hi = FORM == kFormThroughput ? 0xFFFFFFFFu : (FORM == kFormAllPairs ? T : q4);
+    if (n < lo || n >= hi) return;
+    constexpr uint32_t G = FORM == kFormQuad ? 4 : 1;          // lanes per particle
+    const uint32_t per = blockDim.x / G;                       // particles per workgroup round
+    const uint32_t share = ((n + gridDim.x - 1) / gridDim.x + per - 1) / per * per;
+    const uint32_t tile = min(max((uint32_t)a.tile, per), max(per, share));
     const uint32_t ntiles = (n + tile - 1) / tile;
     uint32_t taken = 0;
     for (;;) {
@@ -270,10 +286,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         __syncthreads();
         if (t >= ntiles) break;
         const uint32_t end = min(n, (t + 1) * tile);
-        for (uint32_t slot = t * tile + threadIdx.x; slot < end; slot += blockDim.x)
-            taken += advance_slot<PREC, FDT, MODE>(a, slot);
+        for (uint32_t slot = t * tile + threadIdx.x / G; slot < end; slot += per)
+            taken += advance_slot<PREC, FDT, MODE, FORM>(a, slot, threadIdx.x % G);
     }
-    count_steps(a, taken);
+    count_steps(a.steps_done + FORM, taken);
+}
+
+template <int PREC, int FDT, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
+    push_persistent<PREC, FDT, MODE, kFormThroughput>(a);
+}
+
+template <int PREC, int FDT, int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent_allpairs(PushArgs a) {
+    push_persistent<PREC, FDT, MODE, kFormAllPairs>(a);
+}
+
+template <int PREC, int FDT, int MODE>
+__global__ __launch_bounds__(256) void k_push_persistent_quad(PushArgs a) {
+    push_persistent<PREC, FDT, MODE, kFormQuad>(a);
 }
 
 
@@ -281,6 +312,12 @@ template <int PREC, int FDT, int MODE>
 static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
     if (persistent) {
         hipLaunchKernelGGL((k_push_persistent<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), 0, s, a);
+        if (a.tail > 0) {
+            hipLaunchKernelGGL((k_push_persistent_allpairs<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), 0, s, a);
+            if (MODE != 2)   // 256-thread workgroups (64 particles per round), as the grid quad form
+                hipLaunchKernelGGL((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE>),
+                                   dim3((uint32_t)grid_blocks * block / 256), dim3(256), 0, s, a);
+        }
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
         if (nb == 0) return hipSuccess;

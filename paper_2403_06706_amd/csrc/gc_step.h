@@ -128,11 +128,12 @@ __device__ __noinline__ BirthState rebirth_state(const FieldDev *f, const EnsDev
     return birth_state<FDT>(*f, *e, pid, gen);
 }
 
-__device__ __forceinline__ void count_steps(const PushArgs &a, uint32_t taken) {
+__device__ __forceinline__ void count_steps(unsigned long long *counter, uint32_t taken) {
     // one atomic per wavefront
     uint32_t v = taken;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(a.steps_done, (unsigned long long)v);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(counter, (unsigned long long)v);
 }
+__device__ __forceinline__ void count_steps(const PushArgs &a, uint32_t taken) { count_steps(a.steps_done, taken); }
 
 }  // namespace gc

@@ -37,6 +37,8 @@ def run_gpu(wl, field, store_dtype="f64", precision="f64", order="bin", chunk=64
     import torch
     import paper_2403_06706_amd as gcp
     stream = torch.cuda.Stream() if graph else None
+    if graph and tail_threshold is None:
+        tail_threshold = 0          # pure replays (with a threshold, the tail runs eagerly)
     ctx = gcp.Context(device=0, precision=precision, order=order, chunk_steps=chunk, log_depth=log_depth,
                       block_size=block, persistent=persistent, tile=tile, bin_coarsen=coarsen, stream=stream,
                       tail_threshold=tail_threshold)

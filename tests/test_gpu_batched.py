@@ -43,8 +43,12 @@ def test_graph_persistent_equals_eager_and_oracle(batched):
     steps = 2304                                   # longer than every stop time (0.2-0.6 h)
     say(f"batched: {wl.n_particles} electrons in {len(wl.ensembles)} ensembles")
     eager = _run(wl, f, steps, graph=False)
-    pers = _run(wl, f, steps, graph=True, persistent=True, tile=512)
+    # pure replays (the device picks no tail form), then the default: replays until the
+    # live count read back is below the tail threshold, eager chunks after that
+    pers = _run(wl, f, steps, graph=True, persistent=True, tile=512, tail_threshold=0)
     same_state(pers, eager)
+    hybrid = _run(wl, f, steps, graph=True, persistent=True, tile=512)
+    same_state(hybrid, eager)
     assert (eager["status"] == O.FINISHED).sum() > 1000 and (eager["status"] == O.EXITED).sum() > 1000
     # oracle on 8 sampled ids of every ensemble
     rng = np.random.default_rng(0)

@@ -26,7 +26,9 @@ def base():
     dict(order="bin", chunk=64, block=256),
     dict(order="bin", chunk=64, block=256, tail_threshold=0),
     dict(order="compact", chunk=100, block=128),
-    dict(order="bin", chunk=64, persistent=True, tile=256),
+    dict(order="bin", chunk=64, persistent=True, tile=256),            # persistent, device picks the quad form
+    dict(order="bin", chunk=64, persistent=True, tile=256, tail_threshold=0),                # throughput form only
+    dict(order="bin", chunk=64, persistent=True, tile=512, block=256, tail_threshold=4000),  # all pairs, then quad
     dict(order="none", chunk=64, persistent=True, tile=1024, block=128),
     dict(order="bin", chunk=64, tail_threshold=0),             # throughput form and binning every chunk
     dict(order="bin", chunk=64, tail_threshold=1 << 30),       # tail policy once a count has been read back
@@ -40,11 +42,36 @@ def test_trajectories_invariant(base, cfg):
     assert np.array_equal(log, ref_log)
 
 
+def test_graph_replay_of_the_persistent_form_matches_eager(base):
+    """The persistent form in graph replays, the device picking its form from
+    the live count: all pairs while all 2,000 electrons are live (tail
+    threshold 8,000), four lanes per particle once one has left."""
+    wl, f, ref, _ = base
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = gcp.Context(device=0, order="bin", chunk_steps=75, stream=stream, persistent=True, tile=256,
+                      tail_threshold=8000)
+    ctx.load_field(wl.grid, f, "f64")
+    ctx.inject(wl.ensembles[0])
+    with torch.cuda.stream(stream):
+        ctx.advance_graph(1.0, 150)          # captured and replayed once (no count read back yet)
+    c = ctx.counters()
+    assert c["form_steps"][1] > 0 and c["form_steps"][2] > 0 and c["form_steps"][0] == 0
+    with torch.cuda.stream(stream):
+        for _ in range(11):                  # then the eager tail policy (the count read back is below 8,000)
+            ctx.advance_graph(1.0, 150)
+            stream.synchronize()
+            torch.zeros(1000, device="cuda").sum().item()
+    st = gcp.state_to_numpy(ctx.get_state())
+    ctx.close()
+    same_state(st, ref)
+
+
 def test_graph_replay_matches_eager(base):
     wl, f, ref, _ = base
     import torch
     stream = torch.cuda.Stream()
-    ctx = gcp.Context(device=0, order="bin", chunk_steps=75, stream=stream)
+    ctx = gcp.Context(device=0, order="bin", chunk_steps=75, stream=stream, tail_threshold=0)   # replays only
     ctx.load_field(wl.grid, f, "f64")
     ctx.inject(wl.ensembles[0])
     with torch.cuda.stream(stream):
@@ -63,7 +90,7 @@ def test_graph_replays_mixed_with_eager_chunks(base):
     wl, f, ref, _ = base
     import torch
     stream = torch.cuda.Stream()
-    ctx = gcp.Context(device=0, order="bin", chunk_steps=75, stream=stream)
+    ctx = gcp.Context(device=0, order="bin", chunk_steps=75, stream=stream, tail_threshold=0)   # replays only
     ctx.load_field(wl.grid, f, "f64")
     ctx.inject(wl.ensembles[0])
     with torch.cuda.stream(stream):
