@@ -521,6 +521,217 @@ def load_profile(path, args):
     return None
 
 
+# Counter passes over the push (one rocprofv3 --pmc run each, with the command
+# PMC_BENCH_ARGS); their CSV output directories are named pmc_<pass>.
+PMC_BENCH_ARGS = "--steps 8 --warmup 0 --no-cpu-baseline --probe-copy"
+PMC_PASSES = {
+    "p1": "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_VMEM_RD SQ_INSTS_SALU SQ_WAIT_INST_ANY "
+          "SQ_BUSY_CYCLES SQ_WAVE_CYCLES GRBM_GUI_ACTIVE GRBM_COUNT",
+    "p2": "SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_TRANS_F64 "
+          "SQ_INSTS_VALU_CVT SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_FMA_F32 GRBM_GUI_ACTIVE",
+    "p3": "TA_TA_BUSY_sum TA_FLAT_READ_WAVEFRONTS_sum TD_TD_BUSY_sum TD_TC_STALL_sum TCP_TOTAL_CACHE_ACCESSES_sum "
+          "TCP_TCC_READ_REQ_sum TCP_PENDING_STALL_CYCLES_sum TCP_READ_TAGCONFLICT_STALL_CYCLES_sum GRBM_GUI_ACTIVE",
+    "p5": "SQ_ACTIVE_INST_VMEM SQ_INST_CYCLES_VMEM_RD SQ_ACTIVE_INST_ANY SQ_THREAD_CYCLES_VALU SQ_WAIT_ANY "
+          "SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VALU_FLOPS_FP64_TRANS SQ_CYCLES GRBM_GUI_ACTIVE",
+    "t1": "FETCH_SIZE",
+    "t2": "WRITE_SIZE",
+    "t3": "TCC_HIT_sum TCC_MISS_sum",
+}
+PUSH_KERNEL = "k_push<0, 1, 0>"
+COPY_KERNEL = "k_copy_probe"
+N_CU = 256
+N_XCD = 8          # GRBM_GUI_ACTIVE is summed over the XCDs
+COPY_PROBE_KIB = 262144.0
+
+
+def _pmc_dispatches(d, kernel):
+    """Counters per dispatch of one kernel (dispatch order) from a rocprofv3 CSV."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    per = {}
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                if kernel not in row["Kernel_Name"]:
+                    continue
+                c = per.setdefault(int(row["Dispatch_Id"]), {})
+                c[row["Counter_Name"]] = c.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    return [per[k] for k in sorted(per)]
+
+
+def _bench_line(path):
+    with open(path) as f:
+        lines = [ln for ln in f if ln.startswith('{"metric"')]
+    if not lines:
+        raise ValueError(f"no bench line in {path}")
+    return json.loads(lines[-1])
+
+
+def summarize_push_pmc(d):
+    """Writes profiles/push_valu.json, push_traffic.json and their tables from
+    the rocprofv3 passes PMC_PASSES under directory d (pmc_<pass>/ with the
+    CSV output, pmc_<pass>.log with the bench line of that run)."""
+    launches, probe = None, {}
+    lines = {}
+    for name in PMC_PASSES:
+        L = _pmc_dispatches(os.path.join(d, f"pmc_{name}"), PUSH_KERNEL)
+        if launches is None:
+            launches = [{"GRBM_GUI_ACTIVE": []} for _ in L]
+        if len(L) != len(launches):
+            raise ValueError(f"pass {name}: {len(L)} push launches, expected {len(launches)}")
+        for acc, cs in zip(launches, L):
+            for k, v in cs.items():
+                if k == "GRBM_GUI_ACTIVE":
+                    acc[k].append(v)
+                else:
+                    acc[k] = v
+        for k, v in (_pmc_dispatches(os.path.join(d, f"pmc_{name}"), COPY_KERNEL) or [{}])[0].items():
+            probe[k] = v
+        lines[name] = _bench_line(os.path.join(d, f"pmc_{name}.log"))
+    cfg = lines["p1"]["config"]
+    rl = lines["p1"]["roofline"]
+    if rl["launches"] != len(launches):
+        raise ValueError("bench line and counters disagree on the number of push launches")
+    steps = float(rl["particle_steps_per_launch"]) * rl["launches"]
+    for acc in launches:
+        acc["GRBM_GUI_ACTIVE"] = sum(acc["GRBM_GUI_ACTIVE"]) / len(acc["GRBM_GUI_ACTIVE"])
+        cu_cycles = N_CU * acc["GRBM_GUI_ACTIVE"] / N_XCD
+        acc["valu_busy"] = acc["SQ_ACTIVE_INST_VALU"] / cu_cycles   # quad-cycles per SIMD: 4 SIMDs per CU
+        acc["ta_busy"] = acc["TA_TA_BUSY_sum"] / cu_cycles
+        acc["td_busy"] = acc["TD_TD_BUSY_sum"] / cu_cycles
+    tot = {k: sum(a[k] for a in launches) for k in launches[0]}
+    cu_cycles = N_CU * tot["GRBM_GUI_ACTIVE"] / N_XCD
+    pps = {k: v / steps for k, v in tot.items() if k.startswith(("SQ_", "TA_", "TD_", "TCP_", "TCC_"))}
+    h = kernel_hash()
+    kname = f"gc::{PUSH_KERNEL} (FP64 arithmetic, FP32 field, plain mode, throughput form)"
+    cmd = f"bench.py {PMC_BENCH_ARGS}"
+    valu = {
+        "kernel": kname, "kernel_hash": h, "store": cfg["field_store"], "precision": cfg["precision"],
+        "launches": len(launches), "particle_steps": steps, "per_particle_step": pps,
+        "valu_instructions_per_particle_step": pps["SQ_INSTS_VALU"],
+        "fp64_flops_per_particle_step": 64.0 * pps["SQ_INSTS_VALU_FLOPS_FP64"],
+        "valu_busy": tot["SQ_ACTIVE_INST_VALU"] / cu_cycles,
+        "ta_busy": tot["TA_TA_BUSY_sum"] / cu_cycles, "td_busy": tot["TD_TD_BUSY_sum"] / cu_cycles,
+        "l1_tag_accesses_per_load": tot["TCP_TOTAL_CACHE_ACCESSES_sum"] / tot["TA_FLAT_READ_WAVEFRONTS_sum"],
+        "derivation": f"sums over the {len(launches)} launches of gc::{PUSH_KERNEL} in '{cmd}' ({steps:.5g} active "
+                      f"particle-steps), one rocprofv3 --pmc pass per counter set; busy fractions = counter / "
+                      f"({N_CU} CUs x GRBM_GUI_ACTIVE / {N_XCD} XCDs); written by bench.py --summarize-push-pmc"}
+    fetch_scale = COPY_PROBE_KIB / probe["FETCH_SIZE"]
+    write_scale = COPY_PROBE_KIB / probe["WRITE_SIZE"]
+    hbm = 1024.0 * (tot["FETCH_SIZE"] * fetch_scale + tot["WRITE_SIZE"] * write_scale)
+    traffic = {
+        "kernel": kname, "kernel_hash": h, "store": cfg["field_store"], "precision": cfg["precision"],
+        "hbm_bytes_per_particle_step": hbm / steps,
+        "l2_hit_rate": tot["TCC_HIT_sum"] / (tot["TCC_HIT_sum"] + tot["TCC_MISS_sum"]),
+        "l2_requests_per_particle_step": (tot["TCC_HIT_sum"] + tot["TCC_MISS_sum"]) / steps,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "derivation": f"FETCH_SIZE x {fetch_scale:.4f} + WRITE_SIZE x {write_scale:.4f} (KiB; scales from the "
+                      f"{COPY_PROBE_KIB:.0f} KiB copy of gc_copy_probe in the same runs) over {steps:.5g} "
+                      f"particle-steps of '{cmd}'; written by bench.py --summarize-push-pmc"}
+    prof = os.path.join(ROOT, "profiles")
+    with open(VALU_JSON, "w") as f:
+        json.dump(valu, f, indent=1)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(traffic, f, indent=1)
+    pmc_cmds = "\n".join(
+        f"    rocprofv3 --pmc {PMC_PASSES[n]} \\\n        --kernel-include-regex 'k_push<|k_copy_probe' "
+        f"--output-format csv -d $D/pmc_{n} -o run -- python3 $R/{cmd} > $D/pmc_{n}.log" for n in PMC_PASSES)
+    head = (f"Commands (one counter set per run, no other tracing; run from `/tmp` with `TMPDIR=/tmp`, `$R` = "
+            f"repository root, `$D` = an output directory), then `python3 $R/bench.py --summarize-push-pmc $D`, "
+            f"which wrote this file's tables and `{os.path.basename(VALU_JSON)}` / "
+            f"`{os.path.basename(TRAFFIC_JSON)}` (kernel source hash `{h}`):\n\n{pmc_cmds}\n\n"
+            f"Workload: the first {len(launches)} chunks of 64 steps of the paper-scale job (2^20 electrons, "
+            f"256x128x256 FP32 field), all in the throughput form: {steps:.5g} active particle-steps over the "
+            f"{len(launches)} launches (`roofline.particle_steps_per_launch` x `roofline.launches` of the bench "
+            f"line).  `--probe-copy` first runs `gc_copy_probe`, a 256 MiB copy, and skips every sub-record.\n")
+    rows = "\n".join(
+        f"| {i + 1} | {a['SQ_INSTS_VALU']:,.0f} | {a['SQ_ACTIVE_INST_VALU']:,.0f} | {a['GRBM_GUI_ACTIVE']:,.0f} | "
+        f"{a['valu_busy']:.3f} | {a['TA_TA_BUSY_sum']:,.0f} | {a['ta_busy']:.3f} | {a['td_busy']:.3f} | "
+        f"{a['SQ_INSTS_VALU_CVT']:,.0f} | {a['SQ_INSTS_VALU_FLOPS_FP64']:,.0f} |" for i, a in enumerate(launches))
+    mix = [("FMA F64", "SQ_INSTS_VALU_FMA_F64"), ("MUL F64", "SQ_INSTS_VALU_MUL_F64"),
+           ("ADD F64", "SQ_INSTS_VALU_ADD_F64"), ("transcendental F64", "SQ_INSTS_VALU_TRANS_F64"),
+           ("conversions", "SQ_INSTS_VALU_CVT"), ("INT32", "SQ_INSTS_VALU_INT32"), ("INT64", "SQ_INSTS_VALU_INT64")]
+    iv = pps["SQ_INSTS_VALU"]
+    other = iv - sum(pps[k] for _, k in mix)
+    mixrows = "\n".join(f"| {n} | {pps[k]:.3f} | {100 * pps[k] / iv:.1f} % |" for n, k in mix)
+    with open(os.path.join(prof, "push_f64_f32field_paper_scale_valu.md"), "w") as f:
+        f.write(f"""# k_push (FP64 arithmetic, FP32 field), paper-scale workload — VALU and vector-memory counters
+
+What limits the throughput form of the grid push, `gc::{PUSH_KERNEL}`, on the paper-scale workload: its
+vector ALU (VALU) issue is busy {valu['valu_busy']:.1%} of the cycles the SIMDs have, the texture-address (TA)
+and texture-data (TD) paths of the field gathers {valu['ta_busy']:.1%} and {valu['td_busy']:.1%}; the HBM traffic
+is {traffic['hbm_bytes_per_particle_step']:.1f} B per particle-step, {traffic['hbm_bytes_per_particle_step'] * steps / len(launches) / 1e9:.2f} GB per launch
+(`push_f64_f32field_paper_scale_traffic.md`).
+
+{head}
+`GRBM_GUI_ACTIVE` is summed over the {N_XCD} XCDs ({N_XCD} x the kernel's cycles), averaged over the passes;
+busy fractions are counter / ({N_CU} CUs x GRBM_GUI_ACTIVE / {N_XCD}).  `SQ_ACTIVE_INST_VALU` counts VALU
+quad-cycles per SIMD, so it divides by {N_CU} CUs for 4 SIMDs.
+
+Per launch:
+
+| Launch | SQ_INSTS_VALU | SQ_ACTIVE_INST_VALU | GRBM_GUI_ACTIVE | VALU busy | TA_TA_BUSY_sum | TA busy | TD busy | SQ_INSTS_VALU_CVT | SQ_INSTS_VALU_FLOPS_FP64 |
+|---|---|---|---|---|---|---|---|---|---|
+{rows}
+
+Sums over the {len(launches)} launches, per active particle-step (wavefront instructions; one wavefront
+instruction serves up to 64 particles):
+
+| VALU instructions | per particle-step | share |
+|---|---|---|
+{mixrows}
+| other (moves, selects, compares, bit operations) | {other:.3f} | {100 * other / iv:.1f} % |
+| **all VALU** | **{iv:.3f}** | 100 % |
+
+* **VALU issue: {iv:.2f} wavefront instructions per particle-step**, busy {valu['valu_busy']:.3f} of the SIMD
+  cycles.  The VALU issue peak of MI355X is one wave64 instruction per 4 cycles per SIMD (16 lanes;
+  full-rate FP64 FMA included): 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G instructions/s, the 78.6 TFLOP/s
+  FP64 vector peak counted in instructions.  bench.py reports `roofline.achieved` = {iv:.3f} x
+  (particle-steps per launch) / (mean launch time from HIP events) against that peak.
+* FP64 arithmetic: {valu['fp64_flops_per_particle_step']:.0f} FLOP per particle-step
+  (`SQ_INSTS_VALU_FLOPS_FP64` x 64 lanes), of which 384 are the 2 x 96 interpolation FMAs.
+* Vector memory: TA busy {valu['ta_busy']:.3f}, TD busy {valu['td_busy']:.3f};
+  {valu['l1_tag_accesses_per_load']:.1f} L1 tag accesses per 16-byte-per-lane load (16 for 64 lanes on
+  consecutive addresses); {pps['TCP_TCC_READ_REQ_sum']:.4f} L2 read requests per particle-step.
+* {pps['SQ_INSTS_VALU_CVT']:.2f} conversions per particle-step are the FP32 field values widened to FP64
+  (96 per gather).
+""")
+    trows = "\n".join(
+        f"| {i + 1} | {a['FETCH_SIZE']:,.1f} | {a['WRITE_SIZE']:,.1f} | {a['TCC_HIT_sum']:,.0f} | {a['TCC_MISS_sum']:,.0f} | "
+        f"{a['TCC_HIT_sum'] / (a['TCC_HIT_sum'] + a['TCC_MISS_sum']):.3f} |" for i, a in enumerate(launches))
+    with open(os.path.join(prof, "push_f64_f32field_paper_scale_traffic.md"), "w") as f:
+        f.write(f"""# k_push (FP64 arithmetic, FP32 field), paper-scale workload — HBM and L2 counters
+
+{head}
+Calibration (same runs):
+
+| Kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) |
+|---|---|---|
+| `gc::{COPY_KERNEL}` (256 MiB copy) | {probe['FETCH_SIZE']:,.1f} | {probe['WRITE_SIZE']:,.1f} |
+
+so FETCH_SIZE is scaled by {COPY_PROBE_KIB:,.0f} / {probe['FETCH_SIZE']:,.1f} = {fetch_scale:.3f} and WRITE_SIZE by
+{write_scale:.3f}.
+
+Push launches (`gc::{PUSH_KERNEL}`):
+
+| Launch | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | TCC_HIT | TCC_MISS | L2 hit rate |
+|---|---|---|---|---|---|
+{trows}
+
+* Scaled HBM bytes: {hbm:.4e} B over {steps:.5g} particle-steps = **{hbm / steps:.2f} B per active particle-step**,
+  against 768 B per step of algorithmic field gathers (2 gathers x 8 nodes x 12 FP32 components): the
+  gathers are served by the caches, and the HBM traffic is essentially the particle state, read and written
+  once per 64-step launch.
+* L2: {traffic['l2_requests_per_particle_step']:.4f} requests per particle-step, hit rate {traffic['l2_hit_rate']:.3f}.
+""")
+    print(json.dumps({"valu": VALU_JSON, "traffic": TRAFFIC_JSON, "kernel_hash": h,
+                      "valu_instructions_per_particle_step": iv, "valu_busy": valu["valu_busy"],
+                      "hbm_bytes_per_particle_step": traffic["hbm_bytes_per_particle_step"]}))
+
+
 def push_roofline(args, c):
     """Roofline of the dominant kernel, the throughput form of the push
     (gc::k_push): bound by its VALU issue (profiles/push_valu.json).  achieved =
@@ -756,7 +967,12 @@ def main():
     ap.add_argument("--no-whole-job", action="store_true", help="skip the whole-24 h sub-record")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched graph-versus-eager sub-record")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision-form table")
+    ap.add_argument("--summarize-push-pmc", metavar="DIR", default=None,
+                    help="write the push counter summaries under profiles/ from rocprofv3 passes in DIR (no GPU)")
     args = ap.parse_args()
+    if args.summarize_push_pmc:
+        summarize_push_pmc(args.summarize_push_pmc)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the guiding-centre push is data-parallel over particles "

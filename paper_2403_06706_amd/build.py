@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgcpush.so")
-SOURCES = ["gc_api.cpp", "gc_push.hip", "gc_push_mlp.hip", "gc_kernels.hip", "gc_order.hip", "gc_mlp.hip", "gc_probe.hip"]
+SOURCES = ["gc_api.cpp", "gc_push.hip", "gc_push_mlp.hip", "gc_kernels.hip", "gc_moments.hip", "gc_order.hip", "gc_mlp.hip", "gc_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -21,7 +21,7 @@ hipError_t launch_push(const PushArgs &a, int precision, int block, bool persist
 // gather ceiling (gc_probe.hip): sink[slot] for every slot below *a.n_active
 hipError_t launch_gather_probe(const PushArgs &a, double *sink, int block, hipStream_t s);
 
-// injection, moments, state copies, fills (gc_kernels.hip)
+// injection, state copies, fills (gc_kernels.hip); moments (gc_moments.hip)
 hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, uint32_t n0, uint32_t n,
                          uint32_t first_id, uint32_t eidx, hipStream_t s);
 hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
