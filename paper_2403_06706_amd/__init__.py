@@ -166,13 +166,19 @@ class Context:
         return self._stream
 
     # Library work runs on the context's stream; torch work on the caller's
-    # current stream.  Order them explicitly around buffers that cross.
+    # current stream.  Order them explicitly around buffers that cross (on one
+    # stream the order is already the issue order, and a wait would only add a
+    # marker packet to the queue).
     def _inputs_ready(self):
-        self._stream.wait_stream(_torch().cuda.current_stream(self.device))
+        cur = _torch().cuda.current_stream(self.device)
+        if cur != self._stream:
+            self._stream.wait_stream(cur)
 
     def _outputs_ready(self, *tensors):
         torch = _torch()
         cur = torch.cuda.current_stream(self.device)
+        if cur == self._stream:
+            return
         for t in tensors:
             t.record_stream(self._stream)
         cur.wait_stream(self._stream)

@@ -187,7 +187,8 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     carve(m[0], cap, na);
     carve(m[1], cap, nb);
     const uint32_t max_blocks = (uint32_t)((cap + kSortTile - 1) / kSortTile);
-    const size_t sort_bytes = (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + 256 * 4 + (cap / 256 + 64) * 4;
+    const size_t look_bytes = (size_t)max_blocks * 256 * sizeof(unsigned long long);
+    const size_t sort_bytes = look_bytes + (size_t)cap * 4 * 4 + (size_t)256 * max_blocks * 4 + kStWords * 4;
     void *sm = nullptr;
     if (dalloc(ctx, (void **)&sm, sort_bytes) != hipSuccess) {
         dfree(ctx, m[0]);
@@ -220,6 +221,8 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
         }                                                                                              \
     } while (0)
     if (log) RESERVE_CHK(launch_fill_u32(log, 0xFFFFFFFFu, (size_t)cap * ctx->opt.log_depth, s));
+    // look-back words and sort state start at zero (never a valid look-back tag)
+    RESERVE_CHK(launch_fill_u32(static_cast<uint32_t *>(sm), 0u, sort_bytes / 4, s));
     if (ctx->n > 0) {
         // keep the current state (and log) of the first n slots
         double **src_d[kNumDoubleArrays] = {&ctx->A.r, &ctx->A.th, &ctx->A.ph, &ctx->A.u, &ctx->A.mu, &ctx->A.fr,
@@ -249,15 +252,16 @@ gc_status reserve(gc_ctx *ctx, uint64_t need) {
     ctx->A = na;
     ctx->B = nb;
     ctx->scratch_mem = sm;
-    uint32_t *p = static_cast<uint32_t *>(sm);
+    ctx->sc.look = static_cast<unsigned long long *>(sm);
+    uint32_t *p = reinterpret_cast<uint32_t *>(static_cast<char *>(sm) + look_bytes);
     ctx->sc.keys[0] = p;
     ctx->sc.keys[1] = p + cap;
     ctx->sc.vals[0] = p + 2 * cap;
     ctx->sc.vals[1] = p + 3 * cap;
     ctx->sc.counts = p + 4 * cap;
-    ctx->sc.totals = ctx->sc.counts + (size_t)256 * max_blocks;
-    ctx->sc.block_alive = ctx->sc.totals + 256;
+    ctx->sc.state = ctx->sc.counts + (size_t)256 * max_blocks;
     ctx->sc.max_blocks = max_blocks;
+    ctx->sc.sorted_keys = ctx->sc.keys[0];
     ctx->log = log;
     ctx->cap = cap;
     ctx->bound_dirty = true;
@@ -326,20 +330,20 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
         ctx->order_known = ctx->keys_known = false;
         return GC_OK;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed) {
-        e0 = take_event(ctx);
-        e1 = take_event(ctx);
-        HIPCHK(hipEventRecord(e0, s));
-    }
     if (ctx->bound_dirty) {
         HIPCHK(launch_set_count(ctx->n_bound, n, s));
         ctx->bound_dirty = false;
     }
+    // timed from the start of the first reorder kernel to the end of the last
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = take_event(ctx);
+        e1 = take_event(ctx);
+    }
     const bool comp = ctx->opt.precision == GC_PREC_F32_KAHAN;
     uint32_t *perm = nullptr;
     if (order == GC_ORDER_COMPACT) {
-        HIPCHK(launch_compact(ctx->A, ctx->n_bound, n, ctx->sc, ctx->n_active, &perm, s));
+        HIPCHK(launch_compact(ctx->A, ctx->n_bound, n, ctx->sc, ctx->n_active, &perm, s, e0));
     } else {
         const int c = ctx->opt.bin_coarsen;
         const uint32_t nrc = ((uint32_t)ctx->f.nr + (1u << c) - 1) >> c;
@@ -347,22 +351,19 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
         const uint32_t nphc = ((uint32_t)ctx->f.nph + (1u << c) - 1) >> c;
         const uint32_t dead = nrc * nthc * nphc;
         ctx->sorted_dead = dead;
-        HIPCHK(launch_cell_keys(ctx->A, ctx->f, ctx->n_bound, n, c, dead, ctx->sc.keys[0], ctx->sc.block_alive,
-                                ctx->n_active, s));
-        HIPCHK(launch_radix_sort(ctx->sc, ctx->n_bound, n, (int)bits_for(dead), &perm, s));
+        const int bits = (int)bits_for(dead);
+        HIPCHK(launch_cell_keys(ctx->A, ctx->f, ctx->n_bound, n, c, dead, bits, ctx->sc, ctx->n_active, s, e0));
+        HIPCHK(launch_radix_sort(ctx->sc, ctx->n_bound, n, bits, ctx->n_active, &perm, s));
     }
     HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
     // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
     HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, s));
-    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->count_host, ctx->sorted_n, s));
+    HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->count_host, ctx->sorted_n, ctx->sc.state, s, e1));
     ctx->order_known = true;
     ctx->keys_known = order == GC_ORDER_BIN;
     std::swap(ctx->A, ctx->B);
     std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
-    if (timed) {
-        HIPCHK(hipEventRecord(e1, s));
-        ctx->ev_reorder.emplace_back(e0, e1);
-    }
+    if (timed) ctx->ev_reorder.emplace_back(e0, e1);
     return GC_OK;
 }
 
@@ -390,20 +391,23 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     a.tail = pers && ctx->opt.field_source == GC_SOURCE_GRID ? (uint32_t)ctx->opt.tail_threshold : 0u;
     const int grid_blocks = ctx->n_cus * (1024 / ctx->opt.block_size);
     if (pers) HIPCHK(launch_fill_u32(ctx->queue, 0u, 1, s));
+    // grid push: the events are attached to the push kernels' own dispatches
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         e0 = take_event(ctx);
         e1 = take_event(ctx);
-        HIPCHK(hipEventRecord(e0, s));
     }
-    if (ctx->opt.field_source == GC_SOURCE_MLP)
+    if (ctx->opt.field_source == GC_SOURCE_MLP) {
+        if (timed) HIPCHK(hipEventRecord(e0, s));
         HIPCHK(launch_push_mlp(a, ctx->mlp.args, ctx->opt.precision, s));
-    else
-        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, form, grid_blocks, s));
-    if (timed) {
-        HIPCHK(hipEventRecord(e1, s));
-        ctx->ev_push.push_back({e0, e1, form});
+        if (timed) HIPCHK(hipEventRecord(e1, s));
+    } else {
+        LaunchEvents ev;
+        ev.start = e0;
+        ev.stop = e1;
+        HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, form, grid_blocks, s, ev));
     }
+    if (timed) ctx->ev_push.push_back({e0, e1, form});
     return GC_OK;
 }
 
@@ -960,6 +964,9 @@ gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out) {
     }
     unsigned long long steps[kPushForms] = {0, 0, 0};
     HIPCHK(hipMemcpy(steps, ctx->steps, sizeof steps, hipMemcpyDeviceToHost));
+    uint32_t sort_error = 0;
+    if (ctx->sc.state) HIPCHK(hipMemcpy(&sort_error, ctx->sc.state + kStError, 4, hipMemcpyDeviceToHost));
+    if (sort_error) return fail(ctx, GC_EDEVICE, "a radix-sort pass gave up waiting for a tile: the particle order is invalid");
     for (int f = 0; f < kPushForms; ++f) {
         out->form_steps[f] = steps[f];
         out->particle_steps += steps[f];

@@ -4,6 +4,9 @@
 //    inactive particles get the largest key; LSD radix sort (8-bit digits) of
 //    (key, slot) pairs; permute the state.  Particles of one cell then sit in
 //    consecutive lanes, so their trilinear gathers hit the same cache lines.
+//    The key kernel also counts the digits of every pass; each pass is then
+//    one kernel that ranks its tile, finds the tile's offset per digit by
+//    looking back over the tiles before it, and scatters.
 //  * compaction: stable partition active-first from wavefront ballots.
 // Both produce perm[dst] = src and leave the active count on the device.
 #include <hip/hip_runtime.h>
@@ -22,161 +25,221 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_cell_keys(SoA st, FieldDev f, const uint32_t *np, int coarsen,
-                                                   uint32_t dead_key, uint32_t *keys, uint32_t *block_alive) {
-    __shared__ uint32_t wsum[4];
-    const uint32_t n = *np;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool alive = false;
-    if (i < n) {
-        uint32_t key = dead_key;
-        if (st.status[i] == GC_ACTIVE) {
-            alive = true;
-            const double x = (st.r[i] - f.r_min) * f.inv_dr;
-            const double y = st.th[i] * f.inv_dth - 0.5;
-            const double z = st.ph[i] * f.inv_dph;
-            double fi = clampr(floor(x), 0.0, (double)(f.nr - 2));
-            double fj = clampr(floor(y), 0.0, (double)(f.nth - 2));
-            double zf = floor(z);
-            double km = zf - (double)f.nph * floor(zf * f.inv_nph);
-            km = km < 0.0 ? km + f.nph : km;
-            km = km >= f.nph ? km - f.nph : km;
-            km = clampr(km, 0.0, (double)(f.nph - 1));
-            if (!(isfinite(x) && isfinite(y) && isfinite(z))) { fi = 0.0; fj = 0.0; km = 0.0; }
-            const uint32_t nthc = ((uint32_t)f.nth + (1u << coarsen) - 1) >> coarsen;
-            const uint32_t nphc = ((uint32_t)f.nph + (1u << coarsen) - 1) >> coarsen;
-            key = (((uint32_t)fi >> coarsen) * nthc + ((uint32_t)fj >> coarsen)) * nphc + ((uint32_t)km >> coarsen);
-        }
-        keys[i] = key;
-    }
-    const uint64_t b = __ballot(alive);
-    if ((threadIdx.x & 63u) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(b);
-    __syncthreads();
-    if (threadIdx.x == 0) block_alive[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+__device__ __forceinline__ uint32_t cell_key(const SoA &st, const FieldDev &f, uint32_t i, int coarsen,
+                                             uint32_t dead_key, bool &alive) {
+    alive = st.status[i] == GC_ACTIVE;
+    if (!alive) return dead_key;
+    const double x = (st.r[i] - f.r_min) * f.inv_dr;
+    const double y = st.th[i] * f.inv_dth - 0.5;
+    const double z = st.ph[i] * f.inv_dph;
+    double fi = clampr(floor(x), 0.0, (double)(f.nr - 2));
+    double fj = clampr(floor(y), 0.0, (double)(f.nth - 2));
+    double zf = floor(z);
+    double km = zf - (double)f.nph * floor(zf * f.inv_nph);
+    km = km < 0.0 ? km + f.nph : km;
+    km = km >= f.nph ? km - f.nph : km;
+    km = clampr(km, 0.0, (double)(f.nph - 1));
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) { fi = 0.0; fj = 0.0; km = 0.0; }
+    const uint32_t nthc = ((uint32_t)f.nth + (1u << coarsen) - 1) >> coarsen;
+    const uint32_t nphc = ((uint32_t)f.nph + (1u << coarsen) - 1) >> coarsen;
+    return (((uint32_t)fi >> coarsen) * nthc + ((uint32_t)fj >> coarsen)) * nphc + ((uint32_t)km >> coarsen);
 }
 
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint32_t *v, uint32_t nb, uint32_t *n_active);
+// lanes of the wavefront whose valid digit equals this lane's
+__device__ __forceinline__ uint64_t same_digit(uint32_t d, bool valid) {
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1u);
+        same &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    return same;
+}
+
+// Keys of the live prefix, one sort tile per workgroup; the digit counts of
+// every pass and the number of active particles are added to the sort state
+// (which the reset at the end of the previous reorder left at zero).
+__global__ __launch_bounds__(kRsThreads) void k_cell_keys(SoA st, FieldDev f, const uint32_t *np, int coarsen,
+                                                         uint32_t dead_key, int passes, uint32_t *keys,
+                                                         uint32_t *state) {
+    __shared__ uint32_t h[kMaxPasses][256];
+    __shared__ uint32_t wsum[kWaves];
+    const uint32_t n = *np, tid = threadIdx.x;
+    for (int p = 0; p < kMaxPasses; ++p) h[p][tid] = 0;
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    uint32_t alive_n = 0;
+    for (int it = 0; it < kRsItems; ++it) {
+        const uint32_t i = blockIdx.x * kSortTile + it * kRsThreads + tid;
+        const bool valid = i < n;
+        bool alive = false;
+        uint32_t key = 0;
+        if (valid) {
+            key = cell_key(st, f, i, coarsen, dead_key, alive);
+            keys[i] = key;
+        }
+        alive_n += alive ? 1u : 0u;
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (key >> (8 * p)) & 255u;
+            const uint64_t same = same_digit(d, valid);
+            if (valid && (same & lt) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(same));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) alive_n += __shfl_xor(alive_n, off);
+    if ((tid & 63u) == 0) wsum[tid >> 6] = alive_n;
+    __syncthreads();
+    for (int p = 0; p < passes; ++p)
+        if (h[p][tid]) atomicAdd(&state[kStHist + p * 256 + tid], h[p][tid]);
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kWaves; ++w) t += wsum[w];
+        if (t) atomicAdd(&state[kStAlive], t);
+    }
+}
 
 hipError_t launch_cell_keys(const SoA &st, const FieldDev &f, const uint32_t *np, uint32_t n_max, int coarsen,
-                            uint32_t dead_key, uint32_t *keys, uint32_t *block_alive, uint32_t *n_active,
-                            hipStream_t s) {
-    if (n_max == 0) return launch_fill_u32(n_active, 0u, 1, s);
-    const uint32_t nb = (n_max + 255) / 256;
-    hipLaunchKernelGGL(k_cell_keys, dim3(nb), dim3(256), 0, s, st, f, np, coarsen, dead_key, keys, block_alive);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, block_alive, nb, n_active);   // total -> n_active
+                            uint32_t dead_key, int bits, OrderScratch &sc, uint32_t *n_active, hipStream_t s,
+                            hipEvent_t start) {
+    if (n_max == 0) {
+        if (start) (void)hipEventRecord(start, s);
+        return launch_fill_u32(n_active, 0u, 1, s);
+    }
+    const int passes = (bits + 7) / 8;
+    const uint32_t nb = (n_max + kSortTile - 1) / kSortTile;
+    if (passes > kMaxPasses || nb > sc.max_blocks) return hipErrorInvalidValue;
+    launch_timed(k_cell_keys, dim3(nb), dim3(kRsThreads), s, start, nullptr, st, f, np, coarsen, dead_key, passes,
+                 sc.keys[0], sc.state);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort, one 8-bit digit per pass: histogram per block, scan per
-// digit across blocks, stable scatter with per-wavefront ranking by ballots.
-// counts layout: [digit][block].
+// LSD radix sort, one 8-bit digit per pass, one kernel per pass.  A workgroup
+// takes the next tile in start order from a ticket counter, ranks its 2,048
+// items stably (per wavefront by ballots, then across wavefronts and item
+// rounds in LDS) and publishes its count per digit.  Its offset per digit
+// among the tiles before it comes from looking back over their published
+// words: an inclusive prefix ends the walk, an aggregate adds to it and the
+// walk goes on.  A tile waits only for tiles that took their tickets before it
+// and so are already running; each publishes its aggregate before it waits
+// itself, so every wait ends.  Look-back words carry a tag (reorder epoch and
+// pass), so words of earlier passes read as not yet published and the array
+// never needs clearing; the tag repeats after 2^28 reorders.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t *keys, const uint32_t *np, int shift,
-                                                       uint32_t *counts, uint32_t nblocks) {
-    __shared__ uint32_t h[256];
-    const uint32_t n = *np;
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t base = blockIdx.x * kSortTile;
-    for (int it = 0; it < kRsItems; ++it) {
-        const uint32_t i = base + it * kRsThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    counts[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+constexpr uint32_t kFlagAgg = 1, kFlagPrefix = 2;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ unsigned long long look_word(uint32_t tag, uint32_t flag, uint32_t v) {
+    return ((unsigned long long)(tag & 0x3FFFFFFFu) << 34) | ((unsigned long long)flag << 32) | v;
 }
 
-// one workgroup per digit: exclusive scan of counts[d][0..nblocks) in place
-__global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t *counts, uint32_t nblocks, uint32_t *totals) {
-    __shared__ uint32_t sh[kRsThreads];
-    uint32_t *row = counts + (size_t)blockIdx.x * nblocks;
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nblocks; base += kRsThreads) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t v = i < nblocks ? row[i] : 0u;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < kRsThreads; off <<= 1) {
-            const uint32_t t = threadIdx.x >= (uint32_t)off ? sh[threadIdx.x - off] : 0u;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nblocks) row[i] = carry + sh[threadIdx.x] - v;
-        carry += sh[kRsThreads - 1];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
-}
-
-__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t *keys_in, const uint32_t *vals_in,
-                                                          uint32_t *keys_out, uint32_t *vals_out,
-                                                          const uint32_t *np, int shift, const uint32_t *counts,
-                                                          const uint32_t *totals, uint32_t nblocks) {
-    const uint32_t n = *np;
-    if (blockIdx.x * kSortTile >= n) return;   // no slot of this tile is live
-    __shared__ uint32_t base[256];          // running output offset per digit for this block
-    __shared__ uint32_t wcnt[kWaves][256];  // per-wave digit counts, then per-wave offsets
-    __shared__ uint32_t tot[256];
+__global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint32_t *keys_in, const uint32_t *vals_in,
+                                                       uint32_t *keys_out, uint32_t *vals_out, const uint32_t *np,
+                                                       int pass, uint32_t *state, unsigned long long *look,
+                                                       uint32_t *n_active) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t wcnt[kRsItems][kWaves][256];   // per (round, wave, digit): count, then offset in the tile
+    __shared__ uint32_t s_base[256];
     const uint32_t tid = threadIdx.x, wave = tid >> 6;
-    tot[tid] = totals[tid];
-    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
-    if (tid == 0) {   // exclusive scan of the 256 digit totals
-        uint32_t run = 0;
-        for (int d = 0; d < 256; ++d) { const uint32_t t = tot[d]; tot[d] = run; run += t; }
+    if (tid == 0) {
+        s_tile = atomicAdd(&state[kStTicket + pass], 1u);
+        if (pass == 0 && s_tile == 0) *n_active = state[kStAlive];
     }
     __syncthreads();
-    base[tid] = tot[tid] + counts[(size_t)tid * nblocks + blockIdx.x];
+    const uint32_t tile = s_tile, n = *np;
+    if (tile * kSortTile >= n) return;   // past the live prefix (uniform over the workgroup)
+    const uint32_t tag = (state[kStEpoch] + 1u) * 4u + (uint32_t)pass;
+    const int shift = 8 * pass;
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it)
+        for (int w = 0; w < kWaves; ++w) wcnt[it][w][tid] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
-    for (int it = 0; it < kRsItems; ++it) {
-        const uint32_t i = blockIdx.x * kSortTile + it * kRsThreads + tid;
-        const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const uint32_t val = valid ? (vals_in ? vals_in[i] : i) : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-        // lanes of this wave holding the same digit
-        uint64_t same = __ballot(valid);
+    uint32_t key[kRsItems], val[kRsItems], rank[kRsItems];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const uint64_t bb = __ballot((d >> b) & 1u);
-            same &= ((d >> b) & 1u) ? bb : ~bb;
+    for (int it = 0; it < kRsItems; ++it) {
+        const uint32_t i = tile * kSortTile + it * kRsThreads + tid;
+        const bool valid = i < n;
+        key[it] = valid ? keys_in[i] : 0xFFFFFFFFu;
+        val[it] = valid ? (vals_in ? vals_in[i] : i) : 0u;
+        const uint32_t d = (key[it] >> shift) & 255u;
+        const uint64_t same = same_digit(d, valid);
+        rank[it] = (uint32_t)__popcll(same & lt);
+        if (valid && rank[it] == 0) wcnt[it][wave][d] = (uint32_t)__popcll(same);
+    }
+    __syncthreads();
+    // thread tid owns digit tid: offsets of each (round, wave) within the tile
+    uint32_t count = 0;
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it)
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = wcnt[it][w][tid];
+            wcnt[it][w][tid] = count;
+            count += c;
         }
-        const uint32_t rank = (uint32_t)__popcll(same & lt);
-        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(same);
-        __syncthreads();
-        {   // per digit: offsets of each wave, advance the running base
-            uint32_t run = base[tid];
-            for (int w = 0; w < kWaves; ++w) { const uint32_t c = wcnt[w][tid]; wcnt[w][tid] = run; run += c; }
-            base[tid] = run;
+    unsigned long long *mine = look + (size_t)tile * 256 + tid;
+    uint32_t prefix = 0;
+    if (tile == 0) {
+        __hip_atomic_store(mine, look_word(tag, kFlagPrefix, count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(mine, look_word(tag, kFlagAgg, count), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long want = (unsigned long long)(tag & 0x3FFFFFFFu);
+        uint32_t j = tile - 1, spins = 0;
+        for (;;) {
+            const unsigned long long w =
+                __hip_atomic_load(look + (size_t)j * 256 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t flag = (uint32_t)(w >> 32) & 3u;
+            if ((w >> 34) == want && flag != 0) {
+                prefix += (uint32_t)w;
+                if (flag == kFlagPrefix || j == 0) break;
+                --j;
+            } else if (++spins > kSpinLimit) {
+                atomicOr(&state[kStError], 1u);   // reported by the next synchronizing call
+                break;
+            } else {
+                __builtin_amdgcn_s_sleep(1);
+            }
         }
+        __hip_atomic_store(mine, look_word(tag, kFlagPrefix, prefix + count), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // global start of each digit: exclusive scan of this pass's digit totals
+    const uint32_t tot = state[kStHist + pass * 256 + tid];
+    s_base[tid] = tot;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t t = tid >= (uint32_t)off ? s_base[tid - off] : 0u;
         __syncthreads();
-        if (valid) {
-            const uint32_t pos = wcnt[wave][d] + rank;
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+        s_base[tid] += t;
+        __syncthreads();
+    }
+    const uint32_t start = s_base[tid] - tot + prefix;
+    __syncthreads();
+    s_base[tid] = start;
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRsItems; ++it) {
+        const uint32_t i = tile * kSortTile + it * kRsThreads + tid;
+        if (i < n) {
+            const uint32_t d = (key[it] >> shift) & 255u;
+            const uint32_t pos = s_base[d] + wcnt[it][wave][d] + rank[it];
+            if (pos < n) {   // always, with digit counts of these keys
+                keys_out[pos] = key[it];
+                vals_out[pos] = val[it];
+            }
         }
-        __syncthreads();
-        for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
     }
 }
 
-hipError_t launch_radix_sort(OrderScratch &sc, const uint32_t *np, uint32_t n_max, int bits, uint32_t **perm_out,
-                             hipStream_t s) {
+hipError_t launch_radix_sort(OrderScratch &sc, const uint32_t *np, uint32_t n_max, int bits, uint32_t *n_active,
+                             uint32_t **perm_out, hipStream_t s) {
     const uint32_t nblocks = (n_max + kSortTile - 1) / kSortTile;
-    if (nblocks > sc.max_blocks) return hipErrorInvalidValue;
+    const int passes = (bits + 7) / 8;
+    if (nblocks > sc.max_blocks || passes > kMaxPasses) return hipErrorInvalidValue;
     int cur = 0;
     const uint32_t *vals_in = nullptr;
-    for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(kRsThreads), 0, s, sc.keys[cur], np, shift, sc.counts,
-                           nblocks);
-        hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(kRsThreads), 0, s, sc.counts, nblocks, sc.totals);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(kRsThreads), 0, s, sc.keys[cur], vals_in,
-                           sc.keys[cur ^ 1], sc.vals[cur ^ 1], np, shift, sc.counts, sc.totals, nblocks);
+    for (int p = 0; p < passes && nblocks > 0; ++p) {
+        hipLaunchKernelGGL(k_rs_pass, dim3(nblocks), dim3(kRsThreads), 0, s, sc.keys[cur], vals_in, sc.keys[cur ^ 1],
+                           sc.vals[cur ^ 1], np, p, sc.state, sc.look, n_active);
         vals_in = sc.vals[cur ^ 1];
         cur ^= 1;
     }
@@ -244,11 +307,14 @@ __global__ __launch_bounds__(256) void k_compact_scatter(const uint32_t *status,
 }
 
 hipError_t launch_compact(const SoA &st, const uint32_t *np, uint32_t n_max, OrderScratch &sc, uint32_t *n_active,
-                          uint32_t **perm_out, hipStream_t s) {
+                          uint32_t **perm_out, hipStream_t s, hipEvent_t start) {
     const uint32_t nb = (n_max + 255) / 256;
-    if (nb == 0) return launch_fill_u32(n_active, 0u, 1, s);
+    if (nb == 0) {
+        if (start) (void)hipEventRecord(start, s);
+        return launch_fill_u32(n_active, 0u, 1, s);
+    }
     if (nb > 256u * sc.max_blocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(256), 0, s, st.status, np, sc.counts);
+    launch_timed(k_compact_count, dim3(nb), dim3(256), s, start, nullptr, st.status, np, sc.counts);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, sc.counts, nb, n_active);
     hipLaunchKernelGGL(k_compact_scatter, dim3(nb), dim3(256), 0, s, st.status, np, sc.counts, n_active, sc.vals[0]);
     *perm_out = sc.vals[0];
@@ -298,16 +364,28 @@ hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo,
     return hipGetLastError();
 }
 
-__global__ void k_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, uint32_t *prev) {
-    const uint32_t v = *src;
-    if (prev) *prev = *dst;
-    *dst = v;
-    if (host_mirror) *host_mirror = v;
+// *dst = *src (and the host mirror and previous value), then the sort state is
+// made ready for the next reorder: digit counts, active count and tickets
+// cleared, epoch advanced.
+__global__ __launch_bounds__(256) void k_copy_count(uint32_t *dst, const uint32_t *src,
+                                                    volatile uint32_t *host_mirror, uint32_t *prev,
+                                                    uint32_t *state) {
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        const uint32_t v = *src;
+        if (prev) *prev = *dst;
+        *dst = v;
+        if (host_mirror) *host_mirror = v;
+        state[kStEpoch] += 1u;
+        state[kStAlive] = 0;
+    }
+    for (uint32_t i = tid; i < kMaxPasses * 256; i += 256) state[kStHist + i] = 0;
+    if (tid < kMaxPasses) state[kStTicket + tid] = 0;
 }
 
 hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, uint32_t *prev,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_count, dim3(1), dim3(1), 0, s, dst, src, host_mirror, prev);
+                             uint32_t *state, hipStream_t s, hipEvent_t stop) {
+    launch_timed(k_copy_count, dim3(1), dim3(256), s, nullptr, stop, dst, src, host_mirror, prev, state);
     return hipGetLastError();
 }
 

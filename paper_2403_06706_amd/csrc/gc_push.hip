@@ -309,56 +309,66 @@ __global__ __launch_bounds__(256) void k_push_persistent_quad(PushArgs a) {
 
 
 template <int PREC, int FDT, int MODE>
-static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
+static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s,
+                           LaunchEvents ev) {
     if (persistent) {
-        hipLaunchKernelGGL((k_push_persistent<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), 0, s, a);
+        const bool quad = a.tail > 0 && MODE != 2;
+        launch_timed((k_push_persistent<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), s, ev.start,
+                     a.tail > 0 ? nullptr : ev.stop, a);
         if (a.tail > 0) {
-            hipLaunchKernelGGL((k_push_persistent_allpairs<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), 0, s, a);
-            if (MODE != 2)   // 256-thread workgroups (64 particles per round), as the grid quad form
-                hipLaunchKernelGGL((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE>),
-                                   dim3((uint32_t)grid_blocks * block / 256), dim3(256), 0, s, a);
+            launch_timed((k_push_persistent_allpairs<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), s, nullptr,
+                         quad ? nullptr : ev.stop, a);
+            if (quad)   // 256-thread workgroups (64 particles per round), as the grid quad form
+                launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE>),
+                             dim3((uint32_t)grid_blocks * block / 256), dim3(256), s, nullptr, ev.stop, a);
         }
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
-        if (nb == 0) return hipSuccess;
+        if (nb == 0) {
+            if (ev.start) (void)hipEventRecord(ev.start, s);
+            if (ev.stop) (void)hipEventRecord(ev.stop, s);
+            return hipGetLastError();
+        }
         if (form == kFormQuad && MODE != 2) {
             // 256-thread workgroups whatever the block size (64 particles each;
             // measured faster for this form than 64 threads)
             const uint32_t qb = (4 * a.n_slots + 255) / 256;
-            hipLaunchKernelGGL((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE>), dim3(qb), dim3(256), 0, s, a);
+            launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE>), dim3(qb), dim3(256), s, ev.start, ev.stop, a);
         } else if (form != kFormThroughput)
-            hipLaunchKernelGGL((k_push_allpairs<PREC, FDT, MODE>), dim3(nb), dim3(block), 0, s, a);
+            launch_timed((k_push_allpairs<PREC, FDT, MODE>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
         else
-            hipLaunchKernelGGL((k_push<PREC, FDT, MODE>), dim3(nb), dim3(block), 0, s, a);
+            launch_timed((k_push<PREC, FDT, MODE>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
     }
     return hipGetLastError();
 }
 
 template <int PREC, int FDT>
-static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
+static hipError_t launch_t(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s,
+                           LaunchEvents ev) {
     switch (a.mode) {
-        case 0: return launch_r<PREC, FDT, 0>(a, block, persistent, form, grid_blocks, s);
-        case 1: return launch_r<PREC, FDT, 1>(a, block, persistent, form, grid_blocks, s);
-        default: return launch_r<PREC, FDT, 2>(a, block, persistent, form, grid_blocks, s);
+        case 0: return launch_r<PREC, FDT, 0>(a, block, persistent, form, grid_blocks, s, ev);
+        case 1: return launch_r<PREC, FDT, 1>(a, block, persistent, form, grid_blocks, s, ev);
+        default: return launch_r<PREC, FDT, 2>(a, block, persistent, form, grid_blocks, s, ev);
     }
 }
 
 template <int PREC>
-static hipError_t launch_p(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s) {
+static hipError_t launch_p(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s,
+                           LaunchEvents ev) {
     switch (a.f.dtype) {
-        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, form, grid_blocks, s);
-        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, form, grid_blocks, s);
-        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, form, grid_blocks, s);
+        case GC_F64: return launch_t<PREC, GC_F64>(a, block, persistent, form, grid_blocks, s, ev);
+        case GC_F32: return launch_t<PREC, GC_F32>(a, block, persistent, form, grid_blocks, s, ev);
+        case GC_F16: return launch_t<PREC, GC_F16>(a, block, persistent, form, grid_blocks, s, ev);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_push(const PushArgs &a, int precision, int block, bool persistent, int form, int grid_blocks,
-                       hipStream_t s) {
+                       hipStream_t s, LaunchEvents ev) {
     switch (precision) {
-        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, form, grid_blocks, s);
-        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, form, grid_blocks, s);
-        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, form, grid_blocks, s);
+        case GC_PREC_F64: return launch_p<GC_PREC_F64>(a, block, persistent, form, grid_blocks, s, ev);
+        case GC_PREC_F32_ACC64: return launch_p<GC_PREC_F32_ACC64>(a, block, persistent, form, grid_blocks, s, ev);
+        case GC_PREC_F32_KAHAN: return launch_p<GC_PREC_F32_KAHAN>(a, block, persistent, form, grid_blocks, s, ev);
     }
     return hipErrorInvalidValue;
 }
