@@ -81,6 +81,7 @@ struct gc_ctx {
     uint32_t *queue = nullptr;
     uint32_t *n_bound = nullptr;      // live prefix: slots at or past it hold no active particle
     uint32_t *sorted_n = nullptr;     // length of the prefix the last reorder sorted
+    unsigned long long *dead = nullptr;   // [6] sums over the slots past n_bound (moments [0..5])
     bool bound_dirty = true;          // the bound must be reset to n before the next reorder
     bool order_known = false;         // a reorder ran since the particle set last changed
     bool keys_known = false;          // ... and it was a cell binning (its keys are in sc.sorted_keys)
@@ -331,7 +332,7 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
         return GC_OK;
     }
     if (ctx->bound_dirty) {
-        HIPCHK(launch_set_count(ctx->n_bound, n, s));
+        HIPCHK(launch_reset_bound(ctx->n_bound, n, ctx->dead, s));
         ctx->bound_dirty = false;
     }
     // timed from the start of the first reorder kernel to the end of the last
@@ -357,7 +358,7 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     }
     HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
     // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
-    HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, s));
+    HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, ctx->dead, s));
     HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->count_host, ctx->sorted_n, ctx->sc.state, s, e1));
     ctx->order_known = true;
     ctx->keys_known = order == GC_ORDER_BIN;
@@ -582,8 +583,10 @@ gc_status gc_create(gc_ctx **out, const gc_options *opt) {
     ctx->n_bound = ctx->n_active + 2;
     ctx->sorted_n = ctx->n_active + 3;
     ctx->steps = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 64);
+    ctx->dead = reinterpret_cast<unsigned long long *>(static_cast<char *>(small) + 128);
     HIPCHK(launch_fill_u32(ctx->n_active, 0u, 4, ctx->stream));
     HIPCHK(launch_fill_u64(ctx->steps, 0ull, kPushForms, ctx->stream));
+    HIPCHK(launch_fill_u64(ctx->dead, 0ull, 8, ctx->stream));
     void *pinned = nullptr;
     HIPCHK(hipHostMalloc(&pinned, 64, hipHostMallocCoherent));
     ctx->count_host = static_cast<volatile uint32_t *>(pinned);
@@ -879,8 +882,11 @@ gc_status gc_moments(gc_ctx *ctx, const gc_moment_spec *s, int64_t *out) {
     m.len_unit = s->len_unit;
     m.min_birth = s->min_birth;
     m.accumulate = s->accumulate != 0;
+    // after a reorder only the live prefix is read; the sums over the slots
+    // past it are kept on the device by the reorders
     HIPCHK(launch_moments(ctx->A, ctx->f, ctx->ens_dev, (uint32_t)ctx->n, m,
-                          reinterpret_cast<unsigned long long *>(out), ctx->stream));
+                          reinterpret_cast<unsigned long long *>(out), ctx->bound_dirty ? nullptr : ctx->n_bound,
+                          ctx->bound_dirty ? nullptr : ctx->dead, ctx->stream));
     return GC_OK;
 }
 

@@ -44,8 +44,12 @@ hipError_t launch_gather_probe(const PushArgs &a, double *sink, int block, hipSt
 // injection, state copies, fills (gc_kernels.hip); moments (gc_moments.hip)
 hipError_t launch_inject(const SoA &st, const FieldDev &f, const EnsDev &e, uint32_t n0, uint32_t n,
                          uint32_t first_id, uint32_t eidx, hipStream_t s);
+// n_scan (device, nullable): only slots [0, *n_scan) are read, and dead (device,
+// nullable) holds the sums [0..5] over the slots past it (particles per status,
+// collision counts, steps), added to out; else all n slots are read
 hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
-                          unsigned long long *out, hipStream_t s);
+                          unsigned long long *out, const uint32_t *n_scan, const unsigned long long *dead,
+                          hipStream_t s);
 hipError_t launch_state_out(const SoA &st, const gc_state_view &dst, uint32_t n, hipStream_t s);
 hipError_t launch_state_in(const SoA &st, const gc_state_view &src, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
@@ -90,8 +94,12 @@ hipError_t launch_compact(const SoA &st, const uint32_t *np, uint32_t n_max, Ord
                           uint32_t **perm_out, hipStream_t s, hipEvent_t start = nullptr);
 hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *np, uint32_t n_max,
                           bool with_comp, hipStream_t s);
+// dst[i] = src[i] for i in [*lo, *hi); with dead set, the per-status counts,
+// collision counts and steps of those slots are added to dead[0..5]
 hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,
-                             bool with_comp, hipStream_t s);
+                             bool with_comp, unsigned long long *dead, hipStream_t s);
+// *n_bound = n and dead[0..5] = 0: the live prefix is every slot again
+hipError_t launch_reset_bound(uint32_t *n_bound, uint32_t n, unsigned long long *dead, hipStream_t s);
 // *dst = *src; also *host_mirror = *src when host_mirror (host-coherent pinned memory) is set,
 // and *prev = the old *dst when prev is set; then resets the sort state for the next reorder
 hipError_t launch_copy_count(uint32_t *dst, const uint32_t *src, volatile uint32_t *host_mirror, uint32_t *prev,

@@ -24,8 +24,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 }
 
 template <int FDT>
-__global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, MomDev m, unsigned long long *out) {
+__global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n_all, MomDev m, unsigned long long *out,
+                          const uint32_t *n_scan, const unsigned long long *dead) {
     extern __shared__ unsigned long long h[];
+    const uint32_t n = n_scan ? *n_scan : n_all;
+    if (blockIdx.x > 0 && blockIdx.x * blockDim.x >= n) return;   // nothing to read (uniform)
     for (int i = threadIdx.x; i < m.total; i += blockDim.x) h[i] = 0ull;
     __syncthreads();
     unsigned long long *rb = h + 8;
@@ -84,18 +87,21 @@ __global__ void k_moments(SoA st, FieldDev f, const EnsDev *ens, uint32_t n, Mom
     __syncthreads();
     for (int i = threadIdx.x; i < m.total; i += blockDim.x)
         if (h[i]) atomicAdd(&out[i], h[i]);
+    // slots past the live prefix: their sums, kept by the reorders
+    if (dead && blockIdx.x == 0 && threadIdx.x < 6 && dead[threadIdx.x]) atomicAdd(&out[threadIdx.x], dead[threadIdx.x]);
 }
 
 hipError_t launch_moments(const SoA &st, const FieldDev &f, const EnsDev *ens, uint32_t n, const MomDev &m,
-                          unsigned long long *out, hipStream_t s) {
+                          unsigned long long *out, const uint32_t *n_scan, const unsigned long long *dead,
+                          hipStream_t s) {
     hipError_t e = m.accumulate ? hipSuccess : launch_fill_u64(out, 0ull, (size_t)m.total, s);
     if (e != hipSuccess || n == 0) return e;
     const dim3 grid(std::min<uint32_t>((n + 255) / 256, 1024u)), block(256);
     const size_t lds = (size_t)m.total * sizeof(unsigned long long);
     switch (f.dtype) {
-        case GC_F64: hipLaunchKernelGGL(k_moments<GC_F64>, grid, block, lds, s, st, f, ens, n, m, out); break;
-        case GC_F32: hipLaunchKernelGGL(k_moments<GC_F32>, grid, block, lds, s, st, f, ens, n, m, out); break;
-        default:     hipLaunchKernelGGL(k_moments<GC_F16>, grid, block, lds, s, st, f, ens, n, m, out); break;
+        case GC_F64: hipLaunchKernelGGL(k_moments<GC_F64>, grid, block, lds, s, st, f, ens, n, m, out, n_scan, dead); break;
+        case GC_F32: hipLaunchKernelGGL(k_moments<GC_F32>, grid, block, lds, s, st, f, ens, n, m, out, n_scan, dead); break;
+        default:     hipLaunchKernelGGL(k_moments<GC_F16>, grid, block, lds, s, st, f, ens, n, m, out, n_scan, dead); break;
     }
     return hipGetLastError();
 }

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(kRsThreads) void k_cell_keys(SoA st, FieldDev f, co
     __shared__ uint32_t h[kMaxPasses][256];
     __shared__ uint32_t wsum[kWaves];
     const uint32_t n = *np, tid = threadIdx.x;
+    if (blockIdx.x * kSortTile >= n) return;   // tile past the live prefix (uniform)
     for (int p = 0; p < kMaxPasses; ++p) h[p][tid] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
@@ -140,13 +141,20 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_pass(const uint32_t *keys_in,
     __shared__ uint32_t wcnt[kRsItems][kWaves][256];   // per (round, wave, digit): count, then offset in the tile
     __shared__ uint32_t s_base[256];
     const uint32_t tid = threadIdx.x, wave = tid >> 6;
+    const uint32_t n = *np;
+    // Only the first ceil(n / kSortTile) workgroups take tickets, so the tiles
+    // of the live prefix are taken once each, in start order; the others leave
+    // at once (workgroup 0 then publishes the active count of an empty prefix).
+    if (blockIdx.x * kSortTile >= n) {
+        if (pass == 0 && blockIdx.x == 0 && tid == 0) *n_active = state[kStAlive];
+        return;
+    }
     if (tid == 0) {
         s_tile = atomicAdd(&state[kStTicket + pass], 1u);
         if (pass == 0 && s_tile == 0) *n_active = state[kStAlive];
     }
     __syncthreads();
-    const uint32_t tile = s_tile, n = *np;
-    if (tile * kSortTile >= n) return;   // past the live prefix (uniform over the workgroup)
+    const uint32_t tile = s_tile;
     const uint32_t tag = (state[kStEpoch] + 1u) * 4u + (uint32_t)pass;
     const int shift = 8 * pass;
 #pragma unroll
@@ -347,26 +355,47 @@ hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, 
 // live prefix are never permuted again.  After a permute, the particles that
 // died since the last reorder (slots [*lo, *hi) of the new buffer) are copied
 // back into the other buffer, which keeps the two in agreement on the tail.
-__global__ void k_copy_range(SoA src, SoA dst, const uint32_t *lo, const uint32_t *hi, bool with_comp) {
+__global__ __launch_bounds__(256) void k_copy_range(SoA src, SoA dst, const uint32_t *lo, const uint32_t *hi,
+                                                    bool with_comp, unsigned long long *dead) {
     const uint32_t i = *lo + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *hi) return;
+    const bool in = i < *hi;
+    uint32_t status = 0xFFFFFFFFu;
+    unsigned long long k = 0, step = 0;
+    if (in) {
 #define T_(name) dst.name[i] = src.name[i];
-    T_(r) T_(th) T_(ph) T_(u) T_(mu) T_(fr) T_(fth) T_(fph) T_(fu) T_(dtp) T_(s) T_(ell) T_(t)
-    T_(k) T_(flags) T_(status) T_(step) T_(id) T_(ens) T_(gid) T_(birth)
-    if (with_comp) { T_(cr) T_(cth) T_(cph) T_(cu) T_(ct) }
+        T_(r) T_(th) T_(ph) T_(u) T_(mu) T_(fr) T_(fth) T_(fph) T_(fu) T_(dtp) T_(s) T_(ell) T_(t)
+        T_(k) T_(flags) T_(status) T_(step) T_(id) T_(ens) T_(gid) T_(birth)
+        if (with_comp) { T_(cr) T_(cth) T_(cph) T_(cu) T_(ct) }
 #undef T_
+        status = src.status[i];
+        k = src.k[i];
+        step = src.step[i];
+    }
+    if (!dead) return;
+    // the slots leave the live prefix for good: their sums join dead[]
+    unsigned long long cnt[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cnt[q] = (unsigned long long)__popcll(__ballot(in && status == (uint32_t)q));
+    for (int off = 32; off > 0; off >>= 1) {
+        k += __shfl_xor(k, off);
+        step += __shfl_xor(step, off);
+    }
+    if ((threadIdx.x & 63u) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cnt[q]) atomicAdd(&dead[q], cnt[q]);
+        if (k) atomicAdd(&dead[4], k);
+        if (step) atomicAdd(&dead[5], step);
+    }
 }
 
 hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,
-                             bool with_comp, hipStream_t s) {
+                             bool with_comp, unsigned long long *dead, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_range, dim3((n_max + 255) / 256), dim3(256), 0, s, src, dst, lo, hi, with_comp);
+    hipLaunchKernelGGL(k_copy_range, dim3((n_max + 255) / 256), dim3(256), 0, s, src, dst, lo, hi, with_comp, dead);
     return hipGetLastError();
 }
 
-// *dst = *src (and the host mirror and previous value), then the sort state is
-// made ready for the next reorder: digit counts, active count and tickets
-// cleared, epoch advanced.
 __global__ __launch_bounds__(256) void k_copy_count(uint32_t *dst, const uint32_t *src,
                                                     volatile uint32_t *host_mirror, uint32_t *prev,
                                                     uint32_t *state) {
@@ -406,6 +435,16 @@ hipError_t launch_keys_out(const uint32_t *sorted_keys, const uint32_t *sorted_n
 }
 
 __global__ void k_set_count(uint32_t *p, uint32_t v) { *p = v; }
+
+__global__ void k_reset_bound(uint32_t *n_bound, uint32_t n, unsigned long long *dead) {
+    if (threadIdx.x == 0) *n_bound = n;
+    if (threadIdx.x < 6) dead[threadIdx.x] = 0;
+}
+
+hipError_t launch_reset_bound(uint32_t *n_bound, uint32_t n, unsigned long long *dead, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_bound, dim3(1), dim3(64), 0, s, n_bound, n, dead);
+    return hipGetLastError();
+}
 
 hipError_t launch_set_count(uint32_t *n_active, uint32_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, n_active, n);

@@ -121,6 +121,22 @@ def oracle_to_state(p, m):
 GEN_SHIFT = 8     # device flags: generation in the bits from here up
 
 
+def state_to_oracle(st, m):
+    """A device state (state_to_numpy of gc_get_state, injection order) as
+    oracle particles (the inverse of oracle_to_state)."""
+    p = np.zeros(len(st["r"]), dtype=O.PARTICLE_DTYPE)
+    for k in ("r", "th", "ph", "u", "dtp", "s", "ell", "t"):
+        p[k] = st[k]
+    p["mu_B"] = st["mu"] * m
+    p["fp"] = np.stack([st["fr"], st["fth"], st["fph"], st["fu"]], axis=1)
+    for k in ("k", "status", "step", "id", "ens", "birth"):
+        p[k] = st[k]
+    flags = st["flags"].astype(np.uint32)
+    p["flags"] = flags & np.uint32((1 << GEN_SHIFT) - 1)
+    p["gen"] = flags >> np.uint32(GEN_SHIFT)
+    return p
+
+
 def generation(st):
     return st["flags"].astype(np.uint32) >> np.uint32(GEN_SHIFT)
 

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 import paper_2403_06706_amd as gcp
-from gpu_helpers import field_of, oracle_to_state, run_oracle, small, say, stored
+from gpu_helpers import field_of, oracle_to_state, run_oracle, small, say, state_to_oracle, stored
 from synthetic import AU, E_CHARGE
 
 pytestmark = pytest.mark.gpu
@@ -46,3 +46,41 @@ def test_moments_match_oracle(store):
     say(f"  moments counts {want[:8]}")
     _check(got, want, spec)
     assert want[8 + 3 * spec.n_rbins:].sum() > 100          # the histograms are populated
+
+
+@pytest.mark.parametrize("order", ["bin", "compact"])
+def test_moments_after_reorders_equal_the_oracle_of_the_device_state(order):
+    """After reorders have moved exited electrons past the live prefix, the
+    device reads only that prefix and adds the sums the reorders kept for the
+    slots past it: each snapshot, and their accumulated sum, must equal the
+    oracle's moments of the device's own state."""
+    import torch
+    wl = small(n=5000, hours=1.0)
+    f = stored(field_of(wl), "f64")
+    spec = O.MomentSpec(**SPEC)
+    of = O.Field(wl.grid, f)
+    tab = O.make_ens_table(wl.ensembles)
+    ctx = gcp.Context(device=0, order=order, chunk_steps=64)
+    ctx.load_field(wl.grid, f, "f64")
+    ctx.inject(wl.ensembles[0])
+    acc = torch.zeros(ctx.moments_size(spec), dtype=torch.int64, device="cuda:0")
+    want_sum = None
+    for rnd in range(3):
+        ctx.advance(wl.dt, 64 * 20)
+        got = ctx.moments(spec).cpu().numpy()
+        ctx.moments(spec, out=acc, accumulate=True)
+        p = state_to_oracle(gcp.state_to_numpy(ctx.get_state()), wl.ensembles[0].m)
+        want = O.moments(of, tab, p, spec)
+        say(f"  {order} snapshot {rnd}: counts {want[:8]}")
+        _check(got, want, spec)
+        want_sum = want if want_sum is None else want_sum + want
+    ctx.close()
+    assert want[1] > 0 and want[0] > 0          # exited electrons past the prefix, active ones in it
+    got_sum = acc.cpu().numpy()
+    nr = spec.n_rbins
+    fixed = np.zeros(len(want_sum), dtype=bool)
+    fixed[6] = True
+    fixed[8 + 1:8 + 3 * nr:3] = True
+    fixed[8 + 2:8 + 3 * nr:3] = True
+    assert np.array_equal(got_sum[~fixed], want_sum[~fixed])
+    assert np.all(np.abs(got_sum[fixed] - want_sum[fixed]) <= 3 * 5000)
