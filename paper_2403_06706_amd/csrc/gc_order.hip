@@ -357,8 +357,11 @@ hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, 
 // back into the other buffer, which keeps the two in agreement on the tail.
 __global__ __launch_bounds__(256) void k_copy_range(SoA src, SoA dst, const uint32_t *lo, const uint32_t *hi,
                                                     bool with_comp, unsigned long long *dead) {
-    const uint32_t i = *lo + blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = i < *hi;
+    __shared__ unsigned long long part[4][6];
+    const uint32_t b0 = *lo + blockIdx.x * blockDim.x, end = *hi;
+    if (b0 >= end) return;                        // workgroup past the range (uniform)
+    const uint32_t i = b0 + threadIdx.x;
+    const bool in = i < end;
     uint32_t status = 0xFFFFFFFFu;
     unsigned long long k = 0, step = 0;
     if (in) {
@@ -372,20 +375,25 @@ __global__ __launch_bounds__(256) void k_copy_range(SoA src, SoA dst, const uint
         step = src.step[i];
     }
     if (!dead) return;
-    // the slots leave the live prefix for good: their sums join dead[]
-    unsigned long long cnt[4];
+    // the slots leave the live prefix for good: their sums join dead[], one
+    // atomic per sum and workgroup
+    unsigned long long v[6];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cnt[q] = (unsigned long long)__popcll(__ballot(in && status == (uint32_t)q));
+    for (int q = 0; q < 4; ++q) v[q] = (unsigned long long)__popcll(__ballot(in && status == (uint32_t)q));
     for (int off = 32; off > 0; off >>= 1) {
         k += __shfl_xor(k, off);
         step += __shfl_xor(step, off);
     }
-    if ((threadIdx.x & 63u) == 0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (cnt[q]) atomicAdd(&dead[q], cnt[q]);
-        if (k) atomicAdd(&dead[4], k);
-        if (step) atomicAdd(&dead[5], step);
+    v[4] = k;
+    v[5] = step;
+    const uint32_t wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63u) == 0)
+        for (int q = 0; q < 6; ++q) part[wave][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const unsigned long long t = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                                     part[3][threadIdx.x];
+        if (t) atomicAdd(&dead[threadIdx.x], t);
     }
 }
 
