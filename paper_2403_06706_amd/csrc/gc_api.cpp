@@ -805,6 +805,12 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
     // would mostly pay for its fixed launches (a reorder every chunk); the chunks
     // then run eagerly with the tail policy (bitwise the same results).
     if (tail_mode(ctx) && ctx->opt.order != GC_ORDER_NONE) return enqueue_advance(ctx, dt, n_steps, ctx->opt.timing != 0);
+    // reset the live prefix now, never inside a graph: captured, the reset would
+    // make every replay sort and copy the stopped particles again
+    if (ctx->bound_dirty && ctx->opt.order != GC_ORDER_NONE) {
+        HIPCHK(launch_reset_bound(ctx->n_bound, (uint32_t)ctx->n, ctx->dead, ctx->stream));
+        ctx->bound_dirty = false;
+    }
     const bool same = ctx->gexec && ctx->gkey.dt == dt && ctx->gkey.n_steps == n_steps && ctx->gkey.n == ctx->n &&
                       ctx->gkey.state == ctx->soa_mem[0] &&
                       std::memcmp(&ctx->gkey.opt, &ctx->opt, sizeof(gc_options)) == 0;
@@ -817,12 +823,6 @@ gc_status gc_advance_graph(gc_ctx *ctx, double dt, int64_t n_steps) {
         const int64_t chunks = (n_steps + ctx->opt.chunk_steps - 1) / ctx->opt.chunk_steps;
         if (ctx->opt.order != GC_ORDER_NONE && (chunks & 1))
             return fail(ctx, GC_EINVAL, "graph mode needs an even number of chunks (n_steps / chunk_steps)");
-        // reset the live prefix now, not in the graph: captured, the reset would
-        // make every replay sort and copy the stopped particles again
-        if (ctx->bound_dirty && ctx->opt.order != GC_ORDER_NONE) {
-            HIPCHK(launch_reset_bound(ctx->n_bound, (uint32_t)ctx->n, ctx->dead, ctx->stream));
-            ctx->bound_dirty = false;
-        }
         HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         ctx->capturing = true;
         st = enqueue_advance(ctx, dt, n_steps, false);
