@@ -336,7 +336,8 @@ gc_status gc_get_order(gc_ctx *ctx, uint32_t *slot_gid, uint32_t *slot_key, uint
  * same way (the device picks the form from the live count) and books the time
  * of its launches under [0].  GC_EDEVICE if a cell-binning sort pass recorded
  * that it stopped waiting for an earlier tile (bounded wait; not expected on
- * working hardware): the particle order, and so the run, is then invalid. */
+ * working hardware): the particle order, and so the run, is then invalid
+ * until gc_set_state loads a state again. */
 typedef struct {
     double push_ms;
     int64_t n_push;

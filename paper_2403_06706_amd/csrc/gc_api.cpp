@@ -921,6 +921,8 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
     gc_status st = reserve(ctx, n);
     if (st != GC_OK) return st;
     HIPCHK(launch_state_in(ctx->A, *src, (uint32_t)n, ctx->stream));
+    // a fresh state: an earlier failed sort pass no longer taints it
+    if (ctx->sc.state) HIPCHK(launch_fill_u32(ctx->sc.state + kStError, 0u, 1, ctx->stream));
     ctx->n = n;
     ctx->bound_dirty = true;
     ctx->order_known = ctx->keys_known = false;
