@@ -570,10 +570,11 @@ def _bench_line(path):
     return json.loads(lines[-1])
 
 
-def summarize_push_pmc(d):
-    """Writes profiles/push_valu.json, push_traffic.json and their tables from
-    the rocprofv3 passes PMC_PASSES under directory d (pmc_<pass>/ with the
-    CSV output, pmc_<pass>.log with the bench line of that run)."""
+def summarize_push_pmc(d, out_dir=None):
+    """Writes push_valu.json, push_traffic.json and their tables (into
+    profiles/, or out_dir) from the rocprofv3 passes PMC_PASSES under directory
+    d (pmc_<pass>/ with the CSV output, pmc_<pass>.log with the bench line of
+    that run).  Returns the two summaries."""
     launches, probe = None, {}
     lines = {}
     for name in PMC_PASSES:
@@ -631,10 +632,12 @@ def summarize_push_pmc(d):
         "derivation": f"FETCH_SIZE x {fetch_scale:.4f} + WRITE_SIZE x {write_scale:.4f} (KiB; scales from the "
                       f"{COPY_PROBE_KIB:.0f} KiB copy of gc_copy_probe in the same runs) over {steps:.5g} "
                       f"particle-steps of '{cmd}'; written by bench.py --summarize-push-pmc"}
-    prof = os.path.join(ROOT, "profiles")
-    with open(VALU_JSON, "w") as f:
+    prof = out_dir or os.path.join(ROOT, "profiles")
+    valu_json = os.path.join(prof, os.path.basename(VALU_JSON))
+    traffic_json = os.path.join(prof, os.path.basename(TRAFFIC_JSON))
+    with open(valu_json, "w") as f:
         json.dump(valu, f, indent=1)
-    with open(TRAFFIC_JSON, "w") as f:
+    with open(traffic_json, "w") as f:
         json.dump(traffic, f, indent=1)
     pmc_cmds = "\n".join(
         f"    rocprofv3 --pmc {PMC_PASSES[n]} \\\n        --kernel-include-regex 'k_push<|k_copy_probe' "
@@ -727,9 +730,10 @@ Push launches (`gc::{PUSH_KERNEL}`):
   once per 64-step launch.
 * L2: {traffic['l2_requests_per_particle_step']:.4f} requests per particle-step, hit rate {traffic['l2_hit_rate']:.3f}.
 """)
-    print(json.dumps({"valu": VALU_JSON, "traffic": TRAFFIC_JSON, "kernel_hash": h,
+    print(json.dumps({"valu": valu_json, "traffic": traffic_json, "kernel_hash": h,
                       "valu_instructions_per_particle_step": iv, "valu_busy": valu["valu_busy"],
                       "hbm_bytes_per_particle_step": traffic["hbm_bytes_per_particle_step"]}))
+    return valu, traffic
 
 
 def push_roofline(args, c):
