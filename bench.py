@@ -1072,6 +1072,13 @@ def main():
         log("[bench] steady-state summary ...")
         out["steady_state"] = run_steady(args, field=field, with_cpu=False)
         out["steady_state"]["note"] = "with the oracle beside it: bench.py --workload steady"
+        if not args.steady_wind:
+            # the same job with scattering in the wind frame and only v_par b (Fig. 11 setting)
+            wind_args = argparse.Namespace(**vars(args))
+            wind_args.steady_wind = True
+            log("[bench] steady-state summary, wind-frame scattering ...")
+            out["steady_state_wind"] = run_steady(wind_args, field=field, with_cpu=False)
+            out["steady_state_wind"]["note"] = "with the oracle beside it: bench.py --workload steady --steady-wind"
 
     if args.steps < WHOLE_JOB_CHUNKS and not args.no_whole_job and not args.probe_copy:
         log("[bench] whole 24 h job ...")
