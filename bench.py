@@ -622,7 +622,8 @@ def summarize_push_pmc(d, out_dir=None):
                       f"({N_CU} CUs x GRBM_GUI_ACTIVE / {N_XCD} XCDs); written by bench.py --summarize-push-pmc"}
     fetch_scale = COPY_PROBE_KIB / probe["FETCH_SIZE"]
     write_scale = COPY_PROBE_KIB / probe["WRITE_SIZE"]
-    hbm = 1024.0 * (tot["FETCH_SIZE"] * fetch_scale + tot["WRITE_SIZE"] * write_scale)
+    fetch_total, write_total = tot["FETCH_SIZE"] * fetch_scale, tot["WRITE_SIZE"] * write_scale
+    hbm = 1024.0 * (fetch_total + write_total)
     traffic = {
         "kernel": kname, "kernel_hash": h, "store": cfg["field_store"], "precision": cfg["precision"],
         "hbm_bytes_per_particle_step": hbm / steps,
@@ -726,8 +727,9 @@ Push launches (`gc::{PUSH_KERNEL}`):
 
 * Scaled HBM bytes: {hbm:.4e} B over {steps:.5g} particle-steps = **{hbm / steps:.2f} B per active particle-step**,
   against 768 B per step of algorithmic field gathers (2 gathers x 8 nodes x 12 FP32 components): the
-  gathers are served by the caches, and the HBM traffic is essentially the particle state, read and written
-  once per 64-step launch.
+  gathers are served by the caches, and the HBM traffic is the particle state, written once per 64-step
+  launch in slot order and read once through the last reorder's permutation, whose scattered 8-byte loads
+  fetch whole cache lines: {fetch_total / max(write_total, 1.0):.1f} times the bytes written are fetched.
 * L2: {traffic['l2_requests_per_particle_step']:.4f} requests per particle-step, hit rate {traffic['l2_hit_rate']:.3f}.
 """)
     print(json.dumps({"valu": valu_json, "traffic": traffic_json, "kernel_hash": h,

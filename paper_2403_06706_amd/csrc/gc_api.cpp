@@ -86,6 +86,11 @@ struct gc_ctx {
     bool order_known = false;         // a reorder ran since the particle set last changed
     bool keys_known = false;          // ... and it was a cell binning (its keys are in sc.sorted_keys)
     uint32_t sorted_dead = 0;         // the inactive key of that binning
+    // a reorder whose permutation the next push applies (grid field source):
+    // the permutation, the order kind, and the reorder's timing events
+    uint32_t *pend_perm = nullptr;
+    int pend_order = 0;
+    hipEvent_t pend_e0 = nullptr, pend_e1 = nullptr;
     unsigned long long *steps = nullptr;       // [kPushForms] active particle-steps by push form
     uint32_t *log = nullptr;
     volatile uint32_t *count_host = nullptr;   // live count of the latest completed reorder (pinned)
@@ -96,7 +101,9 @@ struct gc_ctx {
     // timing
     struct PushEv { hipEvent_t e0, e1; int form; };
     std::vector<PushEv> ev_push;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_reorder;
+    // a reorder's span; with p0, p1 set the span holds that push, not counted
+    struct ReorderEv { hipEvent_t e0, e1, p0, p1; };
+    std::vector<ReorderEv> ev_reorder;
     std::vector<hipEvent_t> ev_pool;   // recorded and read events, ready for reuse
     // graph
     hipGraphExec_t gexec = nullptr;
@@ -322,6 +329,8 @@ int push_form(const gc_ctx *ctx) {
     return seen < (uint32_t)ctx->opt.tail_threshold / 4 ? 2 : 1;
 }
 
+gc_status finish_reorder(gc_ctx *ctx, int order, hipEvent_t e0, hipEvent_t e1, hipEvent_t p0, hipEvent_t p1);
+
 gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     hipStream_t s = ctx->stream;
     const uint32_t n = (uint32_t)ctx->n;
@@ -356,22 +365,49 @@ gc_status reorder(gc_ctx *ctx, bool timed, int order) {
         HIPCHK(launch_cell_keys(ctx->A, ctx->f, ctx->n_bound, n, c, dead, bits, ctx->sc, ctx->n_active, s, e0));
         HIPCHK(launch_radix_sort(ctx->sc, ctx->n_bound, n, bits, ctx->n_active, &perm, s));
     }
-    HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_bound, n, comp, s));
-    // particles that died since the last reorder now sit in [n_active, n_bound) of B: copy them to A too
+    if (ctx->opt.field_source == GC_SOURCE_GRID) {
+        // The grid push applies the permutation itself (it reads every active
+        // particle from A through perm and writes it to B): here only the
+        // particles stopped since the last reorder, slots [n_active, n_bound)
+        // of the new order, move; the push ends the reorder.
+        HIPCHK(launch_permute(ctx->A, ctx->B, perm, ctx->n_active, ctx->n_bound, n, comp, s));
+        ctx->pend_perm = perm;
+        ctx->pend_order = order;
+        ctx->pend_e0 = e0;
+        ctx->pend_e1 = e1;
+        return GC_OK;
+    }
+    HIPCHK(launch_permute(ctx->A, ctx->B, perm, nullptr, ctx->n_bound, n, comp, s));
+    return finish_reorder(ctx, order, e0, e1, nullptr, nullptr);
+}
+
+// The end of a reorder, once B holds the permuted state: the particles stopped
+// since the last reorder, slots [n_active, n_bound) of B, are copied to A too
+// (both buffers keep the same slots past the live prefix), the live prefix
+// shrinks to the active count, and B becomes the current buffer.  e0, e1: the
+// reorder's timing events (e1 attached here); p0, p1: those of a push between
+// them that applied the permutation.
+gc_status finish_reorder(gc_ctx *ctx, int order, hipEvent_t e0, hipEvent_t e1, hipEvent_t p0, hipEvent_t p1) {
+    hipStream_t s = ctx->stream;
+    const uint32_t n = (uint32_t)ctx->n;
+    const bool comp = ctx->opt.precision == GC_PREC_F32_KAHAN;
     HIPCHK(launch_copy_range(ctx->B, ctx->A, ctx->n_active, ctx->n_bound, n, comp, ctx->dead, s));
     HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, ctx->count_host, ctx->sorted_n, ctx->sc.state, s, e1));
     ctx->order_known = true;
     ctx->keys_known = order == GC_ORDER_BIN;
     std::swap(ctx->A, ctx->B);
     std::swap(ctx->soa_mem[0], ctx->soa_mem[1]);
-    if (timed) ctx->ev_reorder.emplace_back(e0, e1);
+    if (e0) ctx->ev_reorder.push_back({e0, e1, p0, p1});
     return GC_OK;
 }
 
 gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     hipStream_t s = ctx->stream;
     PushArgs a{};
-    a.st = ctx->A;
+    const bool moved = ctx->pend_perm != nullptr;   // the push applies the last reorder's permutation
+    a.st = moved ? ctx->B : ctx->A;
+    a.src = ctx->A;
+    a.perm = ctx->pend_perm;
     a.f = ctx->f;
     a.fdev = ctx->f_dev;
     a.ens = ctx->ens_dev;
@@ -399,6 +435,7 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
         e1 = take_event(ctx);
     }
     if (ctx->opt.field_source == GC_SOURCE_MLP) {
+        if (moved) return fail(ctx, GC_ESTATE, "the neural-field push does not apply permutations");
         if (timed) HIPCHK(hipEventRecord(e0, s));
         HIPCHK(launch_push_mlp(a, ctx->mlp.args, ctx->opt.precision, s));
         if (timed) HIPCHK(hipEventRecord(e1, s));
@@ -409,6 +446,10 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
         HIPCHK(launch_push(a, ctx->opt.precision, ctx->opt.block_size, pers, form, grid_blocks, s, ev));
     }
     if (timed) ctx->ev_push.push_back({e0, e1, form});
+    if (moved) {
+        ctx->pend_perm = nullptr;
+        return finish_reorder(ctx, ctx->pend_order, ctx->pend_e0, ctx->pend_e1, e0, e1);
+    }
     return GC_OK;
 }
 
@@ -604,8 +645,8 @@ void gc_destroy(gc_ctx *ctx) {
         (void)hipEventDestroy(p.e1);
     }
     for (auto &p : ctx->ev_reorder) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ahead)
@@ -971,9 +1012,10 @@ gc_status gc_get_counters(gc_ctx *ctx, gc_counters *out) {
         out->form_launches[p.form] += 1;
     }
     for (auto &p : ctx->ev_reorder) {
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, p.first, p.second));
-        out->reorder_ms += ms;
+        float ms = 0, pm = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.e0, p.e1));
+        if (p.p0) HIPCHK(hipEventElapsedTime(&pm, p.p0, p.p1));
+        out->reorder_ms += ms - pm;
         out->n_reorder += 1;
     }
     unsigned long long steps[kPushForms] = {0, 0, 0};
@@ -997,9 +1039,9 @@ gc_status gc_reset_counters(gc_ctx *ctx) {
         ctx->ev_pool.push_back(p.e1);
     }
     ctx->ev_push.clear();
-    for (auto &p : ctx->ev_reorder) {
-        ctx->ev_pool.push_back(p.first);
-        ctx->ev_pool.push_back(p.second);
+    for (auto &p : ctx->ev_reorder) {   // (p0, p1 belong to ev_push)
+        ctx->ev_pool.push_back(p.e0);
+        ctx->ev_pool.push_back(p.e1);
     }
     ctx->ev_reorder.clear();
     HIPCHK(launch_fill_u64(ctx->steps, 0ull, kPushForms, ctx->stream));
@@ -1151,6 +1193,7 @@ gc_status gc_gather_probe(gc_ctx *ctx, double dt, int32_t n_steps, double *sink)
     HIPCHK(hipSetDevice(ctx->opt.device));
     PushArgs a{};
     a.st = ctx->A;
+    a.src = ctx->A;
     a.f = ctx->f;
     a.ens = ctx->ens_dev;
     a.n_active = ctx->bound_dirty ? nullptr : ctx->n_active;

@@ -92,7 +92,11 @@ constexpr int kNumDoubleArrays = 18;
 constexpr int kNumU32Arrays = 8;
 
 struct PushArgs {
-    SoA st;
+    SoA st;                        // the state written
+    SoA src;                       // the state read: st itself, or with perm the other buffer
+    const uint32_t *perm;          // null, or a reorder's permutation that the push applies: the
+                                   // particle of slot i is read from src at perm[i] and every
+                                   // field of it written to st at i
     FieldDev f;
     FieldDev fx;                   // full Eqs. 1-2: the extra node array (mode 2)
     const FieldDev *fdev;          // device copy of f (for the out-of-line rebirth)

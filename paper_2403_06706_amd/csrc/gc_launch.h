@@ -92,8 +92,9 @@ hipError_t launch_radix_sort(OrderScratch &sc, const uint32_t *np, uint32_t n_ma
                              uint32_t **perm_out, hipStream_t s);
 hipError_t launch_compact(const SoA &st, const uint32_t *np, uint32_t n_max, OrderScratch &sc, uint32_t *n_active,
                           uint32_t **perm_out, hipStream_t s, hipEvent_t start = nullptr);
-hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *np, uint32_t n_max,
-                          bool with_comp, hipStream_t s);
+// dst[i] = src[perm[i]] for i in [*lo, *hi) (lo null: from 0)
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *lo,
+                          const uint32_t *hi, uint32_t n_max, bool with_comp, hipStream_t s);
 // dst[i] = src[i] for i in [*lo, *hi); with dead set, the per-status counts,
 // collision counts and steps of those slots are added to dead[0..5]
 hipError_t launch_copy_range(const SoA &src, const SoA &dst, const uint32_t *lo, const uint32_t *hi, uint32_t n_max,

@@ -331,9 +331,9 @@ hipError_t launch_compact(const SoA &st, const uint32_t *np, uint32_t n_max, Ord
 
 // ---------------------------------------------------------------------------
 template <bool kWithComp>
-__global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, const uint32_t *np) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *np) return;
+__global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, const uint32_t *lo, const uint32_t *hi) {
+    const uint32_t i = (lo ? *lo : 0u) + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *hi) return;
     const uint32_t j = perm[i];
 #define P_(name) dst.name[i] = src.name[j];
     P_(r) P_(th) P_(ph) P_(u) P_(mu) P_(fr) P_(fth) P_(fph) P_(fu) P_(dtp) P_(s) P_(ell) P_(t)
@@ -342,12 +342,12 @@ __global__ void k_permute(SoA src, SoA dst, const uint32_t *perm, const uint32_t
 #undef P_
 }
 
-hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *np, uint32_t n_max,
-                          bool with_comp, hipStream_t s) {
+hipError_t launch_permute(const SoA &src, const SoA &dst, const uint32_t *perm, const uint32_t *lo,
+                          const uint32_t *hi, uint32_t n_max, bool with_comp, hipStream_t s) {
     if (n_max == 0) return hipSuccess;
     const dim3 grid((n_max + 255) / 256);
-    if (with_comp) hipLaunchKernelGGL(k_permute<true>, grid, dim3(256), 0, s, src, dst, perm, np);
-    else hipLaunchKernelGGL(k_permute<false>, grid, dim3(256), 0, s, src, dst, perm, np);
+    if (with_comp) hipLaunchKernelGGL(k_permute<true>, grid, dim3(256), 0, s, src, dst, perm, lo, hi);
+    else hipLaunchKernelGGL(k_permute<false>, grid, dim3(256), 0, s, src, dst, perm, lo, hi);
     return hipGetLastError();
 }
 

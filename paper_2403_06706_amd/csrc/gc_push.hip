@@ -33,24 +33,45 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     using R = typename PrecT<PREC>::R;
     using A = typename PrecT<PREC>::A;
     constexpr bool kKahan = PrecT<PREC>::kKahan;
-    const SoA &st = a.st;
-    uint32_t status = st.status[slot];
+    // The particle of this slot is read from sr at ls and written to st at
+    // slot: the same place, or (a reorder's permutation applied by the push)
+    // its place in the other state buffer.  In place, a stopped particle costs
+    // one load.  Moved, every field is loaded at once, one round trip after
+    // the permutation's.
+    const SoA &st = a.st, &sr = a.src;
+    const bool moved = a.perm != nullptr;
+    const uint32_t ls = moved ? a.perm[slot] : slot;
+    if (!moved && sr.status[ls] != GC_ACTIVE) return 0;
+    uint32_t status = sr.status[ls], flags = sr.flags[ls], k = sr.k[ls], step = sr.step[ls];
+    const uint32_t ens_raw = sr.ens[ls], pid = sr.id[ls];
+    const uint32_t gid = sr.gid[ls], birth0 = sr.birth[ls];
+    double r0 = sr.r[ls], th0 = sr.th[ls], ph0 = sr.ph[ls], u0 = sr.u[ls], t0 = sr.t[ls];
+    double fr0 = sr.fr[ls], fth0 = sr.fth[ls], fph0 = sr.fph[ls], fu0 = sr.fu[ls];
+    double mu0 = sr.mu[ls], dtp0 = sr.dtp[ls], s0 = sr.s[ls], ell0 = sr.ell[ls];
+    double cr0 = 0, cth0 = 0, cph0 = 0, cu0 = 0, ct0 = 0;
+    if (kKahan) { cr0 = sr.cr[ls]; cth0 = sr.cth[ls]; cph0 = sr.cph[ls]; cu0 = sr.cu[ls]; ct0 = sr.ct[ls]; }
+    // The empty statements below take every loaded value, so the loads are all
+    // issued before the status test (else the compiler issues the status load
+    // alone, and the others after its round trip).
+#define GC_LOADED(x) asm volatile("" : "+v"(x))
+    GC_LOADED(status); GC_LOADED(flags); GC_LOADED(k); GC_LOADED(step);
+    GC_LOADED(r0); GC_LOADED(th0); GC_LOADED(ph0); GC_LOADED(u0); GC_LOADED(t0);
+    GC_LOADED(fr0); GC_LOADED(fth0); GC_LOADED(fph0); GC_LOADED(fu0);
+    GC_LOADED(mu0); GC_LOADED(dtp0); GC_LOADED(s0); GC_LOADED(ell0);
+    if (kKahan) { GC_LOADED(cr0); GC_LOADED(cth0); GC_LOADED(cph0); GC_LOADED(cu0); GC_LOADED(ct0); }
+#undef GC_LOADED
+    // (moved: every slot is active, a reorder puts the active particles first)
     if (status != GC_ACTIVE) return 0;
-    uint32_t flags = st.flags[slot], k = st.k[slot], step = st.step[slot];
     const uint32_t step0 = step;
-    const uint32_t eidx = min(st.ens[slot], (uint32_t)(kMaxEnsembles - 1));
+    const uint32_t eidx = min(ens_raw, (uint32_t)(kMaxEnsembles - 1));
     const EnsDev e = a.ens[eidx];
     uint32_t birth = 0;
     bool reborn = false;
-    const uint32_t pid = st.id[slot];
-    A X0 = (A)st.r[slot], X1 = (A)st.th[slot], X2 = (A)st.ph[slot], X3 = (A)st.u[slot];
-    A T = (A)st.t[slot];
-    A c0 = 0, c1 = 0, c2 = 0, c3 = 0, cT = 0;
-    if (kKahan) {
-        c0 = (A)st.cr[slot]; c1 = (A)st.cth[slot]; c2 = (A)st.cph[slot]; c3 = (A)st.cu[slot]; cT = (A)st.ct[slot];
-    }
-    R fp0 = (R)st.fr[slot], fp1 = (R)st.fth[slot], fp2 = (R)st.fph[slot], fp3 = (R)st.fu[slot];
-    R mu = (R)st.mu[slot], dtp = (R)st.dtp[slot], s = (R)st.s[slot], ell = (R)st.ell[slot];
+    A X0 = (A)r0, X1 = (A)th0, X2 = (A)ph0, X3 = (A)u0;
+    A T = (A)t0;
+    A c0 = (A)cr0, c1 = (A)cth0, c2 = (A)cph0, c3 = (A)cu0, cT = (A)ct0;
+    R fp0 = (R)fr0, fp1 = (R)fth0, fp2 = (R)fph0, fp3 = (R)fu0;
+    R mu = (R)mu0, dtp = (R)dtp0, s = (R)s0, ell = (R)ell0;
     const R qm = (R)e.qm, iqm = (R)e.iqm;
     const bool drift_free = e.drift_free != 0;
     const bool scatter = e.lambda > 0.0;
@@ -100,7 +121,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
                 k += 1;
                 flags = (flags | GC_FLAG_BOOTSTRAP) & ~GC_FLAG_PENDING;
                 if (a.log_depth > 0 && k <= (uint32_t)a.log_depth && gl == 0)
-                    a.log[(size_t)st.gid[slot] * a.log_depth + (k - 1)] = step;
+                    a.log[(size_t)gid * a.log_depth + (k - 1)] = step;
             }
             R F[4], vp;
             if (FULL) {
@@ -186,7 +207,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             birth = step;
             reborn = true;
             if (a.log_depth > 0 && gl == 0) {
-                uint32_t *row = a.log + (size_t)st.gid[slot] * a.log_depth;
+                uint32_t *row = a.log + (size_t)gid * a.log_depth;
                 for (int j = 0; j < a.log_depth; ++j) row[j] = 0xFFFFFFFFu;
             }
             if (b.status != GC_ACTIVE) { status = b.status; break; }
@@ -203,7 +224,9 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     st.fr[slot] = (double)fp0; st.fth[slot] = (double)fp1; st.fph[slot] = (double)fp2; st.fu[slot] = (double)fp3;
     st.mu[slot] = (double)mu; st.dtp[slot] = (double)dtp; st.s[slot] = (double)s; st.ell[slot] = (double)ell;
     st.k[slot] = k; st.flags[slot] = flags; st.status[slot] = status; st.step[slot] = step;
-    if (reborn) st.birth[slot] = birth;
+    // (in place these rewrite the values loaded: no branch, and no flag kept over the loop)
+    st.id[slot] = pid; st.ens[slot] = ens_raw; st.gid[slot] = gid;
+    st.birth[slot] = reborn ? birth : birth0;
     return step - step0;
 }
 
