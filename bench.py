@@ -327,7 +327,7 @@ def run_batched(args, wl=None, field=None):
     t0 = time.time()
     # the batched form is the persistent push: tune its workgroup, bin and tile sizes
     tune = ctx.autotune(wl.dt, probe_steps=128, blocks=(128, 256), coarsen=(0, 1), chunks=(),
-                        tiles=(512, 1024, 4096), cache=args.tune_cache, key=f"{wl.name}-{args.store}-{args.precision}")
+                        tiles=(256, 512, 1024, 4096), cache=args.tune_cache, key=f"{wl.name}-{args.store}-{args.precision}")
     log(f"[bench] autotune ({time.time() - t0:.1f} s): {tune}")
     opts = {k: v for k, v in tune["options"].items() if k in ("block_size", "bin_coarsen", "tile", "chunk_steps")}
     ctx.close()
