@@ -36,7 +36,7 @@ VALU_JSON = os.path.join(ROOT, "profiles", "push_valu.json")
 WHOLE_JOB_CHUNKS = 1350          # 24 h of 1 s steps in chunks of 64
 KERNEL_SOURCES = ["paper_2403_06706_amd/csrc/gc_push.hip", "paper_2403_06706_amd/csrc/gc_step.h",
                   "paper_2403_06706_amd/csrc/gc_device.h", "paper_2403_06706_amd/csrc/gc_internal.h",
-                  "paper_2403_06706_amd/csrc/gc_kernels.hip"]
+                  "paper_2403_06706_amd/csrc/gc_kernels.hip", "paper_2403_06706_amd/build.py"]
 
 
 def kernel_hash() -> str:

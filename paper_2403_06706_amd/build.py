@@ -24,7 +24,11 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Wall", "-Wno-unused-result", "-ffp-contract=fast"]
 # Matrix-core sources: MFMA results in ordinary VGPRs (the activation code reads
 # every accumulator; with AGPR results each read is an extra v_accvgpr_read).
-EXTRA = {"gc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "gc_push_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA = {"gc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"], "gc_push_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         # The push kernels of every form must give the same bits: multiply-adds
+         # are contracted only within one source expression, never across
+         # statements, where the choice would follow each kernel's block layout.
+         "gc_push.hip": ["-ffp-contract=on"]}
 
 
 def _compile(src: str) -> str:

@@ -301,8 +301,8 @@ uint32_t bits_for(uint32_t max_key) {
 // Tail of a run (eager advance only): once the live count read back from an
 // earlier reorder is below tail_threshold, the machine is far from full and the
 // push is bound by each wavefront's chain of dependent memory round trips.
-// Then the push takes a latency form (all loads of a gather in flight; below a
-// quarter of the threshold, four lanes per particle), and the reorder runs
+// Then the push takes a latency form (all loads of a gather in flight; below
+// threshold / kQuadShare, four lanes per particle), and the reorder runs
 // only every kTailReorderEvery chunks (particles cross about two cells per 64
 // steps, so the cell order decays slowly, while a reorder costs a fixed ~80 us
 // of launches).  No choice changes any particle's trajectory.
@@ -326,7 +326,7 @@ bool tail_mode(const gc_ctx *ctx) {
 int push_form(const gc_ctx *ctx) {
     const uint32_t seen = seen_count(ctx);
     if (seen == 0xFFFFFFFFu || seen >= (uint32_t)ctx->opt.tail_threshold) return 0;
-    return seen < (uint32_t)ctx->opt.tail_threshold / 4 ? 2 : 1;
+    return seen < (uint32_t)ctx->opt.tail_threshold / kQuadShare ? 2 : 1;
 }
 
 gc_status finish_reorder(gc_ctx *ctx, int order, hipEvent_t e0, hipEvent_t e1, hipEvent_t p0, hipEvent_t p1);

@@ -8,6 +8,9 @@
 namespace gc {
 
 constexpr int kMaxEnsembles = 4096;
+// Tail policy: below tail_threshold / kQuadShare live particles the push takes
+// the four-lanes-per-particle form (above it, in the tail, all pairs in flight).
+constexpr uint32_t kQuadShare = 4;
 constexpr int kMaxMoments = 8192;
 constexpr int64_t kMaxRebirthSteps = 1 << 24;   // generations fit the 24 flag bits above GC_FLAG_GEN_SHIFT
 constexpr int kNumComp = 12;

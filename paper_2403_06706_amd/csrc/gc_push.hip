@@ -80,10 +80,8 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
     const double r_in = e.r_in, r_out = e.r_out, th_lo = a.f.th_lo, th_hi = a.f.th_hi;
 
     for (int it = 0; it < a.n_steps; ++it) {
-        // Field evaluations of the step, through one gather + right-hand side
-        // site: stage 0 at X^n, stage 1 (bootstrap only) at X^{n-1} = X^n - dt F^n,
-        // stage 2 at the predictor X*.  Lanes of a wavefront in different
-        // stages run the same instructions.
+        // Field evaluations of the step: at X^n, at X^{n-1} = X^n - dt F^n on
+        // bootstrap steps only, and at the predictor X*.
         R Fn[4], Fs[4], vpn = 0, vps = 0, tau = 1;
         // A pending collision k+1 draws its generator block before the first
         // gather of the step (few live registers here); it is applied once the
@@ -96,61 +94,38 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             ell_new = (R)d.ell;
         }
         R px = (R)X0, pth = (R)X1, pph = (R)X2, pu = (R)X3;
-        int stage = 0;
         bool bad = false;
-        for (;;) {
-            R g[12], x[12];   // x: the extra node array (full equations only)
-            bool ok, xok = true;
-            if constexpr (FULL) ok = gather2<FDT, R, FORM == kFormAllPairs>(a.f, a.fx, px, pth, pph, g, x, xok);
-            else if constexpr (FORM == kFormQuad) ok = gather_quad<FDT, R>(a.f, px, pth, pph, gl, g);
-            else ok = gather<FDT, R, FORM == kFormAllPairs>(a.f, px, pth, pph, g);
-            if (!ok) { bad = true; break; }
-            if (stage == 0 && (flags & GC_FLAG_PENDING)) {
-                // collision k+1 (Eqs. 9-10): |p| kept, new pitch cosine and free path
-                const R B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-                R p2 = pu * pu + (R)2 * mu * B;                  // (p/m)^2, kept in the inertial frame
-                R un;
-                if (EXT && vw > (R)0) wind_collision<R>(pu, mu, B, g[0], vw, mun, un, p2);
-                else un = mun * sqrt(p2);
-                X3 = (A)un;
-                c3 = 0;
-                pu = (R)X3;
-                mu = p2 * ((R)1 - mun * mun) / ((R)2 * B);
-                ell = ell_new;
-                s = 0;
-                k += 1;
-                flags = (flags | GC_FLAG_BOOTSTRAP) & ~GC_FLAG_PENDING;
-                if (a.log_depth > 0 && k <= (uint32_t)a.log_depth && gl == 0)
-                    a.log[(size_t)gid * a.log_depth + (k - 1)] = step;
-            }
-            R F[4], vp;
-            if (FULL) {
-                if (!xok) { bad = true; break; }   // after the collision, as the field's own check
-                gc_rhs<R, true>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp, x);
-            } else {
-                gc_rhs<R>(px, pth, pu, mu, qm, iqm, drift_free, g, F, vp);
-            }
-            if (stage == 2) {
-                Fs[0] = F[0]; Fs[1] = F[1]; Fs[2] = F[2]; Fs[3] = F[3];
-                vps = EXT ? path_speed<R>(vp, g, vw) : vp;
-                break;
-            }
-            if (stage == 0) {
-                Fn[0] = F[0]; Fn[1] = F[1]; Fn[2] = F[2]; Fn[3] = F[3];
-                vpn = EXT ? path_speed<R>(vp, g, vw) : vp;
-                if (flags & GC_FLAG_BOOTSTRAP) {
-                    // backward Euler start (Sect. 2.2)
-                    px = (R)X0 - h * F[0]; pth = (R)X1 - h * F[1]; pph = (R)X2 - h * F[2]; pu = (R)X3 - h * F[3];
-                    stage = 1;
-                    continue;
-                }
-                tau = dtp == h ? (R)1 : h * rcp_nr(dtp);
-            } else {   // stage 1: F^{n-1} of the bootstrap
-                fp0 = F[0]; fp1 = F[1]; fp2 = F[2]; fp3 = F[3];
-                tau = (R)1;
-                flags &= ~GC_FLAG_BOOTSTRAP;
-            }
-            // predictor, Eq. 5
+        // the gather at a point (xg: the extra node array, full equations only)
+        auto gather_at = [&](R x, R t, R p, R g[12], R xg[12], bool &xok) -> bool {
+            xok = true;
+            if constexpr (FULL) return gather2<FDT, R, FORM == kFormAllPairs>(a.f, a.fx, x, t, p, g, xg, xok);
+            else if constexpr (FORM == kFormQuad) return gather_quad<FDT, R>(a.f, x, t, p, gl, g);
+            else return gather<FDT, R, FORM == kFormAllPairs>(a.f, x, t, p, g);
+        };
+        auto rhs_at = [&](R x, R t, R u, R g[12], R xg[12], R F[4], R &vp) {
+            if constexpr (FULL) gc_rhs<R, true>(x, t, u, mu, qm, iqm, drift_free, g, F, vp, xg);
+            else gc_rhs<R>(x, t, u, mu, qm, iqm, drift_free, g, F, vp);
+        };
+        // collision k+1 (Eqs. 9-10) at X^n: |p| kept, new pitch cosine and free path
+        auto collide = [&](const R g[12]) {
+            const R B = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+            R p2 = pu * pu + (R)2 * mu * B;                  // (p/m)^2, kept in the inertial frame
+            R un;
+            if (EXT && vw > (R)0) wind_collision<R>(pu, mu, B, g[0], vw, mun, un, p2);
+            else un = mun * sqrt(p2);
+            X3 = (A)un;
+            c3 = 0;
+            pu = (R)X3;
+            mu = p2 * ((R)1 - mun * mun) / ((R)2 * B);
+            ell = ell_new;
+            s = 0;
+            k += 1;
+            flags = (flags | GC_FLAG_BOOTSTRAP) & ~GC_FLAG_PENDING;
+            if (a.log_depth > 0 && k <= (uint32_t)a.log_depth && gl == 0)
+                a.log[(size_t)gid * a.log_depth + (k - 1)] = step;
+        };
+        // predictor, Eq. 5
+        auto predict = [&]() {
             const R wn = (R)1 + (R)0.5 * tau, wq = (R)0.5 * tau;
             const R d0 = h * (wn * Fn[0] - wq * fp0), d1 = h * (wn * Fn[1] - wq * fp1);
             const R d2 = h * (wn * Fn[2] - wq * fp2), d3 = h * (wn * Fn[3] - wq * fp3);
@@ -159,7 +134,98 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             } else {
                 px = (R)(X0 + (A)d0); pth = (R)(X1 + (A)d1); pph = (R)(X2 + (A)d2); pu = (R)(X3 + (A)d3);
             }
-            stage = 2;
+        };
+        // One gather + right-hand side site that the stages loop through
+        // (stage 0 at X^n, 1 at X^{n-1}, 2 at X*; lanes in different stages run
+        // the same instructions) holds fewer registers than three sites in
+        // straight-line code, which avoid the register copies between stages.
+        // Either gives the same bits (multiply-adds are contracted only within
+        // a source expression).  Three sites where measured faster (the
+        // throughput and quad forms on FP32 fields, reduced equations); the
+        // loop for all pairs of a gather in flight (slower with three sites)
+        // and where three sites spill (full equations, FP64 and FP16 fields).
+        constexpr bool kLoopSites = FORM == kFormAllPairs || FULL || FDT != GC_F32;
+        if constexpr (kLoopSites) {
+            int stage = 0;
+            for (;;) {
+                R g[12], xg[12], F[4], vp;
+                bool xok;
+                if (!gather_at(px, pth, pph, g, xg, xok)) { bad = true; break; }
+                if (stage == 0 && (flags & GC_FLAG_PENDING)) collide(g);
+                if (FULL && !xok) { bad = true; break; }   // after the collision, as the field's own check
+                rhs_at(px, pth, pu, g, xg, F, vp);
+                if (stage == 2) {
+                    Fs[0] = F[0]; Fs[1] = F[1]; Fs[2] = F[2]; Fs[3] = F[3];
+                    vps = EXT ? path_speed<R>(vp, g, vw) : vp;
+                    break;
+                }
+                if (stage == 0) {
+                    Fn[0] = F[0]; Fn[1] = F[1]; Fn[2] = F[2]; Fn[3] = F[3];
+                    vpn = EXT ? path_speed<R>(vp, g, vw) : vp;
+                    if (flags & GC_FLAG_BOOTSTRAP) {
+                        // backward Euler start (Sect. 2.2)
+                        px = (R)X0 - h * F[0]; pth = (R)X1 - h * F[1]; pph = (R)X2 - h * F[2]; pu = (R)X3 - h * F[3];
+                        stage = 1;
+                        continue;
+                    }
+                    tau = dtp == h ? (R)1 : h * rcp_nr(dtp);
+                } else {   // stage 1: F^{n-1} of the bootstrap
+                    fp0 = F[0]; fp1 = F[1]; fp2 = F[2]; fp3 = F[3];
+                    tau = (R)1;
+                    flags &= ~GC_FLAG_BOOTSTRAP;
+                }
+                predict();
+                stage = 2;
+            }
+        } else {
+            // Straight-line sites: no register copies between the stages of a
+            // loop (measured faster for these forms).
+            {   // X^n
+                R g[12], xg[12];
+                bool xok;
+                if (!gather_at(px, pth, pph, g, xg, xok)) {
+                    bad = true;
+                } else {
+                    if (flags & GC_FLAG_PENDING) collide(g);
+                    if (FULL && !xok) {
+                        bad = true;   // after the collision, as the field's own check
+                    } else {
+                        R vp;
+                        rhs_at(px, pth, pu, g, xg, Fn, vp);
+                        vpn = EXT ? path_speed<R>(vp, g, vw) : vp;
+                    }
+                }
+            }
+            if (!bad) {
+                if (flags & GC_FLAG_BOOTSTRAP) {
+                    // backward Euler start (Sect. 2.2): F^{n-1} at X^n - dt F^n
+                    const R bx = (R)X0 - h * Fn[0], bth = (R)X1 - h * Fn[1], bph = (R)X2 - h * Fn[2];
+                    const R bu = (R)X3 - h * Fn[3];
+                    R g[12], xg[12], F[4], vp;
+                    bool xok;
+                    if (!gather_at(bx, bth, bph, g, xg, xok) || (FULL && !xok)) {
+                        bad = true;
+                    } else {
+                        rhs_at(bx, bth, bu, g, xg, F, vp);
+                        fp0 = F[0]; fp1 = F[1]; fp2 = F[2]; fp3 = F[3];
+                        tau = (R)1;
+                        flags &= ~GC_FLAG_BOOTSTRAP;
+                    }
+                } else {
+                    tau = dtp == h ? (R)1 : h * rcp_nr(dtp);
+                }
+            }
+            if (!bad) {   // X*
+                predict();
+                R g[12], xg[12], vp;
+                bool xok;
+                if (!gather_at(px, pth, pph, g, xg, xok) || (FULL && !xok)) {
+                    bad = true;
+                } else {
+                    rhs_at(px, pth, pu, g, xg, Fs, vp);
+                    vps = EXT ? path_speed<R>(vp, g, vw) : vp;
+                }
+            }
         }
         if (bad) { status = GC_NONFINITE; break; }
         // corrector, Eq. 6: dt/(6(1+tau)) [(1+tau)(3+tau) F^n + (3+2 tau) F* - tau^2 F^{n-1}]
@@ -282,8 +348,8 @@ __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
 // With a tail threshold T = a.tail > 0 each chunk launches the throughput,
 // all-pairs and four-lanes-per-particle kernels in turn, and the live count on
 // the device (written by the reorder) selects the one that works, the others
-// returning at once: T and more, the throughput form; [T/4, T), all pairs
-// (for the full equations, [0, T)); below T/4, four lanes per particle.  These
+// returning at once: T and more, the throughput form; [T/kQuadShare, T), all
+// pairs (for the full equations, [0, T)); below it, four lanes per particle.  These
 // are the forms of the eager tail policy, chosen on the device so that a
 // captured graph follows the count without a host read-back.  Steps are
 // counted per form (a.steps_done + form).
@@ -292,7 +358,7 @@ __device__ __forceinline__ void push_persistent(const PushArgs &a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
     const uint32_t T = a.tail;
-    const uint32_t q4 = MODE == 2 ? 0u : T / 4;               // the full equations have no quad form
+    const uint32_t q4 = MODE == 2 ? 0u : T / kQuadShare;      // the full equations have no quad form
     const uint32_t lo = FORM == kFormThroughput ? T : (FORM == kFormAllPairs ? q4 : 0u);
     const uint32_t hi = FORM == kFormThroughput ? 0xFFFFFFFFu : (FORM == kFormAllPairs ? T : q4);
     if (n < lo || n >= hi) return;
