@@ -15,7 +15,9 @@
  * Conventions (all entry points):
  *   - Every call returns a gc_status and never throws.  Argument errors are
  *     detected on the host before any device work and described by
- *     gc_last_error().  A failed HIP call or launch returns GC_EDEVICE.
+ *     gc_last_error().  A failed HIP call or launch returns GC_EDEVICE; after
+ *     one from gc_advance or gc_advance_graph the particle state may be part
+ *     way through a chunk: reload it (gc_set_state) or destroy the context.
  *   - Device work is queued on the context's HIP stream and returns without
  *     waiting, unless stated otherwise.
  *   - Units are SI.  Field vectors are in the local orthonormal spherical

@@ -334,6 +334,9 @@ gc_status finish_reorder(gc_ctx *ctx, int order, hipEvent_t e0, hipEvent_t e1, h
 gc_status reorder(gc_ctx *ctx, bool timed, int order) {
     hipStream_t s = ctx->stream;
     const uint32_t n = (uint32_t)ctx->n;
+    if (ctx->pend_perm)
+        return fail(ctx, GC_ESTATE, "an earlier advance failed between a reorder and its push: "
+                                    "reload the state (gc_set_state) or destroy the context");
     if (order == GC_ORDER_NONE) {
         HIPCHK(launch_set_count(ctx->n_active, n, s));
         ctx->bound_dirty = true;    // active particles may sit anywhere until the next reorder
@@ -649,6 +652,8 @@ void gc_destroy(gc_ctx *ctx) {
         (void)hipEventDestroy(p.e1);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ctx->pend_e0, ctx->pend_e1})
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->ahead)
         if (e) (void)hipEventDestroy(e);
     for (int i = 0; i < 2; ++i)
@@ -962,8 +967,19 @@ gc_status gc_set_state(gc_ctx *ctx, const gc_state_view *src, uint64_t n) {
     gc_status st = reserve(ctx, n);
     if (st != GC_OK) return st;
     HIPCHK(launch_state_in(ctx->A, *src, (uint32_t)n, ctx->stream));
-    // a fresh state: an earlier failed sort pass no longer taints it
-    if (ctx->sc.state) HIPCHK(launch_fill_u32(ctx->sc.state + kStError, 0u, 1, ctx->stream));
+    // a fresh state: an earlier failed sort pass no longer taints it, and a
+    // reorder cut short by a failed advance leaves no counts, tickets or
+    // look-back tags behind (the reset also moves the tags to a new epoch)
+    if (ctx->sc.state) {
+        HIPCHK(launch_fill_u32(ctx->sc.state + kStError, 0u, 1, ctx->stream));
+        HIPCHK(launch_copy_count(ctx->n_bound, ctx->n_active, nullptr, nullptr, ctx->sc.state, ctx->stream));
+    }
+    if (ctx->pend_perm) {
+        ctx->pend_perm = nullptr;
+        for (hipEvent_t e : {ctx->pend_e0, ctx->pend_e1})
+            if (e) ctx->ev_pool.push_back(e);
+        ctx->pend_e0 = ctx->pend_e1 = nullptr;
+    }
     ctx->n = n;
     ctx->bound_dirty = true;
     ctx->order_known = ctx->keys_known = false;
