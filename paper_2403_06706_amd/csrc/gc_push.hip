@@ -16,9 +16,10 @@ namespace gc {
 // Forms of the push (all bitwise identical in their results):
 //   kFormThroughput  one lane per particle, two node pairs of a gather in registers at a time;
 //   kFormAllPairs    one lane per particle, all four pairs of a gather in flight;
-//   kFormQuad        four lanes per particle (an aligned quad): each lane loads one node pair
-//                    of every gather, all four run the rest of the step on identical values,
-//                    lane gl = 0 writes.
+//   kFormQuad        four lanes per particle (an aligned quad): each lane interpolates three
+//                    of the twelve components of every gather (FP16 fields: loads one node
+//                    pair), the quad shares the results, all four run the rest of the step
+//                    on identical values, lane gl = 0 writes.
 enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 
 // MODE 0: the reduced equations, no rebirth, centres at rest.  MODE 1: also
