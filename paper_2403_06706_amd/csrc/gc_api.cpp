@@ -71,7 +71,7 @@ struct gc_ctx {
     EnsDev *ens_dev = nullptr;
     bool any_rebirth = false;         // some ensemble has rebirth_steps > 0
     bool any_wind = false;            // some ensemble scatters in the wind frame
-    // particles (A is current, B is the permutation target)
+    // particles (A is current, B the target of a reorder's permutation)
     uint64_t n = 0, cap = 0;
     void *soa_mem[2] = {nullptr, nullptr};
     SoA A{}, B{};

@@ -2,8 +2,11 @@
 //
 //  * cell binning: key = field cell of the particle (optionally coarsened),
 //    inactive particles get the largest key; LSD radix sort (8-bit digits) of
-//    (key, slot) pairs; permute the state.  Particles of one cell then sit in
-//    consecutive lanes, so their trilinear gathers hit the same cache lines.
+//    (key, slot) pairs; permute the state (for the grid push, only the
+//    particles stopped since the last reorder: the push applies the
+//    permutation to the others as it reads them).  Particles of one cell then
+//    sit in consecutive lanes, so their trilinear gathers hit the same cache
+//    lines.
 //    The key kernel also counts the digits of every pass; each pass is then
 //    one kernel that ranks its tile, finds the tile's offset per digit by
 //    looking back over the tiles before it, and scatters.
