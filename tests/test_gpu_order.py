@@ -42,6 +42,25 @@ def test_trajectories_invariant(base, cfg):
     assert np.array_equal(log, ref_log)
 
 
+@pytest.mark.parametrize("precision", ["f32_acc64", "f32_kahan"])
+def test_fp32_forms_invariant(base, precision):
+    """The FP32-arithmetic forms, FP32 field store: binning every chunk (the
+    push applying each reorder's permutation), the tail forms (all pairs, then
+    four lanes per particle) and the persistent form give the bits of one
+    unreordered launch, the Kahan compensation terms included."""
+    wl, f, _, _ = base
+    keys = None
+    ref, ref_log = run_gpu(wl, f, store_dtype="f32", precision=precision, order="none", chunk=1800, log_depth=16)
+    if precision == "f32_kahan":
+        keys = list(ref)                 # every field, the compensation terms too
+    for cfg in (dict(order="bin", chunk=64), dict(order="bin", chunk=64, tail_threshold=1 << 30),
+                dict(order="bin", chunk=64, persistent=True, tile=512, block=256, tail_threshold=4000)):
+        say(f"{precision} invariance {cfg}")
+        st, log = run_gpu(wl, f, store_dtype="f32", precision=precision, log_depth=16, **cfg)
+        same_state(st, ref, keys)
+        assert np.array_equal(log, ref_log)
+
+
 def test_graph_replay_of_the_persistent_form_matches_eager(base):
     """The persistent form in graph replays, the device picking its form from
     the live count: all pairs while all 2,000 electrons are live (tail
