@@ -450,8 +450,11 @@ gc_status push(gc_ctx *ctx, double dt, int32_t steps, bool timed) {
     }
     if (timed) ctx->ev_push.push_back({e0, e1, form});
     if (moved) {
+        // the reorder's events pass to finish_reorder (and its timing list)
+        hipEvent_t r0 = ctx->pend_e0, r1 = ctx->pend_e1;
         ctx->pend_perm = nullptr;
-        return finish_reorder(ctx, ctx->pend_order, ctx->pend_e0, ctx->pend_e1, e0, e1);
+        ctx->pend_e0 = ctx->pend_e1 = nullptr;
+        return finish_reorder(ctx, ctx->pend_order, r0, r1, e0, e1);
     }
     return GC_OK;
 }
