@@ -523,7 +523,7 @@ def load_profile(path, args):
 
 # Counter passes over the push (one rocprofv3 --pmc run each, with the command
 # PMC_BENCH_ARGS); their CSV output directories are named pmc_<pass>.
-PMC_BENCH_ARGS = "--steps 8 --warmup 0 --no-cpu-baseline --probe-copy"
+PMC_BENCH_ARGS = "--warmup 0 --no-cpu-baseline --probe-copy"
 PMC_PASSES = {
     "p1": "SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_VMEM_RD SQ_INSTS_SALU SQ_WAIT_INST_ANY "
           "SQ_BUSY_CYCLES SQ_WAVE_CYCLES GRBM_GUI_ACTIVE GRBM_COUNT",
@@ -568,6 +568,25 @@ def _bench_line(path):
     if not lines:
         raise ValueError(f"no bench line in {path}")
     return json.loads(lines[-1])
+
+
+def _launch_groups(n, max_rows=12, groups=10):
+    """Row ranges [a, b) of the per-launch tables: every launch, or ten groups
+    of consecutive launches when there are many."""
+    if n <= max_rows:
+        return [(i, i + 1) for i in range(n)]
+    return [(n * g // groups, n * (g + 1) // groups) for g in range(groups)]
+
+
+def _group_sums(launches, a, b):
+    """Counter sums over launches [a, b) with their busy fractions."""
+    g = {k: sum(x[k] for x in launches[a:b]) for k in launches[a]}
+    cu_cycles = N_CU * g["GRBM_GUI_ACTIVE"] / N_XCD
+    g["valu_busy"] = g["SQ_ACTIVE_INST_VALU"] / cu_cycles
+    g["ta_busy"] = g["TA_TA_BUSY_sum"] / cu_cycles
+    g["td_busy"] = g["TD_TD_BUSY_sum"] / cu_cycles
+    g["label"] = f"{a + 1}" if b == a + 1 else f"{a + 1}–{b}"
+    return g
 
 
 def summarize_push_pmc(d, out_dir=None):
@@ -647,14 +666,16 @@ def summarize_push_pmc(d, out_dir=None):
             f"repository root, `$D` = an output directory), then `python3 $R/bench.py --summarize-push-pmc $D`, "
             f"which wrote this file's tables and `{os.path.basename(VALU_JSON)}` / "
             f"`{os.path.basename(TRAFFIC_JSON)}` (kernel source hash `{h}`):\n\n{pmc_cmds}\n\n"
-            f"Workload: the first {len(launches)} chunks of 64 steps of the paper-scale job (2^20 electrons, "
-            f"256x128x256 FP32 field), all in the throughput form: {steps:.5g} active particle-steps over the "
-            f"{len(launches)} launches (`roofline.particle_steps_per_launch` x `roofline.launches` of the bench "
-            f"line).  `--probe-copy` first runs `gc_copy_probe`, a 256 MiB copy, and skips every sub-record.\n")
+            f"Workload: the paper-scale job (2^20 electrons, 256x128x256 FP32 field, chunks of 64 steps) as the "
+            f"bench line times it; the counters cover its {len(launches)} launches of the throughput form, "
+            f"{steps:.5g} active particle-steps (`roofline.particle_steps_per_launch` x `roofline.launches` of the "
+            f"bench line), the tail forms are not counted.  `--probe-copy` first runs `gc_copy_probe`, a 256 MiB "
+            f"copy, and skips every sub-record.\n")
+    groups = [_group_sums(launches, a, b) for a, b in _launch_groups(len(launches))]
     rows = "\n".join(
-        f"| {i + 1} | {a['SQ_INSTS_VALU']:,.0f} | {a['SQ_ACTIVE_INST_VALU']:,.0f} | {a['GRBM_GUI_ACTIVE']:,.0f} | "
+        f"| {a['label']} | {a['SQ_INSTS_VALU']:,.0f} | {a['SQ_ACTIVE_INST_VALU']:,.0f} | {a['GRBM_GUI_ACTIVE']:,.0f} | "
         f"{a['valu_busy']:.3f} | {a['TA_TA_BUSY_sum']:,.0f} | {a['ta_busy']:.3f} | {a['td_busy']:.3f} | "
-        f"{a['SQ_INSTS_VALU_CVT']:,.0f} | {a['SQ_INSTS_VALU_FLOPS_FP64']:,.0f} |" for i, a in enumerate(launches))
+        f"{a['SQ_INSTS_VALU_CVT']:,.0f} | {a['SQ_INSTS_VALU_FLOPS_FP64']:,.0f} |" for a in groups)
     mix = [("FMA F64", "SQ_INSTS_VALU_FMA_F64"), ("MUL F64", "SQ_INSTS_VALU_MUL_F64"),
            ("ADD F64", "SQ_INSTS_VALU_ADD_F64"), ("transcendental F64", "SQ_INSTS_VALU_TRANS_F64"),
            ("conversions", "SQ_INSTS_VALU_CVT"), ("INT32", "SQ_INSTS_VALU_INT32"), ("INT64", "SQ_INSTS_VALU_INT64")]
@@ -675,9 +696,9 @@ is {traffic['hbm_bytes_per_particle_step']:.1f} B per particle-step, {traffic['h
 busy fractions are counter / ({N_CU} CUs x GRBM_GUI_ACTIVE / {N_XCD}).  `SQ_ACTIVE_INST_VALU` counts VALU
 quad-cycles per SIMD, so it divides by {N_CU} CUs for 4 SIMDs.
 
-Per launch:
+Per launch (or, for many launches, summed over groups of consecutive launches):
 
-| Launch | SQ_INSTS_VALU | SQ_ACTIVE_INST_VALU | GRBM_GUI_ACTIVE | VALU busy | TA_TA_BUSY_sum | TA busy | TD busy | SQ_INSTS_VALU_CVT | SQ_INSTS_VALU_FLOPS_FP64 |
+| Launches | SQ_INSTS_VALU | SQ_ACTIVE_INST_VALU | GRBM_GUI_ACTIVE | VALU busy | TA_TA_BUSY_sum | TA busy | TD busy | SQ_INSTS_VALU_CVT | SQ_INSTS_VALU_FLOPS_FP64 |
 |---|---|---|---|---|---|---|---|---|---|
 {rows}
 
@@ -704,8 +725,8 @@ instruction serves up to 64 particles):
   (96 per gather).
 """)
     trows = "\n".join(
-        f"| {i + 1} | {a['FETCH_SIZE']:,.1f} | {a['WRITE_SIZE']:,.1f} | {a['TCC_HIT_sum']:,.0f} | {a['TCC_MISS_sum']:,.0f} | "
-        f"{a['TCC_HIT_sum'] / (a['TCC_HIT_sum'] + a['TCC_MISS_sum']):.3f} |" for i, a in enumerate(launches))
+        f"| {a['label']} | {a['FETCH_SIZE']:,.1f} | {a['WRITE_SIZE']:,.1f} | {a['TCC_HIT_sum']:,.0f} | {a['TCC_MISS_sum']:,.0f} | "
+        f"{a['TCC_HIT_sum'] / (a['TCC_HIT_sum'] + a['TCC_MISS_sum']):.3f} |" for a in groups)
     with open(os.path.join(prof, "push_f64_f32field_paper_scale_traffic.md"), "w") as f:
         f.write(f"""# k_push (FP64 arithmetic, FP32 field), paper-scale workload — HBM and L2 counters
 
@@ -719,9 +740,9 @@ Calibration (same runs):
 so FETCH_SIZE is scaled by {COPY_PROBE_KIB:,.0f} / {probe['FETCH_SIZE']:,.1f} = {fetch_scale:.3f} and WRITE_SIZE by
 {write_scale:.3f}.
 
-Push launches (`gc::{PUSH_KERNEL}`):
+Push launches (`gc::{PUSH_KERNEL}`; for many launches, sums over groups of consecutive launches):
 
-| Launch | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | TCC_HIT | TCC_MISS | L2 hit rate |
+| Launches | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | TCC_HIT | TCC_MISS | L2 hit rate |
 |---|---|---|---|---|---|
 {trows}
 
