@@ -84,7 +84,9 @@ typedef struct {
     int32_t persistent;     /* 1: persistent push with a tile work queue */
     int32_t tile;           /* particles per work-queue tile (persistent mode, multiple of block_size) */
     int32_t log_depth;      /* per particle, record the step of the first log_depth collisions (0: off) */
-    int32_t timing;         /* 1: record HIP events around each push launch (see gc_get_counters) */
+    int32_t timing;         /* 1: HIP events on each push launch and each reorder (gc_get_counters);
+                               2: on the push launches only (reorder_ms stays 0; each timed
+                               dispatch idles the queue a few microseconds) */
     int32_t field_source;   /* GC_SOURCE_GRID (trilinear grid) or GC_SOURCE_MLP (neural field, gc_mlp_set) */
     int32_t tail_threshold; /* grid form, eager gc_advance: chunks whose live count (as read back from an
                                earlier reorder) is below this reorder only every 8 chunks and use a
@@ -330,7 +332,9 @@ gc_status gc_get_order(gc_ctx *ctx, uint32_t *slot_gid, uint32_t *slot_key, uint
 
 /* ----------------------------------------------------------- counters */
 /* Waits for the stream.  push_ms: summed duration of push launches recorded
- * with timing = 1; n_push: their number; particle_steps: steps taken by active
+ * with timing = 1 or 2; n_push: their number; reorder_ms, n_reorder: the same for
+ * reorders (their kernels from the first to the last, less any push between),
+ * with timing = 1; particle_steps: steps taken by active
  * particles since the context was created or counters were reset.  form_*: the
  * same split by form of the grid push: [0] throughput form (and the
  * neural-field push), [1] all loads of a gather in flight, [2] four lanes per

@@ -81,10 +81,12 @@ class Context:
 
     def __init__(self, device: int = 0, precision: str = "f64", order: str = "bin", chunk_steps: int = 64,
                  bin_coarsen: int = 0, block_size: Optional[int] = None, persistent: bool = False, tile: int = 1024,
-                 log_depth: int = 0, timing: bool = False, field_source: str = "grid", tail_threshold: Optional[int] = None,
+                 log_depth: int = 0, timing=False, field_source: str = "grid", tail_threshold: Optional[int] = None,
                  stream=None, allocator: str = "torch"):
         """allocator "torch" (default): the context's device memory comes from
-        torch's caching allocator, on the context's stream; "hip": from hipMalloc."""
+        torch's caching allocator, on the context's stream; "hip": from hipMalloc.
+        timing: False/0 off, True/1 events on pushes and reorders, 2 or "push"
+        on pushes only (gc_options.timing)."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the guiding-centre pusher runs only on the device")
@@ -103,7 +105,7 @@ class Context:
         o.persistent = int(persistent)
         o.tile = tile
         o.log_depth = log_depth
-        o.timing = int(timing)
+        o.timing = 2 if timing == "push" else int(timing)
         o.field_source = _SOURCES[field_source]
         if tail_threshold is not None:
             o.tail_threshold = int(tail_threshold)

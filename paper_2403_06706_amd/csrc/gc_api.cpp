@@ -144,6 +144,7 @@ gc_status check_options(gc_ctx *ctx, const gc_options *o) {
     if (o->persistent && (o->tile <= 0 || o->tile % o->block_size != 0))
         return fail(ctx, GC_EINVAL, "tile must be a positive multiple of block_size");
     if (o->log_depth < 0 || o->log_depth > 4096) return fail(ctx, GC_EINVAL, "log_depth must be in [0, 4096]");
+    if (o->timing < 0 || o->timing > 2) return fail(ctx, GC_EINVAL, "timing must be 0, 1 or 2");
     if (o->field_source != GC_SOURCE_GRID && o->field_source != GC_SOURCE_MLP)
         return fail(ctx, GC_EINVAL, "unknown field_source %d", o->field_source);
     if (o->tail_threshold < 0) return fail(ctx, GC_EINVAL, "tail_threshold must be >= 0");
@@ -477,7 +478,7 @@ gc_status enqueue_advance(gc_ctx *ctx, double dt, int64_t n_steps, bool timed) {
         const bool tail = tail_mode(ctx) && ctx->opt.order != GC_ORDER_NONE;   // (NONE: nothing to skip)
         gc_status st = GC_OK;
         if (!tail || ctx->bound_dirty || ctx->tail_skip <= 0) {
-            st = reorder(ctx, timed, ctx->opt.order);
+            st = reorder(ctx, timed && ctx->opt.timing == 1, ctx->opt.order);   // (timing 2: pushes only)
             ctx->tail_skip = kTailReorderEvery - 1;
         } else {
             --ctx->tail_skip;

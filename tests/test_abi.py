@@ -66,6 +66,12 @@ def test_host_side_errors_without_device():
     assert b"block_size" in lib.gc_last_error(h)
     lib.gc_destroy(h)
     o.block_size = 256
+    o.timing = 3
+    st = lib.gc_create(C.byref(h), C.byref(o))
+    assert st == _abi.GC_EINVAL
+    assert b"timing" in lib.gc_last_error(h)
+    lib.gc_destroy(h)
+    o.timing = 0
     o.field_source = 7
     st = lib.gc_create(C.byref(h), C.byref(o))
     assert st == _abi.GC_EINVAL

@@ -223,3 +223,13 @@ def test_counters_count_active_steps(base):
     ctx.close()
     assert c["particle_steps"] == int(ref["step"].sum())
     assert c["n_push"] == (1800 + 63) // 64 and c["push_ms"] > 0
+    assert c["n_reorder"] > 0 and c["reorder_ms"] > 0
+    # timing 2: the push launches only
+    ctx = gcp.Context(device=0, timing="push")
+    ctx.load_field(wl.grid, f, "f64")
+    ctx.inject(wl.ensembles[0])
+    ctx.advance(1.0, 1800)
+    c2 = ctx.counters()
+    ctx.close()
+    assert c2["particle_steps"] == c["particle_steps"] and c2["n_push"] == c["n_push"] and c2["push_ms"] > 0
+    assert c2["n_reorder"] == 0 and c2["reorder_ms"] == 0
