@@ -97,3 +97,22 @@ def test_committed_summary_belongs_to_the_push_sources():
         traffic = json.load(f)
     assert valu["kernel_hash"] == traffic["kernel_hash"] == bench.kernel_hash()
     assert 0.0 < valu["valu_busy"] <= 1.0 and 0.0 < valu["ta_busy"] <= 1.0
+
+
+def test_launch_groups_cover_every_launch_once():
+    assert bench._launch_groups(8) == [(i, i + 1) for i in range(8)]
+    for n in (13, 100, 331, 1000):
+        g = bench._launch_groups(n)
+        assert len(g) == 10 and g[0][0] == 0 and g[-1][1] == n
+        assert all(a < b for a, b in g) and all(g[i][1] == g[i + 1][0] for i in range(9))
+
+
+def test_group_sums_and_busy_fractions():
+    launches = [{"SQ_INSTS_VALU": 10.0 * (i + 1), "SQ_ACTIVE_INST_VALU": 5.0 * (i + 1), "GRBM_GUI_ACTIVE": 8.0,
+                 "TA_TA_BUSY_sum": 2.0, "TD_TD_BUSY_sum": 3.0} for i in range(4)]
+    g = bench._group_sums(launches, 1, 3)
+    assert g["label"] == "2–3" and g["SQ_INSTS_VALU"] == 50.0 and g["GRBM_GUI_ACTIVE"] == 16.0
+    cu_cycles = 256 * 16.0 / 8
+    assert g["valu_busy"] == pytest.approx(25.0 / cu_cycles)
+    assert g["ta_busy"] == pytest.approx(4.0 / cu_cycles) and g["td_busy"] == pytest.approx(6.0 / cu_cycles)
+    assert bench._group_sums(launches, 2, 3)["label"] == "3"
