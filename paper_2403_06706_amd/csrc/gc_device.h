@@ -368,6 +368,20 @@ __device__ __forceinline__ R sin_0_pi(R x) {
     const bool use_cos = y > quarter_pi;
     const R z = use_cos ? half_pi - y : y;           // sin(y) = cos(pi/2 - y)
     const R z2 = z * z;
+    // One series per lane, behind a branch: the particles of a wavefront are
+    // binned by cell, so nearly always all of its lanes take the same one.
+    if (use_cos) {
+        // cos z = 1 - z^2/2! + z^4/4! - ... + z^16/16!
+        R pc = (R)(1.0 / 20922789888000.0);
+        pc = fma(pc, -z2, (R)(1.0 / 87178291200.0));
+        pc = fma(pc, -z2, (R)(1.0 / 479001600.0));
+        pc = fma(pc, -z2, (R)(1.0 / 3628800.0));
+        pc = fma(pc, -z2, (R)(1.0 / 40320.0));
+        pc = fma(pc, -z2, (R)(1.0 / 720.0));
+        pc = fma(pc, -z2, (R)(1.0 / 24.0));
+        pc = fma(pc, -z2, (R)0.5);
+        return fma(pc, -z2, (R)1);
+    }
     // sin z = z (1 - z^2/3! + z^4/5! - ... + z^16/17!)
     R ps = (R)(1.0 / 355687428096000.0);
     ps = fma(ps, -z2, (R)(1.0 / 1307674368000.0));
@@ -378,17 +392,7 @@ __device__ __forceinline__ R sin_0_pi(R x) {
     ps = fma(ps, -z2, (R)(1.0 / 120.0));
     ps = fma(ps, -z2, (R)(1.0 / 6.0));
     ps = fma(ps, -z2, (R)1);
-    // cos z = 1 - z^2/2! + z^4/4! - ... + z^16/16!
-    R pc = (R)(1.0 / 20922789888000.0);
-    pc = fma(pc, -z2, (R)(1.0 / 87178291200.0));
-    pc = fma(pc, -z2, (R)(1.0 / 479001600.0));
-    pc = fma(pc, -z2, (R)(1.0 / 3628800.0));
-    pc = fma(pc, -z2, (R)(1.0 / 40320.0));
-    pc = fma(pc, -z2, (R)(1.0 / 720.0));
-    pc = fma(pc, -z2, (R)(1.0 / 24.0));
-    pc = fma(pc, -z2, (R)0.5);
-    pc = fma(pc, -z2, (R)1);
-    return use_cos ? pc : z * ps;
+    return z * ps;
 }
 
 // ---------------------------------------------------------------------------
