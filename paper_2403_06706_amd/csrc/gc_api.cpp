@@ -517,7 +517,7 @@ gc_status check_advance(gc_ctx *ctx, double dt, int64_t n_steps) {
 // [nr][nth][nph+1][12] of the store type; scale receives the FP16
 // per-component scales.  Waits.
 gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int nc, void **out, void **rec_out,
-                     float scale[12]) {
+                     float scale[12], int32_t *tame) {
     hipStream_t s = ctx->stream;
     const size_t nodes = (size_t)d->nr * d->nth * d->nph;
     const size_t packed = (size_t)field_layout(d->nr, d->nth, d->nph, d->store_dtype).total;
@@ -531,6 +531,12 @@ gc_status pack_nodes(gc_ctx *ctx, const gc_field_desc *d, const void *host, int 
                                                           : static_cast<const double *>(host)[i * nc + c];
         src = conv.data();
     }
+    *tame = 1;
+    for (size_t i = 0; i < nodes * 12; ++i)
+        if (!(std::fabs(src[i]) <= kTameField)) {   // NaN included
+            *tame = 0;
+            break;
+        }
     float inv_scale[12];
     for (int c = 0; c < 12; ++c) scale[c] = inv_scale[c] = 1.0f;
     if (d->store_dtype == GC_F16) {
@@ -723,12 +729,13 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     HIPCHK(hipSetDevice(ctx->opt.device));
     hipStream_t s = ctx->stream;
     float scale[12], xscale[12];
+    int32_t tame = 0, xtame = 0;
     void *buf = nullptr, *rbuf = nullptr, *xbuf = nullptr;
     // node records for the four-lanes-per-particle form (FP32 and FP64 stores)
-    gc_status st = pack_nodes(ctx, d, d->data, 12, &buf, d->store_dtype == GC_F16 ? nullptr : &rbuf, scale);
+    gc_status st = pack_nodes(ctx, d, d->data, 12, &buf, d->store_dtype == GC_F16 ? nullptr : &rbuf, scale, &tame);
     if (st != GC_OK) return st;
     if (d->extra) {
-        st = pack_nodes(ctx, d, d->extra, 9, &xbuf, nullptr, xscale);
+        st = pack_nodes(ctx, d, d->extra, 9, &xbuf, nullptr, xscale, &xtame);
         if (st != GC_OK) {
             dfree(ctx, buf);
             dfree(ctx, rbuf);
@@ -760,9 +767,11 @@ gc_status gc_load_field(gc_ctx *ctx, const gc_field_desc *d) {
     f.ks = lay.ks;
     f.js = lay.js;
     f.rec = rbuf;
+    f.tame = tame;
     ctx->fx = f;                      // same geometry, the extra node array (or none)
     ctx->fx.data = xbuf;
     ctx->fx.rec = nullptr;
+    ctx->fx.tame = xtame;
     if (xbuf)
         for (int c = 0; c < 12; ++c) ctx->fx.scale[c] = xscale[c];
     HIPCHK(hipMemcpyAsync(ctx->f_dev, &ctx->f, sizeof(FieldDev), hipMemcpyHostToDevice, s));

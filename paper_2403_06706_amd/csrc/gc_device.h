@@ -181,12 +181,26 @@ __device__ __forceinline__ bool finite12(const R out[12]) {
     return isfinite(sum);
 }
 
+// Whether a gather from f at finite interpolation weights gave a finite
+// result: always for a tame field (FieldDev::tame), else the sum of the
+// twelve components is tested.  The branch is uniform; the empty asm keeps
+// the compiler from summing on every lane and selecting.
+template <typename R>
+__device__ __forceinline__ bool gather_ok(const FieldDev &f, const R out[12]) {
+    if (f.tame) return true;
+    asm volatile("");
+    return finite12(out);
+}
+
 // One lane: the four node pairs added in order.
 // kAllPairs: issue the loads of all four node pairs at once (one memory round
 // trip per gather, more registers); otherwise at most two pairs are in
 // registers at a time, which keeps the push within two wavefronts per SIMD.
-// The arithmetic, and so the result, is the same either way.
-template <int FDT, typename R, bool kAllPairs = false>
+// The arithmetic, and so the result, is the same either way.  kTame: the
+// finiteness test of gather_ok (the push's one-lane forms and the gather probe
+// that bounds them; in the moments kernel the branch cost spilled registers,
+// in the quad form more time than the test).
+template <int FDT, typename R, bool kAllPairs = false, bool kTame = false>
 __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
     GatherPlan<R> gp;
     if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
@@ -199,7 +213,8 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
         gather_add<FDT, R>(f, gp, q, p, out);
         if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
     }
-    return finite12(out);
+    if constexpr (kTame) return gather_ok(f, out);
+    else return finite12(out);
 }
 
 // The field and the extra node array of the full Eqs. 1-2 (same geometry and

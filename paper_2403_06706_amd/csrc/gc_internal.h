@@ -81,7 +81,13 @@ struct FieldDev {
     // type, for the four-lanes-per-particle form of FP32 and FP64 fields (its
     // lanes take three components of a node each); NULL otherwise.
     const void *rec;
+    // Nonzero when every value of the grid is finite and at most kTameField
+    // in magnitude: then a trilinear combination of its nodes (weights in
+    // [0, 1]) and the sum of twelve such cannot overflow, in FP32 or FP64, and
+    // the push's one-lane gathers skip their test for a non-finite result.
+    int32_t tame;
 };
+constexpr double kTameField = 1e30;
 
 // Structure-of-arrays particle state (one slot per particle).
 struct SoA {

@@ -32,8 +32,8 @@ __global__ __launch_bounds__(256) void k_gather_probe(PushArgs a, double *sink) 
     double acc = 0.0;
     for (int it = 0; it < a.n_steps; ++it) {
         double g[12];
-        if (gather<FDT, double>(a.f, x, y, z, g)) acc += g[0] + g[5] + g[11];
-        if (gather<FDT, double>(a.f, x + 0.5 * h * vx, y + 0.5 * h * vy, z + 0.5 * h * vz, g))
+        if (gather<FDT, double, false, true>(a.f, x, y, z, g)) acc += g[0] + g[5] + g[11];
+        if (gather<FDT, double, false, true>(a.f, x + 0.5 * h * vx, y + 0.5 * h * vy, z + 0.5 * h * vz, g))
             acc += g[1] + g[6] + g[9];
         x += h * vx;
         y += h * vy;

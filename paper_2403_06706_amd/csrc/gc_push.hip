@@ -101,7 +101,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             xok = true;
             if constexpr (FULL) return gather2<FDT, R, FORM == kFormAllPairs>(a.f, a.fx, x, t, p, g, xg, xok);
             else if constexpr (FORM == kFormQuad) return gather_quad<FDT, R>(a.f, x, t, p, gl, g);
-            else return gather<FDT, R, FORM == kFormAllPairs>(a.f, x, t, p, g);
+            else return gather<FDT, R, FORM == kFormAllPairs, true>(a.f, x, t, p, g);
         };
         auto rhs_at = [&](R x, R t, R u, R g[12], R xg[12], R F[4], R &vp) {
             if constexpr (FULL) gc_rhs<R, true>(x, t, u, mu, qm, iqm, drift_free, g, F, vp, xg);
