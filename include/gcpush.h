@@ -138,6 +138,10 @@ gc_status gc_get_options(const gc_ctx *ctx, gc_options *opt);
  * may be freed when the call returns.  The call waits for the upload.  For
  * GC_F32 and GC_F64 stores it keeps a second copy as node records for its
  * four-lanes-per-particle form (device memory about twice the packed field).
+ * Non-finite values are allowed: an electron whose field evaluation meets one
+ * ends GC_NONFINITE.  (The call scans the data once on the host; a grid whose
+ * values are all finite and at most 1e30 in magnitude lets the push skip that
+ * test, with the same results.)
  * extra: NULL (the reduced Eqs. 1-2, dropping the terms with derivatives of b
  *   and v_E), or a HOST pointer to [nr][nth][nph][9] values of src_dtype:
  *   (v_E.grad)b | (b.grad)v_E | (v_E.grad)v_E, local basis, v_E = E x B / B^2;
