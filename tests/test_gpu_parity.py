@@ -83,6 +83,26 @@ def test_nonfinite_field_marks_particles():
     assert np.array_equal(st["step"], p["step"]) and np.array_equal(st["k"], p["k"])
 
 
+@pytest.mark.parametrize("store", ["f64", "f32"])
+@pytest.mark.parametrize("tail", [0, 1000])
+def test_untame_field_gives_the_same_bits(store, tail):
+    """One node value above 1e30, far from every electron, makes the field
+    not tame: the push then tests each gather's result for non-finite values
+    (a tame field lets the throughput and all-pairs forms skip the test).
+    Both give the same bits.  tail 0: the throughput form throughout; 1000:
+    the all-pairs form, then the quad form below 250 electrons."""
+    from gpu_helpers import same_state
+    wl = small(n=500, hours=0.5)
+    f = field_of(wl)
+    g = f.copy()
+    g[-1, 0, 0, 11] = 2e30        # outermost shell, first theta row: never gathered
+    say(f"tame/untame field, store={store}, tail={tail}")
+    a, _ = run_gpu(wl, f, store_dtype=store, tail_threshold=tail)
+    b, _ = run_gpu(wl, g, store_dtype=store, tail_threshold=tail)
+    same_state(a, b)
+    assert np.sum(a["status"] == O.EXITED) > 10
+
+
 def test_drift_free_and_flux_weighted_law():
     wl = small(n=500, hours=0.5, drift_free=True, scatter_law=1, lambda_par=0.05 * AU)
     f = field_of(wl)
