@@ -287,7 +287,7 @@ __device__ __forceinline__ R quad_bcast_value(R x) {
 // exchanges the finished components, so all four lanes hold the bits of
 // gather().  Each lane converts and multiplies a quarter of the values.  All
 // four lanes must call it together.
-template <int FDT, typename R>
+template <int FDT, typename R, bool kTame = false>
 __device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
     using T = typename std::conditional<FDT == GC_F64, double, float>::type;
     GatherPlan<R> gp;
@@ -322,7 +322,8 @@ __device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, 
         out[6 + c] = quad_bcast_value<2>(acc[c]);
         out[9 + c] = quad_bcast_value<3>(acc[c]);
     }
-    return finite12(out);
+    if constexpr (kTame) return true;   // the caller knows the field is tame (FieldDev::tame)
+    else return finite12(out);
 }
 
 // Four lanes of an aligned quad, one particle: for FP32 and FP64 fields the
@@ -330,9 +331,9 @@ __device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, 
 // shares the loaded words, and every lane adds the four pairs in the one-lane
 // order.  Either way all four lanes hold the bits of gather().  All four lanes
 // must call it together.
-template <int FDT, typename R>
+template <int FDT, typename R, bool kTame = false>
 __device__ __forceinline__ bool gather_quad(const FieldDev &f, R r, R th, R ph, uint32_t gl, R out[12]) {
-    if constexpr (FDT != GC_F16) return gather_quad_split<FDT, R>(f, r, th, ph, gl, out);
+    if constexpr (FDT != GC_F16) return gather_quad_split<FDT, R, kTame>(f, r, th, ph, gl, out);
     GatherPlan<R> gp;
     if (!gather_plan<FDT>(f, r, th, ph, gp)) return false;
     Pair<FDT> mine;
@@ -343,7 +344,8 @@ __device__ __forceinline__ bool gather_quad(const FieldDev &f, R r, R th, R ph, 
     gather_add<FDT, R>(f, gp, 1, quad_bcast_pair<FDT, 1>(mine), out);
     gather_add<FDT, R>(f, gp, 2, quad_bcast_pair<FDT, 2>(mine), out);
     gather_add<FDT, R>(f, gp, 3, quad_bcast_pair<FDT, 3>(mine), out);
-    return finite12(out);
+    if constexpr (kTame) return true;
+    else return finite12(out);
 }
 
 // ---------------------------------------------------------------------------

@@ -27,7 +27,10 @@ enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 // instantiation because the out-of-line rebirth raises the register count of
 // the FP32 forms.  MODE 2: also the full Eqs. 1-2 (the extra node array is
 // gathered with the field's stencil at each evaluation; no quad form).
-template <int PREC, int FDT, int MODE, int FORM = kFormThroughput>
+// TAME: the field is tame (FieldDev::tame), so the quad form's gathers skip
+// their finiteness test (compiled out: there a branch cost more than the
+// test; the one-lane forms test the flag at run time).
+template <int PREC, int FDT, int MODE, int FORM = kFormThroughput, bool TAME = false>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
     constexpr bool EXT = MODE >= 1;
     constexpr bool FULL = MODE == 2;
@@ -100,7 +103,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
         auto gather_at = [&](R x, R t, R p, R g[12], R xg[12], bool &xok) -> bool {
             xok = true;
             if constexpr (FULL) return gather2<FDT, R, FORM == kFormAllPairs>(a.f, a.fx, x, t, p, g, xg, xok);
-            else if constexpr (FORM == kFormQuad) return gather_quad<FDT, R>(a.f, x, t, p, gl, g);
+            else if constexpr (FORM == kFormQuad) return gather_quad<FDT, R, TAME>(a.f, x, t, p, gl, g);
             else return gather<FDT, R, FORM == kFormAllPairs, true>(a.f, x, t, p, g);
         };
         auto rhs_at = [&](R x, R t, R u, R g[12], R xg[12], R F[4], R &vp) {
@@ -303,7 +306,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
 // gives each XCD a contiguous range of that prefix, so that (with cell-sorted
 // slots) its L2 holds the field cells of its own particles, and every XCD gets
 // an equal share however small the active prefix is.
-template <int PREC, int FDT, int MODE, int FORM>
+template <int PREC, int FDT, int MODE, int FORM, bool TAME = false>
 __device__ __forceinline__ void push_grid(const PushArgs &a) {
     constexpr uint32_t G = FORM == kFormQuad ? 4 : 1;          // lanes per particle
     const uint32_t n = *a.n_active;
@@ -314,7 +317,7 @@ __device__ __forceinline__ void push_grid(const PushArgs &a) {
     const uint32_t lb = (xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q) + pos;
     const uint32_t slot = lb * per_block + threadIdx.x / G;
     uint32_t taken = 0;
-    if (slot < n) taken = advance_slot<PREC, FDT, MODE, FORM>(a, slot, threadIdx.x % G);
+    if (slot < n) taken = advance_slot<PREC, FDT, MODE, FORM, TAME>(a, slot, threadIdx.x % G);
     count_steps(a, taken);
 }
 
@@ -334,9 +337,9 @@ __global__ __launch_bounds__(256) void k_push_allpairs(PushArgs a) {
     push_grid<PREC, FDT, MODE, kFormAllPairs>(a);
 }
 
-template <int PREC, int FDT, int MODE>
+template <int PREC, int FDT, int MODE, bool TAME>
 __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
-    push_grid<PREC, FDT, MODE, kFormQuad>(a);
+    push_grid<PREC, FDT, MODE, kFormQuad, TAME>(a);
 }
 
 // Persistent forms: a fixed grid pulls tiles of consecutive slots from an
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(256) void k_push_quad(PushArgs a) {
 // are the forms of the eager tail policy, chosen on the device so that a
 // captured graph follows the count without a host read-back.  Steps are
 // counted per form (a.steps_done + form).
-template <int PREC, int FDT, int MODE, int FORM>
+template <int PREC, int FDT, int MODE, int FORM, bool TAME = false>
 __device__ __forceinline__ void push_persistent(const PushArgs &a) {
     __shared__ uint32_t s_tile;
     const uint32_t n = *a.n_active;
@@ -377,7 +380,7 @@ __device__ __forceinline__ void push_persistent(const PushArgs &a) {
         if (t >= ntiles) break;
         const uint32_t end = min(n, (t + 1) * tile);
         for (uint32_t slot = t * tile + threadIdx.x / G; slot < end; slot += per)
-            taken += advance_slot<PREC, FDT, MODE, FORM>(a, slot, threadIdx.x % G);
+            taken += advance_slot<PREC, FDT, MODE, FORM, TAME>(a, slot, threadIdx.x % G);
     }
     count_steps(a.steps_done + FORM, taken);
 }
@@ -392,9 +395,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     push_persistent<PREC, FDT, MODE, kFormAllPairs>(a);
 }
 
-template <int PREC, int FDT, int MODE>
+template <int PREC, int FDT, int MODE, bool TAME>
 __global__ __launch_bounds__(256) void k_push_persistent_quad(PushArgs a) {
-    push_persistent<PREC, FDT, MODE, kFormQuad>(a);
+    push_persistent<PREC, FDT, MODE, kFormQuad, TAME>(a);
 }
 
 
@@ -408,9 +411,15 @@ static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int fo
         if (a.tail > 0) {
             launch_timed((k_push_persistent_allpairs<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), s, nullptr,
                          quad ? nullptr : ev.stop, a);
-            if (quad)   // 256-thread workgroups (64 particles per round), as the grid quad form
-                launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE>),
-                             dim3((uint32_t)grid_blocks * block / 256), dim3(256), s, nullptr, ev.stop, a);
+            if (quad) {  // 256-thread workgroups (64 particles per round), as the grid quad form
+                const dim3 qg((uint32_t)grid_blocks * block / 256);
+                if (a.f.tame)
+                    launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE, true>), qg, dim3(256), s,
+                                 nullptr, ev.stop, a);
+                else
+                    launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE, false>), qg, dim3(256), s,
+                                 nullptr, ev.stop, a);
+            }
         }
     } else {
         const uint32_t nb = (a.n_slots + block - 1) / block;
@@ -423,7 +432,12 @@ static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int fo
             // 256-thread workgroups whatever the block size (64 particles each;
             // measured faster for this form than 64 threads)
             const uint32_t qb = (4 * a.n_slots + 255) / 256;
-            launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE>), dim3(qb), dim3(256), s, ev.start, ev.stop, a);
+            if (a.f.tame)
+                launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE, true>), dim3(qb), dim3(256), s, ev.start,
+                             ev.stop, a);
+            else
+                launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE, false>), dim3(qb), dim3(256), s, ev.start,
+                             ev.stop, a);
         } else if (form != kFormThroughput)
             launch_timed((k_push_allpairs<PREC, FDT, MODE>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
         else
