@@ -537,7 +537,7 @@ PMC_PASSES = {
     "t2": "WRITE_SIZE",
     "t3": "TCC_HIT_sum TCC_MISS_sum",
 }
-PUSH_KERNEL = "k_push<0, 1, 0>"
+PUSH_KERNEL = "k_push<0, 1, 0, true>"   # the tame-field instantiation (FP32 field of finite values)
 COPY_KERNEL = "k_copy_probe"
 N_CU = 256
 N_XCD = 8          # GRBM_GUI_ACTIVE is summed over the XCDs

@@ -181,25 +181,12 @@ __device__ __forceinline__ bool finite12(const R out[12]) {
     return isfinite(sum);
 }
 
-// Whether a gather from f at finite interpolation weights gave a finite
-// result: always for a tame field (FieldDev::tame), else the sum of the
-// twelve components is tested.  The branch is uniform; the empty asm keeps
-// the compiler from summing on every lane and selecting.
-template <typename R>
-__device__ __forceinline__ bool gather_ok(const FieldDev &f, const R out[12]) {
-    if (f.tame) return true;
-    asm volatile("");
-    return finite12(out);
-}
-
 // One lane: the four node pairs added in order.
 // kAllPairs: issue the loads of all four node pairs at once (one memory round
 // trip per gather, more registers); otherwise at most two pairs are in
 // registers at a time, which keeps the push within two wavefronts per SIMD.
 // The arithmetic, and so the result, is the same either way.  kTame: the
-// finiteness test of gather_ok (the push's one-lane forms and the gather probe
-// that bounds them; in the moments kernel the branch cost spilled registers,
-// in the quad form more time than the test).
+// caller knows the field is tame (FieldDev::tame): no finiteness test.
 template <int FDT, typename R, bool kAllPairs = false, bool kTame = false>
 __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out[12]) {
     GatherPlan<R> gp;
@@ -213,7 +200,7 @@ __device__ __forceinline__ bool gather(const FieldDev &f, R r, R th, R ph, R out
         gather_add<FDT, R>(f, gp, q, p, out);
         if (!kAllPairs && (q & 1)) __builtin_amdgcn_sched_barrier(0);   // at most two node pairs in registers
     }
-    if constexpr (kTame) return gather_ok(f, out);
+    if constexpr (kTame) return true;
     else return finite12(out);
 }
 
@@ -322,7 +309,7 @@ __device__ __forceinline__ bool gather_quad_split(const FieldDev &f, R r, R th, 
         out[6 + c] = quad_bcast_value<2>(acc[c]);
         out[9 + c] = quad_bcast_value<3>(acc[c]);
     }
-    if constexpr (kTame) return true;   // the caller knows the field is tame (FieldDev::tame)
+    if constexpr (kTame) return true;
     else return finite12(out);
 }
 

@@ -84,7 +84,8 @@ struct FieldDev {
     // Nonzero when every value of the grid is finite and at most kTameField
     // in magnitude: then a trilinear combination of its nodes (weights in
     // [0, 1]) and the sum of twelve such cannot overflow, in FP32 or FP64, and
-    // the push's one-lane gathers skip their test for a non-finite result.
+    // the push kernels (an instantiation of their own) and the gather probe
+    // skip the test of a gather's result for non-finite values.
     int32_t tame;
 };
 constexpr double kTameField = 1e30;

@@ -14,7 +14,7 @@
 
 namespace gc {
 
-template <int FDT>
+template <int FDT, bool TAME>
 __global__ __launch_bounds__(256) void k_gather_probe(PushArgs a, double *sink) {
     const uint32_t n = *a.n_active;
     const uint32_t nb = (n + blockDim.x - 1) / blockDim.x, b = blockIdx.x;
@@ -32,8 +32,8 @@ __global__ __launch_bounds__(256) void k_gather_probe(PushArgs a, double *sink) 
     double acc = 0.0;
     for (int it = 0; it < a.n_steps; ++it) {
         double g[12];
-        if (gather<FDT, double, false, true>(a.f, x, y, z, g)) acc += g[0] + g[5] + g[11];
-        if (gather<FDT, double, false, true>(a.f, x + 0.5 * h * vx, y + 0.5 * h * vy, z + 0.5 * h * vz, g))
+        if (gather<FDT, double, false, TAME>(a.f, x, y, z, g)) acc += g[0] + g[5] + g[11];
+        if (gather<FDT, double, false, TAME>(a.f, x + 0.5 * h * vx, y + 0.5 * h * vy, z + 0.5 * h * vz, g))
             acc += g[1] + g[6] + g[9];
         x += h * vx;
         y += h * vy;
@@ -45,10 +45,21 @@ __global__ __launch_bounds__(256) void k_gather_probe(PushArgs a, double *sink) 
 hipError_t launch_gather_probe(const PushArgs &a, double *sink, int block, hipStream_t s) {
     const uint32_t nb = (a.n_slots + block - 1) / block;      // the push's workgroup size
     if (nb == 0) return hipSuccess;
+    // the push's gathers: without the finiteness test on a tame field
+    const bool t = a.f.tame != 0;
     switch (a.f.dtype) {
-        case GC_F64: hipLaunchKernelGGL(k_gather_probe<GC_F64>, dim3(nb), dim3(block), 0, s, a, sink); break;
-        case GC_F32: hipLaunchKernelGGL(k_gather_probe<GC_F32>, dim3(nb), dim3(block), 0, s, a, sink); break;
-        default:     hipLaunchKernelGGL(k_gather_probe<GC_F16>, dim3(nb), dim3(block), 0, s, a, sink); break;
+        case GC_F64:
+            if (t) hipLaunchKernelGGL((k_gather_probe<GC_F64, true>), dim3(nb), dim3(block), 0, s, a, sink);
+            else hipLaunchKernelGGL((k_gather_probe<GC_F64, false>), dim3(nb), dim3(block), 0, s, a, sink);
+            break;
+        case GC_F32:
+            if (t) hipLaunchKernelGGL((k_gather_probe<GC_F32, true>), dim3(nb), dim3(block), 0, s, a, sink);
+            else hipLaunchKernelGGL((k_gather_probe<GC_F32, false>), dim3(nb), dim3(block), 0, s, a, sink);
+            break;
+        default:
+            if (t) hipLaunchKernelGGL((k_gather_probe<GC_F16, true>), dim3(nb), dim3(block), 0, s, a, sink);
+            else hipLaunchKernelGGL((k_gather_probe<GC_F16, false>), dim3(nb), dim3(block), 0, s, a, sink);
+            break;
     }
     return hipGetLastError();
 }

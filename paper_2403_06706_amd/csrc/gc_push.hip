@@ -27,9 +27,9 @@ enum { kFormThroughput = 0, kFormAllPairs = 1, kFormQuad = 2 };
 // instantiation because the out-of-line rebirth raises the register count of
 // the FP32 forms.  MODE 2: also the full Eqs. 1-2 (the extra node array is
 // gathered with the field's stencil at each evaluation; no quad form).
-// TAME: the field is tame (FieldDev::tame), so the quad form's gathers skip
-// their finiteness test (compiled out: there a branch cost more than the
-// test; the one-lane forms test the flag at run time).
+// TAME: the field is tame (FieldDev::tame), so the gathers skip their
+// finiteness test (compiled out; a run-time branch around it measured slower,
+// and in the quad form no faster than the test).
 template <int PREC, int FDT, int MODE, int FORM = kFormThroughput, bool TAME = false>
 __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slot, uint32_t gl = 0) {
     constexpr bool EXT = MODE >= 1;
@@ -104,7 +104,7 @@ __device__ __forceinline__ uint32_t advance_slot(const PushArgs &a, uint32_t slo
             xok = true;
             if constexpr (FULL) return gather2<FDT, R, FORM == kFormAllPairs>(a.f, a.fx, x, t, p, g, xg, xok);
             else if constexpr (FORM == kFormQuad) return gather_quad<FDT, R, TAME>(a.f, x, t, p, gl, g);
-            else return gather<FDT, R, FORM == kFormAllPairs, true>(a.f, x, t, p, g);
+            else return gather<FDT, R, FORM == kFormAllPairs, TAME>(a.f, x, t, p, g);
         };
         auto rhs_at = [&](R x, R t, R u, R g[12], R xg[12], R F[4], R &vp) {
             if constexpr (FULL) gc_rhs<R, true>(x, t, u, mu, qm, iqm, drift_free, g, F, vp, xg);
@@ -322,9 +322,9 @@ __device__ __forceinline__ void push_grid(const PushArgs &a) {
 }
 
 // Throughput form: at most 256 registers per lane (two wavefronts per SIMD).
-template <int PREC, int FDT, int MODE>
+template <int PREC, int FDT, int MODE, bool TAME>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push(PushArgs a) {
-    push_grid<PREC, FDT, MODE, kFormThroughput>(a);
+    push_grid<PREC, FDT, MODE, kFormThroughput, TAME>(a);
 }
 
 // Latency forms, for fewer active particles than fill the machine: a
@@ -332,9 +332,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // and by how many distinct cache lines its load instructions touch.  The
 // all-pairs form has each gather in one round trip; the quad form also spreads
 // the particles over four times as many wavefronts (and compute units).
-template <int PREC, int FDT, int MODE>
+template <int PREC, int FDT, int MODE, bool TAME>
 __global__ __launch_bounds__(256) void k_push_allpairs(PushArgs a) {
-    push_grid<PREC, FDT, MODE, kFormAllPairs>(a);
+    push_grid<PREC, FDT, MODE, kFormAllPairs, TAME>(a);
 }
 
 template <int PREC, int FDT, int MODE, bool TAME>
@@ -385,14 +385,14 @@ __device__ __forceinline__ void push_persistent(const PushArgs &a) {
     count_steps(a.steps_done + FORM, taken);
 }
 
-template <int PREC, int FDT, int MODE>
+template <int PREC, int FDT, int MODE, bool TAME>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent(PushArgs a) {
-    push_persistent<PREC, FDT, MODE, kFormThroughput>(a);
+    push_persistent<PREC, FDT, MODE, kFormThroughput, TAME>(a);
 }
 
-template <int PREC, int FDT, int MODE>
+template <int PREC, int FDT, int MODE, bool TAME>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_push_persistent_allpairs(PushArgs a) {
-    push_persistent<PREC, FDT, MODE, kFormAllPairs>(a);
+    push_persistent<PREC, FDT, MODE, kFormAllPairs, TAME>(a);
 }
 
 template <int PREC, int FDT, int MODE, bool TAME>
@@ -401,24 +401,19 @@ __global__ __launch_bounds__(256) void k_push_persistent_quad(PushArgs a) {
 }
 
 
-template <int PREC, int FDT, int MODE>
-static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s,
+template <int PREC, int FDT, int MODE, bool TAME>
+static hipError_t launch_rt(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s,
                            LaunchEvents ev) {
     if (persistent) {
         const bool quad = a.tail > 0 && MODE != 2;
-        launch_timed((k_push_persistent<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), s, ev.start,
+        launch_timed((k_push_persistent<PREC, FDT, MODE, TAME>), dim3(grid_blocks), dim3(block), s, ev.start,
                      a.tail > 0 ? nullptr : ev.stop, a);
         if (a.tail > 0) {
-            launch_timed((k_push_persistent_allpairs<PREC, FDT, MODE>), dim3(grid_blocks), dim3(block), s, nullptr,
+            launch_timed((k_push_persistent_allpairs<PREC, FDT, MODE, TAME>), dim3(grid_blocks), dim3(block), s, nullptr,
                          quad ? nullptr : ev.stop, a);
             if (quad) {  // 256-thread workgroups (64 particles per round), as the grid quad form
-                const dim3 qg((uint32_t)grid_blocks * block / 256);
-                if (a.f.tame)
-                    launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE, true>), qg, dim3(256), s,
-                                 nullptr, ev.stop, a);
-                else
-                    launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE, false>), qg, dim3(256), s,
-                                 nullptr, ev.stop, a);
+                launch_timed((k_push_persistent_quad<PREC, FDT, MODE == 2 ? 1 : MODE, TAME>),
+                             dim3((uint32_t)grid_blocks * block / 256), dim3(256), s, nullptr, ev.stop, a);
             }
         }
     } else {
@@ -432,18 +427,24 @@ static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int fo
             // 256-thread workgroups whatever the block size (64 particles each;
             // measured faster for this form than 64 threads)
             const uint32_t qb = (4 * a.n_slots + 255) / 256;
-            if (a.f.tame)
-                launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE, true>), dim3(qb), dim3(256), s, ev.start,
-                             ev.stop, a);
-            else
-                launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE, false>), dim3(qb), dim3(256), s, ev.start,
-                             ev.stop, a);
+            launch_timed((k_push_quad<PREC, FDT, MODE == 2 ? 1 : MODE, TAME>), dim3(qb), dim3(256), s, ev.start,
+                         ev.stop, a);
         } else if (form != kFormThroughput)
-            launch_timed((k_push_allpairs<PREC, FDT, MODE>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
+            launch_timed((k_push_allpairs<PREC, FDT, MODE, TAME>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
         else
-            launch_timed((k_push<PREC, FDT, MODE>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
+            launch_timed((k_push<PREC, FDT, MODE, TAME>), dim3(nb), dim3(block), s, ev.start, ev.stop, a);
     }
     return hipGetLastError();
+}
+
+// The tame instantiations (FieldDev::tame) for the reduced equations; the
+// full equations test every gather (their extra node array is not scanned).
+template <int PREC, int FDT, int MODE>
+static hipError_t launch_r(const PushArgs &a, int block, bool persistent, int form, int grid_blocks, hipStream_t s,
+                           LaunchEvents ev) {
+    if constexpr (MODE != 2)
+        if (a.f.tame) return launch_rt<PREC, FDT, MODE, true>(a, block, persistent, form, grid_blocks, s, ev);
+    return launch_rt<PREC, FDT, MODE, false>(a, block, persistent, form, grid_blocks, s, ev);
 }
 
 template <int PREC, int FDT>

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
-PUSH = "void gc::k_push<0, 1, 0>(gc::PushArgs)"
+PUSH = "void gc::k_push<0, 1, 0, true>(gc::PushArgs)"
 COPY = "gc::k_copy_probe(uint4*, uint4 const*, unsigned long)"
 FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size",
           "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
